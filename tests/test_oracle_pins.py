@@ -1,0 +1,182 @@
+"""Pins of the CPU oracle against facts outside the oracle itself.
+
+- FNV-1a 64: the published test vectors (tests/golden/fnv1a64_vectors.txt).
+- pread plumbing: every (offset, length) pair on tiny files, including EOF
+  and zero-length reads, against slicing the file's bytes; bad fds -> -EBADF.
+- word counts: a hand-counted fixture (tests/golden/wordcount_small.json),
+  Python's bytes.split() counter on generated corpora, planted tokens.
+- key-value GET: a Python dict built from the same keys.
+- memory release: Linux madvise(2) semantics (zero pages after DONTNEED on
+  private anonymous memory).
+"""
+import collections
+import errno
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _vectors():
+    out = []
+    with open(os.path.join(GOLDEN, "fnv1a64_vectors.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            m = re.match(r'^"(.*)"\s+([0-9a-f]{16})$', line)
+            assert m, line
+            out.append((m.group(1).encode(), int(m.group(2), 16)))
+    return out
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def test_fnv_published_vectors():
+    vec = _vectors()
+    assert len(vec) >= 10
+    for data, want in vec:
+        assert oracle.fnv1a64(data) == want, data
+
+
+def test_fnv_is_order_sensitive_and_distinguishes_fnv1():
+    # FNV-1 (multiply before xor) of "a" is 0xaf63bd4c8601b7be; FNV-1a differs.
+    assert oracle.fnv1a64(b"a") != 0xaf63bd4c8601b7be
+    assert oracle.fnv1a64(b"ab") != oracle.fnv1a64(b"ba")
+
+
+def _write(tmpdata, name, data: bytes) -> str:
+    p = os.path.join(tmpdata, name)
+    with open(p, "wb") as f:
+        f.write(data)
+    return p
+
+
+@pytest.mark.parametrize("size", [0, 1, 100, 4095, 4096, 5000])
+def test_pread_bruteforce_tiny_files(tmpdata, size):
+    data = np.random.default_rng(size + 7).integers(0, 256, size, dtype=np.uint8).tobytes()
+    p = _write(tmpdata, "tiny_%d.bin" % size, data)
+    offs = np.arange(0, size + 6, dtype=np.uint64)
+    for ln in (0, 1, 7, 64, 4096):
+        fnv, ret = oracle.pread_fnv(p, offs, ln, threads=3)
+        for i, o in enumerate(offs.tolist()):
+            want = data[o:o + ln]
+            assert ret[i] == len(want), (o, ln)
+            assert fnv[i] == oracle.fnv1a64(want), (o, ln)
+
+
+def test_pread_tiny_config_matches_file_slices(tmpdata):
+    os.environ.setdefault("GSYS_DATA_DIR", tmpdata)
+    p = synth.random_file(1, 262144, name="pin_c1.bin")
+    data = synth.file_bytes(p)
+    offs = synth.tiny_offsets(64)
+    fnv, ret = oracle.pread_fnv(p, offs, 4096)
+    assert (ret == 4096).all()
+    for i in range(64):
+        assert fnv[i] == oracle.fnv1a64(data[4096 * i:4096 * (i + 1)])
+    # distinct blocks of random data: all checksums distinct
+    assert len(set(fnv.tolist())) == 64
+
+
+def test_pread_bad_fd_gives_ebadf():
+    lib = oracle.lib()
+    offs = np.zeros(2, dtype=np.uint64)
+    out = np.zeros(2, dtype=np.uint64)
+    ret = np.zeros(2, dtype=np.int64)
+    rc = lib.oracle_pread_fnv(987654, offs.ctypes.data, 2, 16, out.ctypes.data,
+                              ret.ctypes.data, 1)
+    assert rc == 0
+    assert (ret == -errno.EBADF).all()
+    assert (out == 0xcbf29ce484222325).all()
+
+
+def test_wordcount_hand_fixture(tmpdata):
+    doc = json.load(open(os.path.join(GOLDEN, "wordcount_small.json")))
+    p = _write(tmpdata, "wc_hand.txt", doc["text"].encode())
+    qs = [k.encode() for k in doc["expected"]]
+    counts = oracle.wordcount([p], qs)
+    assert counts[0].tolist() == list(doc["expected"].values())
+
+
+def test_wordcount_vs_bytes_split(tmpdata):
+    os.environ["GSYS_DATA_DIR"] = tmpdata
+    c = synth.wordcount_corpus(n_files=12, median_bytes=8192, n_vocab=300, tag="pin12")
+    counts = oracle.wordcount(c.paths, c.queries, threads=4)
+    for f, p in enumerate(c.paths):
+        data = open(p, "rb").read()
+        assert set(data) <= set(b"abcdefghijklmnopqrstuvwxyz \n")
+        cnt = collections.Counter(data.split())
+        assert counts[f].tolist() == [cnt.get(q, 0) for q in c.queries]
+    # 8 of the 64 queries are not vocabulary words; upper-case ones never match
+    assert counts[:, 60:].sum() == 0
+
+
+def test_wordcount_planted_tokens(tmpdata):
+    # a token is counted once wherever it sits: file start, end, next to
+    # newlines or runs of delimiters, or straddling a 4 KiB boundary
+    q = b"needle"
+    body = bytearray(b"x " * 5000)
+    for pos in (0, 4093, 8190, len(body) - 6):
+        body[pos:pos + 6] = q
+    data = bytes(body[:len(body) - 6]) + b"\n" + q  # last token ends at EOF
+    p = _write(tmpdata, "planted.txt", data)
+    want = collections.Counter(data.split())[q]
+    counts = oracle.wordcount([p], [q, b"needl", b"eedle", b"x"])
+    assert counts[0, 0] == want
+    assert counts[0, 1] == 0 and counts[0, 2] == 0
+    assert counts[0, 3] == collections.Counter(data.split())[b"x"]
+
+
+def test_wordcount_empty_and_delimiter_only_files(tmpdata):
+    p0 = _write(tmpdata, "empty.txt", b"")
+    p1 = _write(tmpdata, "delims.txt", b" \n \n\n  ")
+    counts = oracle.wordcount([p0, p1], [b"a", b" "])
+    assert counts.sum() == 0
+
+
+def test_kv_lookup_vs_dict():
+    kv = synth.kv_set(n_keys=2000, n_req=3000, miss_every=16)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    d = {kv.keys[i].tobytes(): i for i in range(len(kv.keys))}
+    for j in range(len(kv.req_keys)):
+        k = kv.req_keys[j].tobytes()
+        want = d.get(k, -1)
+        assert ix.find(k) == want
+        assert want == kv.req_index[j]
+        req = int(kv.req_ids[j]).to_bytes(8, "little") + bytes([1]) + bytes(7) + k
+        rep = ix.reply(req)
+        assert rep[:8] == req[:8]
+        if want < 0:
+            assert rep[8] == 1 and len(rep) == 16
+        else:
+            ln = int(kv.val_len[want])
+            off = int(kv.val_off[want])
+            assert rep[8] == 0
+            assert int.from_bytes(rep[10:12], "little") == ln
+            assert rep[16:] == kv.heap[off:off + ln].tobytes()
+    # a malformed request (wrong op) is answered with status 2
+    bad = (5).to_bytes(8, "little") + bytes([7]) + bytes(23)
+    assert ix.reply(bad)[8] == 2
+    ix.close()
+
+
+def test_release_zero_pages_after_dontneed():
+    stamp = bytes(range(64))
+    rc, before, after = oracle.release(2 << 20, stamp)
+    assert rc == 0
+    pages = (2 << 20) // 4096
+    for p in range(pages):
+        want = bytearray(stamp)
+        want[0] ^= p & 0xFF
+        assert before[p].tobytes() == bytes(want)
+    assert not after.any()
