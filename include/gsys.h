@@ -1,0 +1,228 @@
+/*
+ * gsys: GPU-issued system calls on one MI355X (gfx950), serviced in user
+ * space by a host service pool.  C ABI of libgsys.so.
+ *
+ * Conventions for every entry point below:
+ *   - Return 0 (or a non-negative count) on success and -errno on failure.
+ *     Nothing aborts the process; gsys_strerror() names the code.
+ *   - "device address" means an address a GPU kernel can dereference.  Host
+ *     buffers from gsys_host_alloc() have one (returned in *dev_out); device
+ *     buffers are plain hipMalloc memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - A gsys_ctx is not thread-safe for init/shutdown; the launch entry points
+ *     may be called from one host thread at a time per context.  Any number of
+ *     GPU lanes may issue calls concurrently.
+ *
+ * Whitelist.  The service pool executes only pread64, pwrite64, read, write,
+ * sendto and recvfrom (IPv4 loopback peers only), mmap (anonymous, inside the
+ * context's arena), munmap and madvise (MADV_DONTNEED, inside the arena), on
+ * file descriptors the caller allowed with gsys_allow_fd and buffers it
+ * registered.  Anything else completes with -EPERM (call not allowed),
+ * -EBADF (fd not allowed), -EFAULT (address range not registered) or
+ * -EINVAL (flags).
+ */
+#ifndef GSYS_H
+#define GSYS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gsys_abi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsys_ctx gsys_ctx;
+
+/* gsys_config.flags */
+#define GSYS_CFG_LEDGER    0x1u  /* record every serviced ticket (exactly-once checks) */
+#define GSYS_CFG_NO_DEVICE 0x2u  /* host memory only, no HIP calls (CPU tests)        */
+#define GSYS_CFG_NO_PIN    0x4u  /* do not pin service threads to cores              */
+
+typedef struct gsys_config {
+    uint32_t abi_version;        /* must be GSYS_ABI_VERSION                          */
+    int32_t  device;             /* HIP device ordinal                                */
+    uint32_t ring_slots;         /* D, power of two >= 64 (0 = 65536)                 */
+    uint32_t service_threads;    /* P host pollers (0 = online cores - 1, at least 1) */
+    uint32_t coalesce_max;       /* K: max calls per coalesced bundle (0/1 = off)     */
+    uint32_t coalesce_window_ns; /* T: how long a poller waits to fill a bundle       */
+    uint32_t stripe;             /* tickets per poller stripe (0 = 8)                 */
+    uint32_t flags;              /* GSYS_CFG_*                                        */
+    uint64_t arena_bytes;        /* reserved address range for GPU mmap (0 = none)    */
+    uint64_t device_timeout_ns;  /* GPU watchdog on every wait (0 = 30 s)             */
+    int32_t  first_cpu;          /* pin pollers to cores first_cpu.. (-1 = 1..P)      */
+    uint32_t ledger_capacity;    /* ledger records kept (0 = 1<<20)                   */
+    uint32_t reserved[4];
+} gsys_config;
+
+/*
+ * Create a context: allocate the slot ring (D x 64 B) and the completion
+ * records (4D x 16 B) in fine-grained, host-coherent memory, the device-side
+ * ticket counter, and start P service threads that poll the ring.
+ * The ring replaces the paper's syscall area (section 5); the polling pool
+ * replaces its interrupt + work-queue dispatch (section 3 notes that the
+ * design is orthogonal to interrupts versus polling).
+ * cfg == NULL uses all defaults.  *out receives the context.
+ * Errors: -EINVAL (bad D / version), -ENOMEM, -ENODEV (HIP failure).
+ */
+int gsys_init(const gsys_config *cfg, gsys_ctx **out);
+
+/* fd permissions for gsys_allow_fd */
+#define GSYS_FD_READ  0x1u
+#define GSYS_FD_WRITE 0x2u
+#define GSYS_FD_SOCK  0x4u
+
+/*
+ * Allow GPU calls on `fd` with `perms` (GSYS_FD_*).  The caller keeps
+ * ownership of the fd and must keep it open until gsys_wait() returns.
+ * perms == 0 revokes the fd (later calls on it complete with -EBADF).
+ * Errors: -EBADF (fd < 0 or >= 65536).
+ */
+int gsys_allow_fd(gsys_ctx *ctx, int fd, uint32_t perms);
+
+/* buffer kinds */
+#define GSYS_BUF_HOST   1u  /* host memory the host can write (pinned or library-allocated) */
+#define GSYS_BUF_DEVICE 2u  /* HBM: GPU only, never a host call's target                  */
+
+/*
+ * Register [dev_addr, dev_addr + bytes) as a target of GPU calls.  host_addr
+ * is where the host service pool reaches the same bytes (for GSYS_BUF_HOST;
+ * NULL for GSYS_BUF_DEVICE).  The caller keeps ownership; the memory must
+ * outlive gsys_wait().  *out_id receives a handle.
+ * Errors: -EINVAL (bytes == 0, bad kind), -EEXIST (overlaps a registration).
+ */
+int gsys_register_buffer(gsys_ctx *ctx, uint64_t dev_addr, void *host_addr, uint64_t bytes,
+                         uint32_t kind, uint32_t *out_id);
+
+/* Drop a registration.  Errors: -ENOENT. */
+int gsys_unregister_buffer(gsys_ctx *ctx, uint32_t id);
+
+/*
+ * Allocate `bytes` of fine-grained, host-coherent pinned memory that GPU
+ * kernels can read and write while host threads do the same, and register it
+ * as GSYS_BUF_HOST.  *host_out / *dev_out receive the host and device
+ * addresses, *id_out the registration.  Freed by gsys_host_free() or at
+ * shutdown.  Errors: -ENOMEM, -ENODEV.
+ */
+int gsys_host_alloc(gsys_ctx *ctx, uint64_t bytes, void **host_out, uint64_t *dev_out,
+                    uint32_t *id_out);
+int gsys_host_free(gsys_ctx *ctx, void *host_ptr);
+
+/* Copy the device context (what a kernel needs to issue calls) into *out. */
+int gsys_device_ctx(gsys_ctx *ctx, gsys_dev_ctx *out);
+
+/* launch modes */
+#define GSYS_PLAIN      0u  /* one launch as described                              */
+#define GSYS_PERSISTENT 1u  /* grid clamped to what is co-resident on the device    */
+#define GSYS_GRAPH      2u  /* persistent, captured once into a hipGraph, replayed  */
+
+typedef struct gsys_launch_desc {
+    const void *kernel;      /* __global__ function (host stub address)          */
+    uint32_t grid[3];
+    uint32_t block[3];
+    uint32_t lds_bytes;      /* dynamic LDS                                      */
+    uint32_t mode;           /* GSYS_PLAIN | GSYS_PERSISTENT | GSYS_GRAPH         */
+    void   **args;           /* kernel argument pointers, as for hipLaunchKernel */
+} gsys_launch_desc;
+
+/*
+ * Launch a kernel that issues gsys calls.  PERSISTENT clamps grid[0] to the
+ * number of work-groups of that kernel that fit on the device at once, so
+ * that waits on the host never wait on a work-group that cannot run
+ * (section 4.1: kernel-wide strong ordering can deadlock when not every
+ * work-item is resident).  GRAPH captures the clamped launch once per
+ * (kernel, shape) into a hipGraph and replays it.
+ * Errors: -EINVAL, -ENODEV (HIP launch failure).
+ */
+int gsys_launch(gsys_ctx *ctx, const gsys_launch_desc *desc, void *stream);
+
+/*
+ * Drain (section 8.3: a CPU-side call that makes sure every GPU system call
+ * has completed).  Reads how many tickets the GPU has claimed and waits until
+ * the host has serviced all of them, or `timeout_ns` passed (0 = forever).
+ * Call it after the issuing kernels finished to drain everything.
+ * Errors: -ETIMEDOUT.
+ */
+int gsys_wait(gsys_ctx *ctx, uint64_t timeout_ns);
+
+typedef struct gsys_stats {
+    uint64_t requests;          /* ring requests serviced (tickets)              */
+    uint64_t host_calls;        /* POSIX calls executed for them                 */
+    uint64_t bytes_in;          /* bytes delivered toward the GPU (pread, recv)  */
+    uint64_t bytes_out;         /* bytes taken from the GPU (pwrite, send)       */
+    uint64_t errors;            /* calls that returned -errno                    */
+    uint64_t rejected;          /* requests refused by the whitelist checks      */
+    uint64_t bundles;           /* coalesced bundles executed                    */
+    uint64_t merged;            /* transfers folded into a neighbour's call      */
+    uint64_t idle_polls;        /* poller passes that found nothing              */
+    uint64_t retired_lo;        /* every ticket below this has retired           */
+    uint64_t claimed;           /* tickets the GPU has claimed (read at call)    */
+    uint64_t service_ns;        /* host time spent executing calls               */
+    uint64_t bundle_hist[8];    /* bundle sizes 1, 2, 3-4, 5-8, 9-16, 17-32, 33-64, 65+ */
+    uint64_t errno_hist[8];     /* EPERM, EBADF, EFAULT, EINVAL, EAGAIN, ESHUTDOWN, ETIMEDOUT, other */
+} gsys_stats;
+
+/* Snapshot (and optionally reset) the counters. */
+int gsys_stats_get(gsys_ctx *ctx, gsys_stats *out, int reset);
+
+/*
+ * Ledger (GSYS_CFG_LEDGER): copy up to `max` records of serviced tickets,
+ * oldest first, into out[4*i .. 4*i+3] = {ticket, nr, ret, args digest}.
+ * Returns the number of records copied; reset != 0 clears the ledger.
+ */
+int64_t gsys_ledger(gsys_ctx *ctx, uint64_t *out, uint64_t max, int reset);
+
+/*
+ * Stop the pool: drain with `timeout_ns`, complete every request still in the
+ * ring with -ESHUTDOWN so GPU waiters return, join the threads, free the ring,
+ * the completion records and every gsys_host_alloc() buffer.  ctx is invalid
+ * afterwards.  Returns 0, or -ETIMEDOUT if the drain timed out (the context is
+ * torn down all the same).
+ */
+int gsys_shutdown(gsys_ctx *ctx, uint64_t timeout_ns);
+
+/* Static text for a 0 / -errno code. */
+const char *gsys_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * Workload entry points.  Each launches hand-written gfx950 kernels that
+ * issue calls through the ring and consume the results on the GPU.
+ * ------------------------------------------------------------------------ */
+
+/* invocation cell: granularity x ordering x blocking (section 4.1) */
+#define GSYS_CELL_GRAN(c)   ((c) & 3u)        /* GSYS_GRAN_WI / _WG / _KERNEL */
+#define GSYS_CELL_STRONG    0x4u
+#define GSYS_CELL_BLOCKING  0x8u
+
+/*
+ * Per-item pread + FNV-1a-64 checksum (the pread microbenchmark of section 6,
+ * Fig. 5): item i reads item_bytes at offsets[i] from `fd` into
+ * staging + i * item_bytes, then the GPU computes out_fnv[i] over the bytes
+ * read and stores the call's return value in out_ret[i].
+ *
+ *   offsets   device address, uint64[n_items]
+ *   staging   device address of a registered GSYS_BUF_HOST buffer of at least
+ *             n_items * item_bytes bytes
+ *   lists     device address of a registered GSYS_BUF_HOST buffer of at least
+ *             n_items * 16 bytes (descriptor lists of group calls)
+ *   out_fnv   device address, uint64[n_items];  out_ret: int64[n_items]
+ *   cell      GSYS_CELL_* bits; work-item must be strong and kernel must be
+ *             relaxed (section 4.1), others give -EINVAL
+ *   form      GSYS_PLAIN (grid n_items / wg_size) or GSYS_PERSISTENT /
+ *             GSYS_GRAPH (co-resident grid looping over batches of wg_size
+ *             items, double-buffered non-blocking group calls; cell ignored)
+ *   wg_size   work-items per work-group: 64, 128, 256, 512 or 1024
+ * item_bytes must be a multiple of 64 and at most 1 MiB; n_items % wg_size
+ * need not be 0 (the tail work-group is partial).
+ * Errors: -EINVAL (shapes), -EFAULT (unregistered buffers), -ENODEV.
+ */
+int gsys_fnv4k(gsys_ctx *ctx, int fd, uint64_t offsets, uint64_t n_items, uint32_t item_bytes,
+               uint64_t staging, uint64_t lists, uint64_t out_fnv, uint64_t out_ret,
+               uint32_t cell, uint32_t form, uint32_t wg_size, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSYS_H */

@@ -1,0 +1,603 @@
+// C ABI of libgsys.so: context set-up and tear-down, whitelist registration,
+// launches and the drain call.  See include/gsys.h for the contract.
+#include <errno.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/mman.h>
+#include <time.h>
+#include <unistd.h>
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "gsys.h"
+#include "gsys_testing.h"
+#include "host_pool.hpp"
+#include "kernels.hpp"
+
+struct gsys_ctx {
+  gsys_config cfg;
+  bool no_device = false;
+  int device = 0;
+  uint64_t D = 0, C = 0;
+  gsys_slot* ring = nullptr;       // host view
+  gsys_comp* comp = nullptr;       // host view
+  uint64_t* host_words = nullptr;  // [0] retired_lo (own 256-byte line); NO_DEVICE: [32] tail, [48] lo_cache
+  gsys_slot* ring_dev = nullptr;
+  gsys_comp* comp_dev = nullptr;
+  uint64_t* retired_lo_dev = nullptr;
+  unsigned long long* dev_words = nullptr;  // [0] tail, [16] lo_cache, [32..63] kernel-call state
+  gsys_host::Pool* pool = nullptr;
+  hipStream_t aux = nullptr;
+  std::mutex mu;
+  std::map<void*, std::pair<uint64_t, uint32_t>> host_allocs;  // host ptr -> (bytes, id)
+  uint8_t* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  uint64_t timeout_ticks = 0;
+  uint32_t sleep_max = 16;
+  uint32_t grid_override = 0;
+  int cu_count = 0;
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+};
+
+namespace {
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+uint64_t env_u64(const char* name, uint64_t dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return strtoull(v, nullptr, 0);
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+// fine-grained, host-coherent pinned memory visible to the GPU
+int host_coherent(gsys_ctx* c, uint64_t bytes, void** host, void** dev) {
+  if (c->no_device) {
+    void* p = nullptr;
+    if (posix_memalign(&p, 4096, bytes)) return -ENOMEM;
+    memset(p, 0, bytes);
+    *host = p;
+    *dev = p;
+    return 0;
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable) !=
+      hipSuccess)
+    return -ENOMEM;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+    hipHostFree(p);
+    return -ENODEV;
+  }
+  memset(p, 0, bytes);
+  *host = p;
+  *dev = d;
+  return 0;
+}
+
+void host_coherent_free(gsys_ctx* c, void* host) {
+  if (!host) return;
+  if (c->no_device) free(host);
+  else hipHostFree(host);
+}
+
+uint64_t claimed_tickets(gsys_ctx* c) {
+  if (c->no_device) return __atomic_load_n(&c->host_words[32], __ATOMIC_ACQUIRE);
+  unsigned long long v = 0;
+  hipSetDevice(c->device);
+  if (hipMemcpyAsync(&v, c->dev_words, sizeof v, hipMemcpyDeviceToHost, c->aux) != hipSuccess)
+    return 0;
+  hipStreamSynchronize(c->aux);
+  return v;
+}
+
+void destroy(gsys_ctx* c) {
+  if (!c) return;
+  if (c->pool) {
+    c->pool->stop_and_join();
+    delete c->pool;
+    c->pool = nullptr;
+  }
+  if (!c->no_device) {
+    hipSetDevice(c->device);
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.second);
+    for (auto g : c->graph_defs) hipGraphDestroy(g);
+    if (c->aux) hipStreamDestroy(c->aux);
+    if (c->dev_words) hipFree(c->dev_words);
+  }
+  for (auto& kv : c->host_allocs) host_coherent_free(c, kv.first);
+  c->host_allocs.clear();
+  host_coherent_free(c, c->ring);
+  host_coherent_free(c, c->comp);
+  host_coherent_free(c, c->host_words);
+  if (c->arena) munmap(c->arena, c->arena_bytes);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
+  if (!out) return -EINVAL;
+  *out = nullptr;
+  gsys_config cfg;
+  memset(&cfg, 0, sizeof cfg);
+  cfg.abi_version = GSYS_ABI_VERSION;
+  cfg.first_cpu = -1;
+  if (cfg_in) cfg = *cfg_in;
+  if (cfg.abi_version != GSYS_ABI_VERSION) return -EINVAL;
+  // environment overrides (the autotuner writes these)
+  cfg.ring_slots = (uint32_t)env_u64("GSYS_RING_SLOTS", cfg.ring_slots);
+  cfg.service_threads = (uint32_t)env_u64("GSYS_SERVICE_THREADS", cfg.service_threads);
+  cfg.coalesce_max = (uint32_t)env_u64("GSYS_COALESCE_MAX", cfg.coalesce_max);
+  cfg.coalesce_window_ns = (uint32_t)env_u64("GSYS_COALESCE_WINDOW_NS", cfg.coalesce_window_ns);
+  cfg.stripe = (uint32_t)env_u64("GSYS_STRIPE", cfg.stripe);
+  if (!cfg.ring_slots) cfg.ring_slots = 65536;
+  if (!is_pow2(cfg.ring_slots) || cfg.ring_slots < 64 || cfg.ring_slots > (1u << 24)) return -EINVAL;
+  if (cfg.stripe > 64) return -EINVAL;
+
+  gsys_ctx* c = new (std::nothrow) gsys_ctx;
+  if (!c) return -ENOMEM;
+  c->cfg = cfg;
+  c->no_device = (cfg.flags & GSYS_CFG_NO_DEVICE) != 0;
+  c->device = cfg.device;
+  c->D = cfg.ring_slots;
+  c->C = 4 * c->D;
+  c->grid_override = (uint32_t)env_u64("GSYS_PERSISTENT_GRID", 0);
+  c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", 16);
+  const uint64_t tmo = cfg.device_timeout_ns ? cfg.device_timeout_ns : 30000000000ull;
+  c->timeout_ticks = tmo / 10;  // 100 MHz device wall clock
+
+  if (!c->no_device) {
+    if (hipSetDevice(c->device) != hipSuccess) {
+      destroy(c);
+      return -ENODEV;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+      destroy(c);
+      return -ENODEV;
+    }
+    c->cu_count = prop.multiProcessorCount;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess &&
+        wall_khz > 0)
+      c->timeout_ticks = (uint64_t)((double)tmo * 1e-9 * (double)wall_khz * 1e3);
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void**)&c->dev_words, 64 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->dev_words, 0, 64 * sizeof(unsigned long long)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+      destroy(c);
+      return -ENODEV;
+    }
+  }
+  void *rh, *rd, *ch, *cd, *wh, *wd;
+  int e;
+  if ((e = host_coherent(c, c->D * sizeof(gsys_slot), &rh, &rd)) ||
+      (c->ring = (gsys_slot*)rh, c->ring_dev = (gsys_slot*)rd, false) ||
+      (e = host_coherent(c, c->C * sizeof(gsys_comp), &ch, &cd)) ||
+      (c->comp = (gsys_comp*)ch, c->comp_dev = (gsys_comp*)cd, false) ||
+      (e = host_coherent(c, 4096, &wh, &wd))) {
+    destroy(c);
+    return e;
+  }
+  c->host_words = (uint64_t*)wh;
+  c->retired_lo_dev = (uint64_t*)wd;
+  for (uint64_t i = 0; i < c->D; ++i) c->ring[i].ctl = GSYS_CTL(i, GSYS_ST_FREE);
+  if (cfg.arena_bytes) {
+    const uint64_t bytes = (cfg.arena_bytes + (2u << 20) - 1) & ~((2ull << 20) - 1);
+    // reserve, 2 MiB aligned
+    void* m = mmap(nullptr, bytes + (2u << 20), PROT_NONE,
+                   MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+    if (m == MAP_FAILED) {
+      destroy(c);
+      return -ENOMEM;
+    }
+    uint8_t* a = (uint8_t*)(((uint64_t)m + (2u << 20) - 1) & ~((2ull << 20) - 1));
+    if (a != m) munmap(m, (size_t)(a - (uint8_t*)m));
+    munmap(a + bytes, (size_t)(((uint8_t*)m + bytes + (2u << 20)) - (a + bytes)));
+    c->arena = a;
+    c->arena_bytes = bytes;
+  }
+  __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  c->pool = new (std::nothrow) gsys_host::Pool(c->ring, c->comp, c->D, c->C, c->host_words, cfg);
+  if (!c->pool) {
+    destroy(c);
+    return -ENOMEM;
+  }
+  if (c->arena) c->pool->set_arena(c->arena, c->arena_bytes);
+  c->pool->start();
+  *out = c;
+  return 0;
+}
+
+int gsys_allow_fd(gsys_ctx* c, int fd, uint32_t perms) {
+  if (!c) return -EINVAL;
+  return c->pool->allow_fd(fd, perms);
+}
+
+int gsys_register_buffer(gsys_ctx* c, uint64_t dev, void* host, uint64_t bytes, uint32_t kind,
+                         uint32_t* out_id) {
+  if (!c) return -EINVAL;
+  return c->pool->add_buffer(dev, (uint8_t*)host, bytes, kind, out_id);
+}
+
+int gsys_unregister_buffer(gsys_ctx* c, uint32_t id) {
+  if (!c) return -EINVAL;
+  return c->pool->remove_buffer(id);
+}
+
+int gsys_host_alloc(gsys_ctx* c, uint64_t bytes, void** host_out, uint64_t* dev_out,
+                    uint32_t* id_out) {
+  if (!c || !bytes || !host_out || !dev_out) return -EINVAL;
+  if (!c->no_device) hipSetDevice(c->device);
+  void *h, *d;
+  if (int e = host_coherent(c, bytes, &h, &d)) return e;
+  uint32_t id = 0;
+  if (int e = c->pool->add_buffer((uint64_t)d, (uint8_t*)h, bytes, GSYS_BUF_HOST, &id)) {
+    host_coherent_free(c, h);
+    return e;
+  }
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->host_allocs[h] = {bytes, id};
+  }
+  *host_out = h;
+  *dev_out = (uint64_t)d;
+  if (id_out) *id_out = id;
+  return 0;
+}
+
+int gsys_host_free(gsys_ctx* c, void* host) {
+  if (!c) return -EINVAL;
+  std::lock_guard<std::mutex> g(c->mu);
+  auto it = c->host_allocs.find(host);
+  if (it == c->host_allocs.end()) return -ENOENT;
+  c->pool->remove_buffer(it->second.second);
+  host_coherent_free(c, host);
+  c->host_allocs.erase(it);
+  return 0;
+}
+
+int gsys_device_ctx(gsys_ctx* c, gsys_dev_ctx* out) {
+  if (!c || !out) return -EINVAL;
+  memset(out, 0, sizeof *out);
+  out->ring = c->ring_dev;
+  out->comp = c->comp_dev;
+  if (c->no_device) {
+    out->tail = (unsigned long long*)&c->host_words[32];
+    out->lo_cache = (unsigned long long*)&c->host_words[48];
+  } else {
+    out->tail = c->dev_words;
+    out->lo_cache = c->dev_words + 16;
+  }
+  out->retired_lo = c->retired_lo_dev;
+  out->ring_mask = c->D - 1;
+  out->comp_mask = c->C - 1;
+  out->timeout_ticks = c->timeout_ticks;
+  out->sleep_max = c->sleep_max;
+  out->flags = c->cfg.flags;
+  out->arena = (uint64_t)c->arena;
+  out->arena_bytes = c->arena_bytes;
+  return 0;
+}
+
+int gsys_launch(gsys_ctx* c, const gsys_launch_desc* d, void* stream) {
+  if (!c || !d || !d->kernel || c->no_device) return -EINVAL;
+  uint32_t grid = d->grid[0];
+  if (d->mode == GSYS_PERSISTENT || d->mode == GSYS_GRAPH) {
+    uint32_t r = gsys_internal::resident_grid(c, d->kernel, d->block[0] * d->block[1] * d->block[2],
+                                              d->lds_bytes);
+    if (!r) return -ENODEV;
+    if (grid > r) grid = r;
+  } else if (d->mode != GSYS_PLAIN) {
+    return -EINVAL;
+  }
+  hipSetDevice(c->device);
+  dim3 g(grid, d->grid[1] ? d->grid[1] : 1, d->grid[2] ? d->grid[2] : 1);
+  dim3 b(d->block[0], d->block[1] ? d->block[1] : 1, d->block[2] ? d->block[2] : 1);
+  if (d->mode == GSYS_GRAPH) {
+    if (g.y != 1 || g.z != 1 || b.y != 1 || b.z != 1) return -EINVAL;
+    const uint64_t key = gsys_internal::hash_words(
+        {(uint64_t)d->kernel, grid, d->block[0], d->lds_bytes, (uint64_t)d->args});
+    return gsys_internal::launch_graph(c, key, d->kernel, grid, d->block[0], d->lds_bytes, d->args,
+                                       (hipStream_t)stream);
+  }
+  if (hipLaunchKernel(d->kernel, g, b, d->args, d->lds_bytes, (hipStream_t)stream) != hipSuccess)
+    return -ENODEV;
+  return 0;
+}
+
+int gsys_wait(gsys_ctx* c, uint64_t timeout_ns) {
+  if (!c) return -EINVAL;
+  const uint64_t want = claimed_tickets(c);
+  const uint64_t t0 = now_ns();
+  uint32_t spins = 0;
+  while (c->pool->serviced() < want) {
+    if (timeout_ns && now_ns() - t0 > timeout_ns) return -ETIMEDOUT;
+    if (++spins < 1000) {
+      std::this_thread::yield();
+    } else {
+      timespec ts{0, 20000};
+      nanosleep(&ts, nullptr);
+    }
+  }
+  c->pool->retire_scan();
+  return 0;
+}
+
+int gsys_stats_get(gsys_ctx* c, gsys_stats* out, int reset) {
+  if (!c || !out) return -EINVAL;
+  c->pool->stats(out, reset);
+  out->claimed = claimed_tickets(c);
+  return 0;
+}
+
+int64_t gsys_ledger(gsys_ctx* c, uint64_t* out, uint64_t max, int reset) {
+  if (!c) return -EINVAL;
+  return c->pool->ledger(out, max, reset);
+}
+
+int gsys_shutdown(gsys_ctx* c, uint64_t timeout_ns) {
+  if (!c) return -EINVAL;
+  int rc = gsys_wait(c, timeout_ns ? timeout_ns : 1);
+  c->pool->stop_and_join();
+  c->pool->poison_outstanding(claimed_tickets(c));
+  if (!c->no_device) {
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+  }
+  destroy(c);
+  return rc;
+}
+
+const char* gsys_strerror(int code) {
+  switch (-code) {
+    case 0: return "success";
+    case EPERM: return "call not in the whitelist";
+    case EBADF: return "file descriptor not allowed";
+    case EFAULT: return "address range not registered";
+    case EINVAL: return "invalid argument";
+    case ENOMEM: return "out of memory";
+    case ENODEV: return "HIP runtime failure";
+    case EEXIST: return "overlaps a registered buffer";
+    case ENOENT: return "no such registration";
+    case ETIMEDOUT: return "timed out";
+    case ESHUTDOWN: return "context shut down";
+    case EOVERFLOW: return "completion record reused before it was read";
+    case EAGAIN: return "try again";
+    case EINPROGRESS: return "not waited for";
+    default: return strerror(-code);
+  }
+}
+
+// ------------------------------------------------------------------ testing
+namespace {
+
+struct EmuShared {
+  gsys_dev_ctx d;
+  uint64_t timeout_ns;
+};
+
+uint64_t emu_claim(const EmuShared& e, uint32_t n, int* err) {
+  uint64_t t = __atomic_fetch_add((uint64_t*)e.d.tail, (uint64_t)n, __ATOMIC_RELAXED);
+  const uint64_t D = e.d.ring_mask + 1;
+  const uint64_t t0 = now_ns();
+  for (;;) {
+    uint64_t lo = __atomic_load_n(e.d.retired_lo, __ATOMIC_ACQUIRE);
+    if (lo + D >= t + n) break;
+    if (now_ns() - t0 > e.timeout_ns) {
+      *err = -ETIMEDOUT;
+      break;
+    }
+    std::this_thread::yield();
+  }
+  return t;
+}
+
+void emu_publish(const EmuShared& e, uint64_t t, uint16_t nr, uint8_t flags, uint32_t n,
+                 uint32_t off, const uint64_t* a) {
+  gsys_slot* s = e.d.ring + (t & e.d.ring_mask);
+  __atomic_store_n(&s->ctl, GSYS_CTL(t, GSYS_ST_POPULATING), __ATOMIC_RELAXED);
+  s->nr = nr;
+  s->flags = flags;
+  s->grp_n = (uint8_t)n;
+  s->grp_off = off;
+  for (int i = 0; i < 6; ++i) s->args[i] = a[i];
+  __atomic_store_n(&s->ctl, GSYS_CTL(t, GSYS_ST_READY), __ATOMIC_RELEASE);
+}
+
+int emu_wait(const EmuShared& e, uint64_t head, uint32_t n) {
+  const uint64_t want = GSYS_STAMP(head, n);
+  const uint64_t* st = &e.d.comp[head & e.d.comp_mask].stamp;
+  const uint64_t t0 = now_ns();
+  for (;;) {
+    uint64_t v = __atomic_load_n(st, __ATOMIC_ACQUIRE);
+    if (v == want) return 0;
+    if ((v >> 8) > head) return -EOVERFLOW;
+    if (now_ns() - t0 > e.timeout_ns) return -ETIMEDOUT;
+    std::this_thread::yield();
+  }
+}
+
+}  // namespace
+
+int gsys_test_emulate(gsys_ctx* c, uint32_t threads, uint64_t per, uint32_t group, uint32_t mode,
+                      int fd, uint64_t buf_dev, uint64_t list_dev, uint32_t len, const uint64_t* offs,
+                      int64_t* rets, uint64_t timeout_ns) {
+  if (!c || !c->no_device || !threads || !group || group > 64 || !offs || !rets) return -EINVAL;
+  EmuShared e;
+  gsys_device_ctx(c, &e.d);
+  e.timeout_ns = timeout_ns ? timeout_ns : 10000000000ull;
+  const bool blocking = mode & GSYS_EMU_BLOCKING;
+  const bool list = mode & GSYS_EMU_LIST;
+  std::vector<int> errs(threads, 0);
+  std::vector<std::thread> th;
+  for (uint32_t w = 0; w < threads; ++w) {
+    th.emplace_back([&, w] {
+      uint64_t k = (uint64_t)w * per;
+      const uint64_t end = k + per;
+      while (k < end && !errs[w]) {
+        const uint32_t n = (uint32_t)std::min<uint64_t>(group, end - k);
+        int err = 0;
+        if (list) {
+          gsys_iodesc* L = (gsys_iodesc*)(list_dev + 16 * k);
+          for (uint32_t i = 0; i < n; ++i)
+            L[i] = gsys_iodesc{offs[k + i], (uint32_t)(i * len), (int32_t)len};
+          uint64_t t = emu_claim(e, 1, &err);
+          if (err) { errs[w] = err; break; }
+          uint64_t a[6] = {(uint64_t)(int64_t)fd, (uint64_t)L, n, buf_dev + k * len, 0, 0};
+          emu_publish(e, t, GSYS_NR_PREAD64,
+                      (uint8_t)(GSYS_F_LIST | (blocking ? GSYS_F_BLOCKING : 0) |
+                                (GSYS_GRAN_WG << GSYS_F_GRAN_SHIFT)),
+                      1, 0, a);
+          err = emu_wait(e, t, 1);
+          if (err) { errs[w] = err; break; }
+          for (uint32_t i = 0; i < n; ++i) rets[k + i] = __atomic_load_n(&L[i].len_ret, __ATOMIC_ACQUIRE);
+          if (blocking)
+            __atomic_store_n(&e.d.ring[t & e.d.ring_mask].ctl,
+                             GSYS_CTL(t + e.d.ring_mask + 1, GSYS_ST_FREE), __ATOMIC_RELEASE);
+        } else {
+          uint64_t t = emu_claim(e, n, &err);
+          if (err) { errs[w] = err; break; }
+          for (uint32_t i = 0; i < n; ++i) {
+            uint64_t a[6] = {(uint64_t)(int64_t)fd, buf_dev + (k + i) * len, len, offs[k + i], 0, 0};
+            emu_publish(e, t + i, GSYS_NR_PREAD64,
+                        (uint8_t)((blocking ? GSYS_F_BLOCKING : 0) | GSYS_F_STRONG), n, i, a);
+          }
+          err = emu_wait(e, t, n);
+          if (err) { errs[w] = err; break; }
+          for (uint32_t i = 0; i < n; ++i) {
+            rets[k + i] = __atomic_load_n(&e.d.comp[(t + i) & e.d.comp_mask].ret, __ATOMIC_ACQUIRE);
+            if (blocking)
+              __atomic_store_n(&e.d.ring[(t + i) & e.d.ring_mask].ctl,
+                               GSYS_CTL(t + i + e.d.ring_mask + 1, GSYS_ST_FREE), __ATOMIC_RELEASE);
+          }
+        }
+        k += n;
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  for (int x : errs)
+    if (x) return x;
+  return 0;
+}
+
+int gsys_test_raw_call(gsys_ctx* c, uint16_t nr, uint8_t flags, const uint64_t* args6, int64_t* ret,
+                       uint64_t timeout_ns) {
+  if (!c || !c->no_device || !args6 || !ret) return -EINVAL;
+  EmuShared e;
+  gsys_device_ctx(c, &e.d);
+  e.timeout_ns = timeout_ns ? timeout_ns : 10000000000ull;
+  int err = 0;
+  uint64_t t = emu_claim(e, 1, &err);
+  if (err) return err;
+  emu_publish(e, t, nr, flags, 1, 0, args6);
+  err = emu_wait(e, t, 1);
+  if (err) return err;
+  *ret = __atomic_load_n(&e.d.comp[t & e.d.comp_mask].ret, __ATOMIC_ACQUIRE);
+  if (flags & GSYS_F_BLOCKING)
+    __atomic_store_n(&e.d.ring[t & e.d.ring_mask].ctl, GSYS_CTL(t + e.d.ring_mask + 1, GSYS_ST_FREE),
+                     __ATOMIC_RELEASE);
+  return 0;
+}
+
+int64_t gsys_test_claim_only(gsys_ctx* c, uint32_t n) {
+  if (!c || !c->no_device) return -EINVAL;
+  return (int64_t)__atomic_fetch_add(&c->host_words[32], (uint64_t)n, __ATOMIC_ACQ_REL);
+}
+
+int gsys_test_ring_ctl(gsys_ctx* c, uint64_t* out, uint64_t max) {
+  if (!c || !out) return -EINVAL;
+  const uint64_t n = std::min<uint64_t>(max, c->D);
+  for (uint64_t i = 0; i < n; ++i) out[i] = __atomic_load_n(&c->ring[i].ctl, __ATOMIC_ACQUIRE);
+  return (int)n;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- internal
+namespace gsys_internal {
+
+int check_host_range(gsys_ctx* c, uint64_t dev, uint64_t bytes) {
+  // the pool's table holds every registration, including gsys_host_alloc ones
+  return c->pool->host_range(dev, bytes) ? 0 : -EFAULT;
+}
+
+void* kstate(gsys_ctx* c) { return c->dev_words + 32; }
+
+uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t lds) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, lds) != hipSuccess)
+    return 0;
+  if (per_cu < 1) return 0;
+  return (uint32_t)per_cu * (uint32_t)c->cu_count;
+}
+
+uint32_t persistent_grid_override(gsys_ctx* c) { return c->grid_override; }
+
+uint64_t hash_words(std::initializer_list<uint64_t> w) {
+  uint64_t h = 0x9e3779b97f4a7c15ull;
+  for (uint64_t x : w) {
+    h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h *= 0xbf58476d1ce4e5b9ull;
+  }
+  return h;
+}
+
+int launch(gsys_ctx* c, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds, void** args,
+           hipStream_t s) {
+  hipSetDevice(c->device);
+  if (hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, s) != hipSuccess) return -ENODEV;
+  return 0;
+}
+
+int launch_graph(gsys_ctx* c, uint64_t key, const void* kernel, uint32_t grid, uint32_t block,
+                 uint32_t lds, void** args, hipStream_t s) {
+  hipSetDevice(c->device);
+  hipGraphExec_t ex = nullptr;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) ex = it->second;
+  }
+  if (!ex) {
+    // capture on a private stream so the caller's stream is never in capture mode
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return -ENODEV;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      hipStreamDestroy(cs);
+      return -ENODEV;
+    }
+    hipError_t le = hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, cs);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (le != hipSuccess || ce != hipSuccess || !graph) return -ENODEV;
+    if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(graph);
+      return -ENODEV;
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    c->graphs[key] = ex;
+    c->graph_defs.push_back(graph);
+  }
+  if (hipGraphLaunch(ex, s) != hipSuccess) return -ENODEV;
+  return 0;
+}
+
+}  // namespace gsys_internal

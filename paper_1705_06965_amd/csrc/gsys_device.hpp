@@ -1,0 +1,479 @@
+// Device side of gsys: issuing system calls from gfx950 kernels.
+//
+// A call is made at one of three granularities (section 4.1): by every
+// work-item for itself, by one designated work-item for its work-group, or by
+// one designated work-item for the whole kernel (section 5).  Each call has an
+// ordering -- strong (synchronise the group before and after the call) or
+// relaxed (before only for a producer such as write/send, after only for a
+// consumer such as read/recv) -- and is blocking or non-blocking.  Work-item
+// calls are implicitly strong; kernel calls can only be relaxed, because a
+// kernel-wide barrier before the call can deadlock when not every work-item of
+// the kernel is resident (section 4.1).  Both rules are compile-time errors
+// here.
+//
+// Transport: a ring of 64-byte slots in fine-grained host-coherent memory
+// (section 5's syscall area, claimed by ticket).  Work-item calls of one
+// wavefront are coalesced: the active lanes are counted with a ballot, one
+// lane takes a contiguous run of tickets with a single device-scope
+// fetch-add, and each lane fills its own slot.  A request becomes visible to
+// the host with a system-scope release store of READY; results come back in
+// completion records that one lane per wavefront (or per work-group) polls
+// with s_sleep backoff and a wall-clock watchdog, so a missing host answer
+// ends the wait with -ETIMEDOUT instead of a hung kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsys_abi.h"
+
+namespace gsys {
+
+enum class G { WorkItem, WorkGroup, Kernel };
+enum class O { Strong, Relaxed };
+enum class B { Blocking, NonBlocking };
+enum class Role { Producer, Consumer };
+
+// Role of each whitelisted call under relaxed ordering: data flows out of the
+// GPU program for write/send (producers) and into it for read/recv
+// (section 4.1).  mmap hands back an address, so it is a consumer; munmap and
+// madvise act on memory the program is done with, so they are producers (the
+// paper issues madvise non-blocking and relaxed, section 7.2).
+__host__ __device__ constexpr Role role_of(int nr) {
+  return (nr == GSYS_NR_WRITE || nr == GSYS_NR_PWRITE64 || nr == GSYS_NR_SENDTO ||
+          nr == GSYS_NR_MUNMAP || nr == GSYS_NR_MADVISE)
+             ? Role::Producer
+             : Role::Consumer;
+}
+
+template <G g, O o>
+struct Legal {
+  // section 4.1 / section 5: work-item calls are implicitly strong, kernel
+  // calls are relaxed only.
+  static_assert(!(g == G::WorkItem && o == O::Relaxed),
+                "work-item granularity supports only (implicit) strong ordering");
+  static_assert(!(g == G::Kernel && o == O::Strong),
+                "kernel granularity supports only relaxed ordering");
+  static constexpr bool ok = true;
+};
+
+// A handle on an issued call.  n == 0: this lane holds no call.
+struct Ticket {
+  uint64_t t;         // ticket of this lane's (or the group's) request
+  uint32_t head_off;  // t - first ticket of its claim group
+  uint32_t n;         // size of the claim group
+};
+
+// ----------------------------------------------------------- memory helpers
+__device__ __forceinline__ uint64_t ld_sys(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_sys_acq(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ int64_t ld_sys_i64(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_sys(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_sys_rel(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void fence_release_sys() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, ""); }
+__device__ __forceinline__ void fence_acquire_sys() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t src) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t active_mask() { return __ballot(1); }
+__device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)__ffsll((long long)m) - 1u; }
+
+// Exponential backoff with s_sleep and a wall-clock watchdog
+// (wall_clock64 runs at a constant 100 MHz on gfx9).
+struct Waiter {
+  uint64_t deadline;
+  uint32_t n, cap;
+  __device__ explicit Waiter(const gsys_dev_ctx& c)
+      : deadline(c.timeout_ticks ? wall_clock64() + c.timeout_ticks : ~0ull),
+        n(1), cap(c.sleep_max ? c.sleep_max : 16) {}
+  // false once the watchdog expired
+  __device__ bool pause() {
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(4);
+    if (n < cap) n <<= 1;
+    return wall_clock64() < deadline;
+  }
+};
+
+// ------------------------------------------------------------ ring protocol
+// Wait until tickets [t0, t0 + n) fit in the ring: every ticket below
+// t0 + n - D must have retired.  The host publishes a watermark; the device
+// keeps a cached copy so that the common case costs no host round trip.
+__device__ __forceinline__ int wait_ring_space(const gsys_dev_ctx& c, uint64_t t0, uint32_t n) {
+  const uint64_t D = c.ring_mask + 1;
+  const uint64_t need = t0 + n;  // need lo + D >= t0 + n
+  uint64_t lo = __hip_atomic_load(c.lo_cache, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lo + D >= need) return 0;
+  Waiter w(c);
+  for (;;) {
+    lo = ld_sys_acq(c.retired_lo);
+    __hip_atomic_fetch_max(c.lo_cache, (unsigned long long)lo, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (lo + D >= need) return 0;
+    if (!w.pause()) return GSYS_ETIMEDOUT_RET;
+  }
+}
+
+// Fill slot t and hand it to the host (FREE -> POPULATING -> READY).
+__device__ __forceinline__ void publish(const gsys_dev_ctx& c, uint64_t t, uint16_t nr,
+                                        uint8_t flags, uint32_t grp_n, uint32_t grp_off,
+                                        uint64_t a0, uint64_t a1, uint64_t a2, uint64_t a3,
+                                        uint64_t a4, uint64_t a5) {
+  gsys_slot* s = c.ring + (t & c.ring_mask);
+  uint64_t* w = reinterpret_cast<uint64_t*>(s);
+  st_sys(&s->ctl, GSYS_CTL(t, GSYS_ST_POPULATING));
+  const uint64_t hdr = (uint64_t)nr | ((uint64_t)flags << 16) | ((uint64_t)grp_n << 24) |
+                       ((uint64_t)grp_off << 32);
+  w[1] = hdr;
+  w[2] = a0; w[3] = a1; w[4] = a2; w[5] = a3; w[6] = a4; w[7] = a5;
+  st_sys_rel(&s->ctl, GSYS_CTL(t, GSYS_ST_READY));
+}
+
+// Poll the completion record of claim group `head` until `n` members are done.
+// Returns 0, -ETIMEDOUT, or -EOVERFLOW if the record was reused by a later lap.
+__device__ __forceinline__ int poll_group(const gsys_dev_ctx& c, uint64_t head, uint32_t n) {
+  const uint64_t* st = &c.comp[head & c.comp_mask].stamp;
+  const uint64_t want = GSYS_STAMP(head, n);
+  uint64_t v = ld_sys_acq(st);
+  if (v == want) return 0;
+  Waiter w(c);
+  for (;;) {
+    if (v == want) return 0;
+    if ((v >> 8) > head) return GSYS_EOVERFLOW_RET;
+    if (!w.pause()) return GSYS_ETIMEDOUT_RET;
+    v = ld_sys_acq(st);
+  }
+}
+
+__device__ __forceinline__ int64_t read_ret(const gsys_dev_ctx& c, uint64_t t) {
+  return ld_sys_i64(&c.comp[t & c.comp_mask].ret);
+}
+
+// Blocking calls: the GPU frees the slot once it has the result (section 5).
+__device__ __forceinline__ void free_slot(const gsys_dev_ctx& c, uint64_t t) {
+  gsys_slot* s = c.ring + (t & c.ring_mask);
+  st_sys_rel(&s->ctl, GSYS_CTL(t + c.ring_mask + 1, GSYS_ST_FREE));
+}
+
+// Wave-level wait for the tickets held by the active lanes.  Lanes may hold
+// tickets of different claim groups; one lane polls each distinct group.
+// Returns this lane's result (or the wait's error code).
+__device__ inline int64_t wave_wait(const gsys_dev_ctx& c, const Ticket& tk, bool free_after) {
+  int64_t ret = GSYS_NOT_WAITED;
+  bool pending = tk.n != 0;
+  const uint64_t head = tk.t - tk.head_off;
+  int err = 0;
+  for (;;) {
+    uint64_t m = __ballot(pending);
+    if (!m) break;
+    uint32_t src = first_lane(m);
+    uint64_t h = bcast64(head, src);
+    uint32_t n = __builtin_amdgcn_readlane(tk.n, src);
+    int e = 0;
+    if (lane_id() == src) e = poll_group(c, h, n);
+    e = __builtin_amdgcn_readlane(e, src);
+    if (pending && head == h) {
+      pending = false;
+      err = e;
+    }
+  }
+  if (tk.n != 0) {
+    fence_acquire_sys();
+    if (err == 0) {
+      ret = read_ret(c, tk.t);
+      if (free_after) free_slot(c, tk.t);
+    } else {
+      ret = err;
+    }
+  }
+  return ret;
+}
+
+// ------------------------------------------------------------- public calls
+struct Args6 {
+  uint64_t a[6];
+};
+
+// Work-item granularity: every active lane issues its own call.  Implicitly
+// strong: its prior writes are released at system scope before the call and
+// results are acquired after it.
+template <B b>
+__device__ inline int64_t call_wi(const gsys_dev_ctx& c, uint16_t nr, const Args6& a,
+                                  Ticket* out = nullptr) {
+  (void)Legal<G::WorkItem, O::Strong>::ok;
+  const uint64_t m = active_mask();
+  const uint32_t n = (uint32_t)__popcll(m);
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  const uint32_t leader = first_lane(m);
+  uint64_t base = 0;
+  int err = 0;
+  if (lane_id() == leader) {
+    base = __hip_atomic_fetch_add(c.tail, (unsigned long long)n, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    err = wait_ring_space(c, base, n);
+  }
+  base = bcast64(base, leader);
+  err = __builtin_amdgcn_readlane(err, leader);
+  Ticket tk{base + rank, rank, n};
+  if (err) {
+    // No room appeared before the watchdog: the tickets stay claimed but
+    // unpublished, so nothing can be serviced for them.
+    if (out) *out = Ticket{0, 0, 0};
+    return err;
+  }
+  const uint8_t fl = (uint8_t)((b == B::Blocking ? GSYS_F_BLOCKING : 0u) | GSYS_F_STRONG |
+                               (role_of(nr) == Role::Producer ? GSYS_F_PRODUCER : 0u) |
+                               (GSYS_GRAN_WI << GSYS_F_GRAN_SHIFT));
+  fence_release_sys();
+  publish(c, tk.t, nr, fl, n, rank, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+  if (out) *out = tk;
+  if constexpr (b == B::Blocking) {
+    return wave_wait(c, tk, true);
+  } else {
+    return 0;
+  }
+}
+
+// Wait for a non-blocking work-item call (all active lanes call this).
+__device__ inline int64_t wait_wi(const gsys_dev_ctx& c, const Ticket& tk) {
+  return wave_wait(c, tk, false);
+}
+
+// Work-group granularity.  Every work-item of the group must call this (it
+// contains work-group barriers when the ordering needs them); local thread 0
+// is the designated caller and its arguments are the call's arguments
+// (section 5).  Returns the call's result to every lane that waited for it:
+// all lanes when a barrier follows the call, only the caller's wavefront for
+// a blocking relaxed producer, nobody for non-blocking calls (GSYS_NOT_WAITED;
+// the ticket goes to *out on thread 0).
+template <O o, B b>
+__device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t extra_flags,
+                                  const Args6& a, Ticket* out = nullptr) {
+  (void)Legal<G::WorkGroup, o>::ok;
+  __shared__ int64_t s_ret;
+  const bool producer = role_of(nr) == Role::Producer;
+  const bool barrier_before = (o == O::Strong) || producer;
+  const bool barrier_after = (o == O::Strong) || !producer;
+  if (barrier_before) {
+    fence_release_sys();  // every wavefront makes its writes visible to the host
+    __syncthreads();
+  }
+  Ticket tk{0, 0, 0};
+  int64_t ret = GSYS_NOT_WAITED;
+  if (threadIdx.x == 0) {
+    uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int err = wait_ring_space(c, t, 1);
+    if (err) {
+      ret = err;
+    } else {
+      const uint8_t fl = (uint8_t)((b == B::Blocking ? GSYS_F_BLOCKING : 0u) |
+                                   (o == O::Strong ? GSYS_F_STRONG : 0u) |
+                                   (producer ? GSYS_F_PRODUCER : 0u) | extra_flags |
+                                   (GSYS_GRAN_WG << GSYS_F_GRAN_SHIFT));
+      if (!barrier_before) fence_release_sys();
+      publish(c, t, nr, fl, 1, 0, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+      tk = Ticket{t, 0, 1};
+      if constexpr (b == B::Blocking) {
+        int e = poll_group(c, t, 1);
+        fence_acquire_sys();
+        if (e == 0) {
+          ret = read_ret(c, t);
+          free_slot(c, t);
+        } else {
+          ret = e;
+        }
+      } else {
+        ret = 0;
+      }
+    }
+    if (out) *out = tk;
+  }
+  if (barrier_after) {
+    if (threadIdx.x == 0) s_ret = ret;
+    __syncthreads();
+    ret = s_ret;
+    fence_acquire_sys();
+    if constexpr (b == B::NonBlocking) ret = GSYS_NOT_WAITED;
+  } else if constexpr (b == B::Blocking) {
+    // weak-block: only the caller's wavefront waits (section 6).
+    if (threadIdx.x < 64) ret = bcast64((uint64_t)ret, 0);
+  }
+  return ret;
+}
+
+// Wait for a non-blocking work-group call: thread 0 polls, then the group
+// synchronises.  Every work-item of the group calls this.
+__device__ inline int64_t wait_wg(const gsys_dev_ctx& c, const Ticket& tk_thread0) {
+  __shared__ int64_t s_ret;
+  if (threadIdx.x == 0) {
+    int64_t r = GSYS_NOT_WAITED;
+    if (tk_thread0.n) {
+      int e = poll_group(c, tk_thread0.t, 1);
+      fence_acquire_sys();
+      r = e ? (int64_t)e : read_ret(c, tk_thread0.t);
+    }
+    s_ret = r;
+  }
+  __syncthreads();
+  fence_acquire_sys();
+  return s_ret;
+}
+
+// Per-launch state of one kernel-granularity call site; zero it before each
+// launch.
+struct KState {
+  unsigned int elect;        // consumer calls: the first arriver takes it
+  unsigned int arrived;      // producer calls: arrivals; the last arriver calls
+  unsigned long long ticket; // ticket + 1 once published, KS_FAILED on failure
+};
+constexpr unsigned long long KS_FAILED = ~0ull;
+
+// Kernel granularity, relaxed only.  Every work-item of every work-group calls
+// this.  Consumer calls: the first work-group to arrive is the caller, and
+// every work-group waits for the result before going on (the barrier after).
+// Producer calls: every work-group releases its writes and arrives; the last
+// one to arrive is the caller, and nobody else waits (the barrier before).
+// The caller's arguments come from `make_args`, evaluated by local thread 0
+// of the caller work-group after `prepare` ran on all of its work-items
+// (e.g. to build a descriptor list).  Non-blocking: returns 0 (GSYS_NOT_WAITED
+// outside the caller for producers) and the ticket through *out.
+template <B b, class Prepare, class MakeArgs>
+__device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_t nr,
+                                      uint8_t extra_flags, Prepare prepare, MakeArgs make_args,
+                                      Ticket* out = nullptr) {
+  (void)Legal<G::Kernel, O::Relaxed>::ok;
+  __shared__ int s_caller;
+  __shared__ int64_t s_ret;
+  __shared__ unsigned long long s_t1;  // ticket + 1, 0 = none
+  const bool producer = role_of(nr) == Role::Producer;
+  const unsigned int nwg = gridDim.x * gridDim.y * gridDim.z;
+  if (producer) fence_release_sys();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int caller;
+    if (producer) {
+      caller = __hip_atomic_fetch_add(&ks->arrived, 1u, __ATOMIC_ACQ_REL,
+                                      __HIP_MEMORY_SCOPE_AGENT) == nwg - 1;
+    } else {
+      unsigned int exp = 0;
+      caller = __hip_atomic_compare_exchange_strong(&ks->elect, &exp, 1u, __ATOMIC_ACQ_REL,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_caller = caller;
+    s_t1 = 0;
+    s_ret = GSYS_NOT_WAITED;
+  }
+  __syncthreads();
+  const bool caller = s_caller != 0;
+  if (caller) {
+    prepare();
+    fence_release_sys();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Args6 a = make_args();
+      uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int err = wait_ring_space(c, t, 1);
+      if (err) {
+        s_ret = err;
+      } else {
+        const uint8_t fl = (uint8_t)((b == B::Blocking ? GSYS_F_BLOCKING : 0u) |
+                                     (producer ? GSYS_F_PRODUCER : 0u) | extra_flags |
+                                     (GSYS_GRAN_KERNEL << GSYS_F_GRAN_SHIFT));
+        publish(c, t, nr, fl, 1, 0, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+        s_t1 = t + 1;
+        s_ret = 0;
+      }
+      if (!producer)
+        __hip_atomic_store(&ks->ticket, s_t1 ? s_t1 : KS_FAILED, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  } else if (!producer) {
+    // learn the caller's ticket; the caller is resident because it arrived first
+    if (threadIdx.x == 0) {
+      Waiter w(c);
+      unsigned long long v;
+      for (;;) {
+        v = __hip_atomic_load(&ks->ticket, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v) break;
+        if (!w.pause()) { v = KS_FAILED; break; }
+      }
+      if (v == KS_FAILED) {
+        s_ret = GSYS_ETIMEDOUT_RET;
+      } else {
+        s_t1 = v;
+        s_ret = 0;
+      }
+    }
+    __syncthreads();
+  }
+  const unsigned long long t1 = s_t1;
+  if (out) *out = t1 ? Ticket{t1 - 1, 0, 1} : Ticket{0, 0, 0};
+  if constexpr (b == B::NonBlocking) {
+    return s_ret;
+  } else {
+    if (producer) {
+      // weak-block: only the caller's wavefront waits
+      int64_t ret = GSYS_NOT_WAITED;
+      if (caller && threadIdx.x < 64) {
+        ret = s_ret;
+        if (t1) {
+          int e = 0;
+          if (threadIdx.x == 0) e = poll_group(c, t1 - 1, 1);
+          e = __builtin_amdgcn_readlane(e, 0);
+          fence_acquire_sys();
+          ret = e ? (int64_t)e : read_ret(c, t1 - 1);
+          if (e == 0 && threadIdx.x == 0) free_slot(c, t1 - 1);
+        }
+      }
+      return ret;
+    }
+    // consumer: every work-group waits for the result
+    __syncthreads();
+    if (threadIdx.x == 0 && t1) {
+      int e = poll_group(c, t1 - 1, 1);
+      fence_acquire_sys();
+      int64_t r = e ? (int64_t)e : read_ret(c, t1 - 1);
+      if (caller && e == 0) free_slot(c, t1 - 1);
+      s_ret = r;
+    }
+    __syncthreads();
+    fence_acquire_sys();
+    return s_ret;
+  }
+}
+
+// Wait for a non-blocking kernel call from every work-group (consumer side).
+__device__ inline int64_t wait_kernel(const gsys_dev_ctx& c, const Ticket& tk) {
+  __shared__ int64_t s_ret;
+  if (threadIdx.x == 0) {
+    int64_t r = GSYS_NOT_WAITED;
+    if (tk.n) {
+      int e = poll_group(c, tk.t, 1);
+      fence_acquire_sys();
+      r = e ? (int64_t)e : read_ret(c, tk.t);
+    }
+    s_ret = r;
+  }
+  __syncthreads();
+  fence_acquire_sys();
+  return s_ret;
+}
+
+}  // namespace gsys

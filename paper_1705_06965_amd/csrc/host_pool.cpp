@@ -1,0 +1,662 @@
+// Host service pool (see host_pool.hpp).
+#include "host_pool.hpp"
+
+#include <errno.h>
+#include <fcntl.h>
+#include <netinet/in.h>
+#include <pthread.h>
+#include <sched.h>
+#include <string.h>
+#include <sys/mman.h>
+#include <sys/socket.h>
+#include <sys/stat.h>
+#include <sys/syscall.h>
+#include <time.h>
+#include <unistd.h>
+#include <immintrin.h>
+
+#include <algorithm>
+
+static_assert(sizeof(gsys_slot) == 64, "slot must be one 64-byte line");
+static_assert(sizeof(gsys_comp) == 16, "completion record is 16 bytes");
+static_assert(sizeof(gsys_iodesc) == 16, "io descriptor is 16 bytes");
+static_assert(sizeof(gsys_netdesc) == 32, "net descriptor is 32 bytes");
+static_assert(GSYS_NR_READ == SYS_read && GSYS_NR_WRITE == SYS_write &&
+                  GSYS_NR_MMAP == SYS_mmap && GSYS_NR_MUNMAP == SYS_munmap &&
+                  GSYS_NR_PREAD64 == SYS_pread64 && GSYS_NR_PWRITE64 == SYS_pwrite64 &&
+                  GSYS_NR_MADVISE == SYS_madvise && GSYS_NR_SENDTO == SYS_sendto &&
+                  GSYS_NR_RECVFROM == SYS_recvfrom,
+              "call numbers are the host's system-call numbers");
+
+namespace gsys_host {
+
+namespace {
+
+constexpr uint8_t kPermMask = 0x7;
+constexpr uint8_t kRegular = 0x80;  // fd refers to a regular file (transfers may merge)
+
+inline uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+inline uint64_t ld_acq(const uint64_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+inline void st_rel(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELEASE); }
+
+inline int hist_bucket(uint64_t n) {
+  if (n <= 1) return 0;
+  if (n == 2) return 1;
+  if (n <= 4) return 2;
+  if (n <= 8) return 3;
+  if (n <= 16) return 4;
+  if (n <= 32) return 5;
+  if (n <= 64) return 6;
+  return 7;
+}
+
+inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  return x;
+}
+
+bool loopback_v4(const uint8_t* a, uint64_t len) {
+  if (len < sizeof(sockaddr_in)) return false;
+  sockaddr_in sa;
+  memcpy(&sa, a, sizeof sa);
+  return sa.sin_family == AF_INET && ntohl(sa.sin_addr.s_addr) == INADDR_LOOPBACK;
+}
+
+}  // namespace
+
+Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* retired_lo,
+           const gsys_config& cfg)
+    : ring_(ring), comp_(comp), D_(D), C_(C), retired_lo_(retired_lo), fdperm_(65536) {
+  long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
+  if (ncpu < 1) ncpu = 1;
+  P_ = cfg.service_threads ? (int)cfg.service_threads : (int)std::max(1L, ncpu - 1);
+  stripe_ = cfg.stripe ? cfg.stripe : 8;
+  K_ = cfg.coalesce_max ? cfg.coalesce_max : 1;
+  T_ns_ = cfg.coalesce_window_ns;
+  if (K_ > 1 && stripe_ < K_) stripe_ = K_;
+  if (stripe_ > 64) stripe_ = 64;
+  if (K_ > 64) K_ = 64;
+  first_cpu_ = cfg.first_cpu;
+  pin_ = !(cfg.flags & GSYS_CFG_NO_PIN);
+  ledger_on_ = (cfg.flags & GSYS_CFG_LEDGER) != 0;
+  ledger_cap_ = cfg.ledger_capacity ? cfg.ledger_capacity : (1u << 20);
+  for (auto& h : st_bhist_) h.store(0);
+  for (auto& h : st_ehist_) h.store(0);
+  for (auto& p : fdperm_) p.store(0);
+}
+
+Pool::~Pool() { stop_and_join(); }
+
+void Pool::start() {
+  stop_.store(false);
+  for (int i = 0; i < P_; ++i) threads_.emplace_back([this, i] { poller(i); });
+}
+
+void Pool::stop_and_join() {
+  stop_.store(true);
+  for (auto& t : threads_)
+    if (t.joinable()) t.join();
+  threads_.clear();
+}
+
+int Pool::allow_fd(int fd, uint32_t perms) {
+  if (fd < 0 || fd >= (int)fdperm_.size()) return -EBADF;
+  uint8_t v = (uint8_t)(perms & kPermMask);
+  if (v) {
+    struct stat st;
+    if (fstat(fd, &st) != 0) return -errno;
+    if (S_ISREG(st.st_mode)) v |= kRegular;
+  }
+  fdperm_[fd].store(v, std::memory_order_release);
+  return 0;
+}
+
+bool Pool::fd_ok(int64_t fd, uint32_t need) const {
+  if (fd < 0 || fd >= (int64_t)fdperm_.size()) return false;
+  uint8_t p = fdperm_[fd].load(std::memory_order_acquire);
+  return (p & need) == need && (p & kPermMask) != 0;
+}
+
+int Pool::add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id) {
+  if (!bytes || (kind != GSYS_BUF_HOST && kind != GSYS_BUF_DEVICE)) return -EINVAL;
+  if (kind == GSYS_BUF_HOST && !host) return -EINVAL;
+  std::lock_guard<std::mutex> g(bufmu_);
+  int n = nbufs_.load();
+  if (n >= kMaxBufs) return -ENOSPC;
+  for (int i = 0; i < n; ++i) {
+    const Buf& b = bufs_[i];
+    if (dev < b.dev + b.bytes && b.dev < dev + bytes) return -EEXIST;
+  }
+  bufgen_.fetch_add(1, std::memory_order_acq_rel);  // odd: writers active
+  bufs_[n] = Buf{dev, host, bytes, kind, next_id_};
+  nbufs_.store(n + 1, std::memory_order_release);
+  bufgen_.fetch_add(1, std::memory_order_acq_rel);
+  if (id) *id = next_id_;
+  ++next_id_;
+  return 0;
+}
+
+int Pool::remove_buffer(uint32_t id) {
+  std::lock_guard<std::mutex> g(bufmu_);
+  int n = nbufs_.load();
+  for (int i = 0; i < n; ++i) {
+    if (bufs_[i].id == id) {
+      bufgen_.fetch_add(1, std::memory_order_acq_rel);
+      bufs_[i] = bufs_[n - 1];
+      nbufs_.store(n - 1, std::memory_order_release);
+      bufgen_.fetch_add(1, std::memory_order_acq_rel);
+      return 0;
+    }
+  }
+  return -ENOENT;
+}
+
+// Host address of [dev, dev + len) if it lies inside one registered host
+// buffer (or inside the arena, whose device address is its host address).
+uint8_t* Pool::translate(uint64_t dev, uint64_t len, bool) {
+  if (len > (1ull << 40) || dev + len < dev) return nullptr;
+  if (arena_ && dev >= (uint64_t)arena_ && dev + len <= (uint64_t)arena_ + arena_bytes_)
+    return (uint8_t*)dev;
+  for (;;) {
+    uint64_t g1 = bufgen_.load(std::memory_order_acquire);
+    if (g1 & 1) {
+      _mm_pause();
+      continue;
+    }
+    uint8_t* r = nullptr;
+    int n = nbufs_.load(std::memory_order_acquire);
+    for (int i = 0; i < n; ++i) {
+      const Buf& b = bufs_[i];
+      if (dev >= b.dev && dev + len <= b.dev + b.bytes) {
+        r = b.kind == GSYS_BUF_HOST ? b.host + (dev - b.dev) : nullptr;
+        break;
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    if (bufgen_.load(std::memory_order_relaxed) == g1) return r;
+  }
+}
+
+void Pool::note_errno(int64_t ret) {
+  if (ret >= 0) return;
+  st_err_.fetch_add(1, std::memory_order_relaxed);
+  int b;
+  switch ((int)-ret) {
+    case EPERM: b = 0; break;
+    case EBADF: b = 1; break;
+    case EFAULT: b = 2; break;
+    case EINVAL: b = 3; break;
+    case EAGAIN: b = 4; break;
+    case ESHUTDOWN: b = 5; break;
+    case ETIMEDOUT: b = 6; break;
+    default: b = 7;
+  }
+  st_ehist_[b].fetch_add(1, std::memory_order_relaxed);
+}
+
+// Execute one single (non-list) request.
+int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
+  if (s.flags & GSYS_F_LIST) return exec_list(s, calls, merged);
+  const uint64_t* a = s.args;
+  int64_t r;
+  switch (s.nr) {
+    case GSYS_NR_PREAD64:
+    case GSYS_NR_READ: {
+      if (!fd_ok((int64_t)a[0], GSYS_FD_READ)) return -EBADF;
+      if (a[2] > (1ull << 31)) return -EINVAL;
+      uint8_t* h = translate(a[1], a[2], true);
+      if (!h) return -EFAULT;
+      ssize_t n = s.nr == GSYS_NR_PREAD64 ? pread((int)a[0], h, a[2], (off_t)a[3])
+                                          : read((int)a[0], h, a[2]);
+      ++*calls;
+      r = n < 0 ? -(int64_t)errno : (int64_t)n;
+      if (r > 0) st_in_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      return r;
+    }
+    case GSYS_NR_PWRITE64:
+    case GSYS_NR_WRITE: {
+      if (!fd_ok((int64_t)a[0], GSYS_FD_WRITE)) return -EBADF;
+      if (a[2] > (1ull << 31)) return -EINVAL;
+      uint8_t* h = translate(a[1], a[2], false);
+      if (!h) return -EFAULT;
+      ssize_t n = s.nr == GSYS_NR_PWRITE64 ? pwrite((int)a[0], h, a[2], (off_t)a[3])
+                                           : write((int)a[0], h, a[2]);
+      ++*calls;
+      r = n < 0 ? -(int64_t)errno : (int64_t)n;
+      if (r > 0) st_out_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      return r;
+    }
+    case GSYS_NR_SENDTO: {
+      if (!fd_ok((int64_t)a[0], GSYS_FD_SOCK)) return -EBADF;
+      if (a[3] & ~(uint64_t)MSG_DONTWAIT) return -EINVAL;
+      if (a[2] > 65507) return -EINVAL;
+      uint8_t* h = translate(a[1], a[2], false);
+      uint8_t* addr = translate(a[4], a[5], false);
+      if (!h || !addr) return -EFAULT;
+      if (!loopback_v4(addr, a[5])) return -EINVAL;
+      ssize_t n = sendto((int)a[0], h, a[2], (int)a[3] | MSG_DONTWAIT, (const sockaddr*)addr,
+                         (socklen_t)a[5]);
+      ++*calls;
+      r = n < 0 ? -(int64_t)errno : (int64_t)n;
+      if (r > 0) st_out_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      return r;
+    }
+    case GSYS_NR_RECVFROM: {
+      if (!fd_ok((int64_t)a[0], GSYS_FD_SOCK)) return -EBADF;
+      if (a[3] & ~(uint64_t)MSG_DONTWAIT) return -EINVAL;
+      if (a[2] > 65536) return -EINVAL;
+      uint8_t* h = translate(a[1], a[2], true);
+      if (!h) return -EFAULT;
+      sockaddr_in from;
+      socklen_t fl = sizeof from;
+      // A poller never blocks inside the kernel: recvfrom is always
+      // MSG_DONTWAIT and an empty socket answers -EAGAIN.
+      ssize_t n = recvfrom((int)a[0], h, a[2], MSG_DONTWAIT, (sockaddr*)&from, &fl);
+      ++*calls;
+      r = n < 0 ? -(int64_t)errno : (int64_t)n;
+      if (r >= 0 && a[4]) {
+        uint8_t* out = translate(a[4], sizeof from, true);
+        if (out) memcpy(out, &from, sizeof from);
+      }
+      if (r > 0) st_in_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      return r;
+    }
+    case GSYS_NR_MMAP: {
+      // anonymous private memory at a fixed address inside the arena
+      const uint64_t addr = a[0], len = a[1];
+      if (!arena_ || (addr & 4095) || !len || (len & 4095)) return -EINVAL;
+      if (addr < (uint64_t)arena_ || addr + len > (uint64_t)arena_ + arena_bytes_) return -EFAULT;
+      if (a[2] & ~(uint64_t)(PROT_READ | PROT_WRITE)) return -EINVAL;
+      if ((a[3] & ~(uint64_t)MAP_FIXED) != (uint64_t)(MAP_PRIVATE | MAP_ANONYMOUS)) return -EINVAL;
+      if ((int64_t)a[4] != -1 || a[5] != 0) return -EINVAL;
+      void* m = mmap((void*)addr, len, (int)a[2], MAP_PRIVATE | MAP_ANONYMOUS | MAP_FIXED, -1, 0);
+      ++*calls;
+      return m == MAP_FAILED ? -(int64_t)errno : (int64_t)(uint64_t)m;
+    }
+    case GSYS_NR_MUNMAP: {
+      // inside the arena an unmap returns the range to the reservation
+      const uint64_t addr = a[0], len = a[1];
+      if (!arena_ || (addr & 4095) || !len) return -EINVAL;
+      if (addr < (uint64_t)arena_ || addr + len > (uint64_t)arena_ + arena_bytes_) return -EFAULT;
+      void* m = mmap((void*)addr, (len + 4095) & ~4095ull, PROT_NONE,
+                     MAP_PRIVATE | MAP_ANONYMOUS | MAP_FIXED | MAP_NORESERVE, -1, 0);
+      ++*calls;
+      return m == MAP_FAILED ? -(int64_t)errno : 0;
+    }
+    case GSYS_NR_MADVISE: {
+      const uint64_t addr = a[0], len = a[1];
+      if (a[2] != (uint64_t)MADV_DONTNEED) return -EINVAL;
+      if (!arena_ || (addr & 4095)) return -EINVAL;
+      if (addr < (uint64_t)arena_ || addr + len > (uint64_t)arena_ + arena_bytes_) return -EFAULT;
+      int rc = madvise((void*)addr, len, MADV_DONTNEED);
+      ++*calls;
+      return rc ? -(int64_t)errno : 0;
+    }
+    default:
+      st_rej_.fetch_add(1, std::memory_order_relaxed);
+      return -EPERM;
+  }
+}
+
+// A descriptor-list request: the group's calls run in list order on this
+// thread.  File transfers adjacent both in the file and in memory are merged
+// into one call and the result is split back over the descriptors.
+int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
+  const uint64_t* a = s.args;
+  const int64_t fd = (int64_t)a[0];
+  const uint64_t count = a[2];
+  const uint64_t base = a[3];
+  if (count > (1ull << 24)) return -EINVAL;
+  int64_t first_err = 0;
+  uint64_t total = 0;
+  if (s.nr == GSYS_NR_PREAD64 || s.nr == GSYS_NR_PWRITE64) {
+    const bool rd = s.nr == GSYS_NR_PREAD64;
+    if (!fd_ok(fd, rd ? GSYS_FD_READ : GSYS_FD_WRITE)) return -EBADF;
+    gsys_iodesc* d = (gsys_iodesc*)translate(a[1], count * sizeof(gsys_iodesc), true);
+    if (!d && count) return -EFAULT;
+    const bool mergeable = (fdperm_[fd].load(std::memory_order_relaxed) & kRegular) != 0;
+    uint64_t i = 0;
+    while (i < count) {
+      const uint64_t off = d[i].off;
+      const uint64_t boff = d[i].buf_off;
+      int64_t len = d[i].len_ret;
+      uint64_t j = i + 1;
+      if (len >= 0 && mergeable) {
+        uint64_t run = (uint64_t)len;
+        while (j < count && d[j].len_ret >= 0 && d[j].off == off + run &&
+               (uint64_t)d[j].buf_off == boff + run && run + (uint64_t)d[j].len_ret <= (1ull << 30)) {
+          run += (uint64_t)d[j].len_ret;
+          ++j;
+        }
+        len = (int64_t)run;
+      }
+      int64_t r;
+      uint8_t* h = len >= 0 ? translate(base + boff, (uint64_t)len, rd) : nullptr;
+      if (len < 0) {
+        r = -EINVAL;
+      } else if (!h) {
+        r = -EFAULT;
+      } else {
+        ssize_t n = rd ? pread((int)fd, h, (size_t)len, (off_t)off)
+                       : pwrite((int)fd, h, (size_t)len, (off_t)off);
+        ++*calls;
+        r = n < 0 ? -(int64_t)errno : (int64_t)n;
+      }
+      if (j > i + 1) *merged += j - i - 1;
+      // split the result back over the merged descriptors
+      uint64_t prefix = 0;
+      for (uint64_t k = i; k < j; ++k) {
+        const int64_t lk = d[k].len_ret;
+        int64_t rk;
+        if (r < 0) {
+          rk = r;
+        } else {
+          const int64_t left = r - (int64_t)prefix;
+          rk = left <= 0 ? 0 : (left < lk ? left : lk);
+        }
+        prefix += (uint64_t)(lk > 0 ? lk : 0);
+        d[k].len_ret = (int32_t)rk;
+        if (rk < 0 && !first_err) first_err = rk;
+        if (rk > 0) total += (uint64_t)rk;
+        note_errno(rk);
+      }
+      i = j;
+    }
+    if (rd) st_in_.fetch_add(total, std::memory_order_relaxed);
+    else st_out_.fetch_add(total, std::memory_order_relaxed);
+  } else if (s.nr == GSYS_NR_RECVFROM || s.nr == GSYS_NR_SENDTO) {
+    if (!fd_ok(fd, GSYS_FD_SOCK)) return -EBADF;
+    if (a[4] & ~(uint64_t)MSG_DONTWAIT) return -EINVAL;
+    gsys_netdesc* d = (gsys_netdesc*)translate(a[1], count * sizeof(gsys_netdesc), true);
+    if (!d && count) return -EFAULT;
+    bool drained = false;
+    for (uint64_t i = 0; i < count; ++i) {
+      const int32_t len = d[i].len_ret;
+      int64_t r;
+      uint8_t* h = len >= 0 ? translate(base + d[i].buf_off, (uint64_t)len, true) : nullptr;
+      if (len < 0 || len > 65507) {
+        r = -EINVAL;
+      } else if (!h) {
+        r = -EFAULT;
+      } else if (s.nr == GSYS_NR_RECVFROM) {
+        if (drained) {
+          // the socket answered -EAGAIN to this list already
+          r = -EAGAIN;
+        } else {
+          sockaddr_in from;
+          socklen_t fl = sizeof from;
+          ssize_t n = recvfrom((int)fd, h, (size_t)len, MSG_DONTWAIT, (sockaddr*)&from, &fl);
+          ++*calls;
+          r = n < 0 ? -(int64_t)errno : (int64_t)n;
+          if (n >= 0) {
+            memcpy(d[i].addr, &from, sizeof from);
+            d[i].addr_len = fl;
+          } else if (r == -EAGAIN) {
+            drained = true;
+          }
+        }
+      } else {
+        if (!loopback_v4(d[i].addr, d[i].addr_len)) {
+          r = -EINVAL;
+        } else {
+          ssize_t n = sendto((int)fd, h, (size_t)len, (int)a[4] | MSG_DONTWAIT,
+                             (const sockaddr*)d[i].addr, (socklen_t)d[i].addr_len);
+          ++*calls;
+          r = n < 0 ? -(int64_t)errno : (int64_t)n;
+        }
+      }
+      d[i].len_ret = (int32_t)r;
+      if (r < 0 && r != -EAGAIN && !first_err) first_err = r;
+      if (r > 0) total += (uint64_t)r;
+      if (r != -EAGAIN) note_errno(r);
+    }
+    if (s.nr == GSYS_NR_RECVFROM) st_in_.fetch_add(total, std::memory_order_relaxed);
+    else st_out_.fetch_add(total, std::memory_order_relaxed);
+  } else {
+    st_rej_.fetch_add(1, std::memory_order_relaxed);
+    return -EPERM;
+  }
+  return first_err ? first_err : (int64_t)total;
+}
+
+// Post the result (section 5): the return value goes to the slot's argument
+// field and to the ticket's completion record; a blocking slot becomes
+// FINISHED (the GPU frees it), a non-blocking one becomes FREE for the next
+// lap.  Then the claim group's completion count goes up by one.
+void Pool::complete(uint64_t t, gsys_slot* s, int64_t ret) {
+  const uint8_t flags = s->flags;
+  const uint64_t head = t - s->grp_off;
+  gsys_comp* c = &comp_[t & (C_ - 1)];
+  __atomic_store_n(&c->ret, ret, __ATOMIC_RELAXED);
+  if (flags & GSYS_F_BLOCKING) {
+    __atomic_store_n((int64_t*)&s->args[0], ret, __ATOMIC_RELAXED);
+    st_rel(&s->ctl, GSYS_CTL(t, GSYS_ST_FINISHED));
+  } else {
+    st_rel(&s->ctl, GSYS_CTL(t + D_, GSYS_ST_FREE));
+  }
+  uint64_t* stp = &comp_[head & (C_ - 1)].stamp;
+  uint64_t v = __atomic_load_n(stp, __ATOMIC_ACQUIRE);
+  for (;;) {
+    const uint64_t vh = v >> 8;
+    if (vh > head) break;  // lapped by a later group (the waiter reports -EOVERFLOW)
+    const uint64_t nv = vh == head ? v + 1 : GSYS_STAMP(head, 1);
+    if (__atomic_compare_exchange_n(stp, &v, nv, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) break;
+  }
+}
+
+void Pool::serve_bundle(Req* rq, int n) {
+  const uint64_t t0 = now_ns();
+  uint64_t calls = 0, merged = 0;
+  int i = 0;
+  while (i < n) {
+    gsys_slot& s = *rq[i].s;
+    // Coalesced bundle: fold single pread/pwrite requests that continue the
+    // previous one in the file and in memory into one call.
+    int j = i + 1;
+    if (n > 1 && !(s.flags & GSYS_F_LIST) &&
+        (s.nr == GSYS_NR_PREAD64 || s.nr == GSYS_NR_PWRITE64)) {
+      uint64_t run = s.args[2];
+      while (j < n) {
+        const gsys_slot& u = *rq[j].s;
+        if ((u.flags & GSYS_F_LIST) || u.nr != s.nr || u.args[0] != s.args[0] ||
+            u.args[1] != s.args[1] + run || u.args[3] != s.args[3] + run ||
+            run + u.args[2] > (1ull << 30))
+          break;
+        run += u.args[2];
+        ++j;
+      }
+      const bool regular =
+          (int64_t)s.args[0] >= 0 && (int64_t)s.args[0] < (int64_t)fdperm_.size() &&
+          (fdperm_[s.args[0]].load(std::memory_order_relaxed) & kRegular);
+      if (j > i + 1 && regular) {
+        gsys_slot big = s;
+        big.args[2] = run;
+        int64_t r = execute(big, &calls, &merged);
+        merged += (uint64_t)(j - i - 1);
+        uint64_t prefix = 0;
+        for (int k = i; k < j; ++k) {
+          const int64_t lk = (int64_t)rq[k].s->args[2];
+          int64_t rk = r < 0 ? r : std::max<int64_t>(0, std::min<int64_t>(lk, r - (int64_t)prefix));
+          prefix += (uint64_t)lk;
+          note_errno(rk);
+          if (ledger_on_) {
+            std::lock_guard<std::mutex> g(ledmu_);
+            if (ledger_.size() < ledger_cap_)
+              ledger_.push_back({rq[k].t, rq[k].s->nr, (uint64_t)rk,
+                                 mix64(rq[k].s->args[0] ^ mix64(rq[k].s->args[1] ^ mix64(rq[k].s->args[3])))});
+          }
+          complete(rq[k].t, rq[k].s, rk);
+        }
+        i = j;
+        continue;
+      }
+      j = i + 1;
+    }
+    int64_t r = execute(s, &calls, &merged);
+    if (!(s.flags & GSYS_F_LIST)) note_errno(r);
+    if (ledger_on_) {
+      std::lock_guard<std::mutex> g(ledmu_);
+      if (ledger_.size() < ledger_cap_)
+        ledger_.push_back({rq[i].t, s.nr, (uint64_t)r,
+                           mix64(s.args[0] ^ mix64(s.args[1] ^ mix64(s.args[3])))});
+    }
+    complete(rq[i].t, rq[i].s, r);
+    ++i;
+  }
+  st_requests_.fetch_add((uint64_t)n, std::memory_order_relaxed);
+  st_calls_.fetch_add(calls, std::memory_order_relaxed);
+  st_merged_.fetch_add(merged, std::memory_order_relaxed);
+  st_bundles_.fetch_add(1, std::memory_order_relaxed);
+  st_bhist_[hist_bucket((uint64_t)n)].fetch_add(1, std::memory_order_relaxed);
+  st_ns_.fetch_add(now_ns() - t0, std::memory_order_relaxed);
+  serviced_.fetch_add((uint64_t)n, std::memory_order_acq_rel);
+}
+
+// Advance the retire watermark over slots freed for their next lap.
+void Pool::retire_scan() {
+  if (retire_busy_.test_and_set(std::memory_order_acquire)) return;
+  uint64_t lo = __atomic_load_n(retired_lo_, __ATOMIC_RELAXED);
+  const uint64_t lo0 = lo;
+  for (int k = 0; k < 4096; ++k) {
+    const uint64_t c = ld_acq(&ring_[lo & (D_ - 1)].ctl);
+    if (c != GSYS_CTL(lo + D_, GSYS_ST_FREE)) break;
+    ++lo;
+  }
+  if (lo != lo0) st_rel(retired_lo_, lo);
+  retire_busy_.clear(std::memory_order_release);
+}
+
+void Pool::poller(int idx) {
+  if (pin_) {
+    long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
+    int first = first_cpu_ >= 0 ? first_cpu_ : 1;
+    cpu_set_t set;
+    CPU_ZERO(&set);
+    CPU_SET((int)((first + idx) % (ncpu > 0 ? ncpu : 1)), &set);
+    pthread_setaffinity_np(pthread_self(), sizeof set, &set);
+  }
+  const uint32_t S = stripe_;
+  const uint64_t full = S >= 64 ? ~0ull : ((1ull << S) - 1);
+  std::vector<Req> rq(S);
+  uint64_t s = (uint64_t)idx;
+  uint64_t done = 0;
+  uint64_t idle = 0;
+  while (!stop_.load(std::memory_order_relaxed)) {
+    int n = 0;
+    auto scan = [&](void) {
+      const uint64_t t0 = s * S;
+      for (uint32_t i = 0; i < S && n < (int)S; ++i) {
+        if ((done >> i) & 1) continue;
+        const uint64_t t = t0 + i;
+        gsys_slot* sl = &ring_[t & (D_ - 1)];
+        uint64_t c = ld_acq(&sl->ctl);
+        if (c != GSYS_CTL(t, GSYS_ST_READY)) continue;
+        if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, GSYS_ST_PROCESSING), false,
+                                        __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+          rq[n++] = Req{t, sl};
+          done |= 1ull << i;
+        }
+      }
+    };
+    scan();
+    if (n && K_ > 1 && done != full && (uint32_t)n < K_ && T_ns_) {
+      // coalescing window (section 5): wait for more requests to bundle
+      const uint64_t deadline = now_ns() + T_ns_;
+      while ((uint32_t)n < K_ && done != full && now_ns() < deadline) {
+        _mm_pause();
+        scan();
+      }
+    }
+    if (n) {
+      if (K_ > 1) {
+        // requests in ticket order; bundles of at most K
+        std::sort(rq.begin(), rq.begin() + n, [](const Req& x, const Req& y) { return x.t < y.t; });
+        for (int i = 0; i < n; i += (int)K_) serve_bundle(&rq[i], std::min<int>((int)K_, n - i));
+      } else {
+        for (int i = 0; i < n; ++i) serve_bundle(&rq[i], 1);
+      }
+      idle = 0;
+    }
+    if (done == full) {
+      s += (uint64_t)P_;
+      done = 0;
+      continue;
+    }
+    if (!n) {
+      ++idle;
+      st_idle_.fetch_add(1, std::memory_order_relaxed);
+      if ((idle & 63) == 0) retire_scan();
+      if (idle < 20000) {
+        _mm_pause();
+      } else {
+        timespec ts{0, 20000};
+        nanosleep(&ts, nullptr);
+      }
+    }
+  }
+}
+
+uint64_t Pool::poison_outstanding(uint64_t claimed) {
+  // runs after the pollers stopped: every request still READY (or taken
+  // but never completed) is answered with -ESHUTDOWN so that GPU waiters
+  // return instead of waiting for the watchdog
+  uint64_t lo = __atomic_load_n(retired_lo_, __ATOMIC_RELAXED);
+  uint64_t n = 0;
+  for (uint64_t t = lo; t < claimed; ++t) {
+    gsys_slot* sl = &ring_[t & (D_ - 1)];
+    uint64_t c = ld_acq(&sl->ctl);
+    if (c == GSYS_CTL(t, GSYS_ST_READY) || c == GSYS_CTL(t, GSYS_ST_PROCESSING)) {
+      complete(t, sl, -ESHUTDOWN);
+      st_ehist_[5].fetch_add(1, std::memory_order_relaxed);
+      ++n;
+    }
+  }
+  serviced_.fetch_add(n, std::memory_order_acq_rel);
+  return n;
+}
+
+void Pool::stats(gsys_stats* o, int reset) {
+  auto rd = [reset](std::atomic<uint64_t>& a) { return reset ? a.exchange(0) : a.load(); };
+  memset(o, 0, sizeof *o);
+  o->requests = rd(st_requests_);
+  o->host_calls = rd(st_calls_);
+  o->bytes_in = rd(st_in_);
+  o->bytes_out = rd(st_out_);
+  o->errors = rd(st_err_);
+  o->rejected = rd(st_rej_);
+  o->bundles = rd(st_bundles_);
+  o->merged = rd(st_merged_);
+  o->idle_polls = rd(st_idle_);
+  o->service_ns = rd(st_ns_);
+  for (int i = 0; i < 8; ++i) {
+    o->bundle_hist[i] = rd(st_bhist_[i]);
+    o->errno_hist[i] = rd(st_ehist_[i]);
+  }
+  o->retired_lo = __atomic_load_n(retired_lo_, __ATOMIC_ACQUIRE);
+}
+
+int64_t Pool::ledger(uint64_t* out, uint64_t max, int reset) {
+  std::lock_guard<std::mutex> g(ledmu_);
+  uint64_t n = std::min<uint64_t>(max, ledger_.size());
+  if (out) {
+    std::vector<LedgerRec> v(ledger_.begin(), ledger_.begin() + n);
+    std::sort(v.begin(), v.end(), [](const LedgerRec& x, const LedgerRec& y) { return x.ticket < y.ticket; });
+    for (uint64_t i = 0; i < n; ++i) {
+      out[4 * i] = v[i].ticket;
+      out[4 * i + 1] = v[i].nr;
+      out[4 * i + 2] = v[i].ret;
+      out[4 * i + 3] = v[i].digest;
+    }
+  }
+  if (reset) ledger_.clear();
+  return (int64_t)n;
+}
+
+}  // namespace gsys_host

@@ -1,0 +1,126 @@
+// Host service pool: the CPU side that executes GPU-issued system calls.
+//
+// The paper dispatches each request from a GPU interrupt to a kernel
+// work-queue task that scans the requesting wavefront's slots, moves every
+// ready slot to processing, executes the call and writes the result back
+// (section 5).  Here P pinned user-space threads poll the slot ring instead
+// (section 3 treats interrupts versus polling as orthogonal; section 9 names
+// the user-mode service thread of earlier GPU file and network systems).
+// Tickets are dealt to pollers in stripes of `stripe` consecutive tickets,
+// stripe s going to poller s mod P, so a wavefront's 64 work-item calls are
+// serviced by several threads at once while a kernel-granularity call is one
+// unit of work for one thread (section 6, Fig. 5).
+//
+// Exactly-once: a poller takes a request only by compare-and-swap of the
+// slot's control word from READY to PROCESSING (section 5).
+//
+// Coalescing (section 4.2, section 5): with K > 1 a poller that finds a ready
+// request waits up to T ns for more ready requests of its stripe, up to K,
+// and executes them as one bundle, folding transfers that are adjacent both
+// in the file and in memory into one call.
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "gsys.h"
+
+namespace gsys_host {
+
+struct Buf {
+  uint64_t dev;
+  uint8_t* host;
+  uint64_t bytes;
+  uint32_t kind;
+  uint32_t id;
+};
+
+struct LedgerRec {
+  uint64_t ticket, nr, ret, digest;
+};
+
+class Pool {
+ public:
+  // Memory is owned by the caller (the C-ABI layer).
+  Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* retired_lo,
+       const gsys_config& cfg);
+  ~Pool();
+  void start();
+  void stop_and_join();
+
+  // whitelist
+  int allow_fd(int fd, uint32_t perms);
+  int add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id);
+  int remove_buffer(uint32_t id);
+  void set_arena(uint8_t* base, uint64_t bytes) { arena_ = base; arena_bytes_ = bytes; }
+
+  // servicing
+  uint64_t serviced() const { return serviced_.load(std::memory_order_acquire); }
+  // Complete every request still READY with -ESHUTDOWN (called after the
+  // pollers stopped).  `claimed` bounds the tickets examined.
+  uint64_t poison_outstanding(uint64_t claimed);
+  void retire_scan();
+
+  // true if [dev, dev + len) lies inside one registered host buffer
+  bool host_range(uint64_t dev, uint64_t len) { return translate(dev, len, false) != nullptr; }
+
+  void stats(gsys_stats* out, int reset);
+  int64_t ledger(uint64_t* out, uint64_t max, int reset);
+
+ private:
+  struct Req {
+    uint64_t t;
+    gsys_slot* s;
+  };
+  void poller(int idx);
+  void serve_bundle(Req* rq, int n);
+  int64_t execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
+  int64_t exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
+  void complete(uint64_t t, gsys_slot* s, int64_t ret);
+  uint8_t* translate(uint64_t dev, uint64_t len, bool need_host_write);
+  bool fd_ok(int64_t fd, uint32_t need) const;
+  void note_errno(int64_t ret);
+
+  gsys_slot* ring_;
+  gsys_comp* comp_;
+  uint64_t D_, C_;
+  uint64_t* retired_lo_;
+  int P_;
+  uint32_t stripe_, K_, T_ns_;
+  int first_cpu_;
+  bool pin_;
+  bool ledger_on_;
+  uint64_t ledger_cap_;
+
+  std::vector<std::thread> threads_;
+  std::atomic<bool> stop_{false};
+  std::atomic<uint64_t> serviced_{0};
+  std::atomic_flag retire_busy_ = ATOMIC_FLAG_INIT;
+
+  std::vector<std::atomic<uint8_t>> fdperm_;
+
+  // buffer table: seqlock-protected fixed array
+  static constexpr int kMaxBufs = 512;
+  Buf bufs_[kMaxBufs];
+  std::atomic<int> nbufs_{0};
+  std::atomic<uint64_t> bufgen_{0};
+  std::mutex bufmu_;
+  uint32_t next_id_ = 1;
+
+  uint8_t* arena_ = nullptr;
+  uint64_t arena_bytes_ = 0;
+
+  // stats
+  std::atomic<uint64_t> st_requests_{0}, st_calls_{0}, st_in_{0}, st_out_{0}, st_err_{0},
+      st_rej_{0}, st_bundles_{0}, st_merged_{0}, st_idle_{0}, st_ns_{0};
+  std::atomic<uint64_t> st_bhist_[8];
+  std::atomic<uint64_t> st_ehist_[8];
+
+  std::mutex ledmu_;
+  std::vector<LedgerRec> ledger_;
+};
+
+}  // namespace gsys_host

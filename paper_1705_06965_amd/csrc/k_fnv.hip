@@ -1,0 +1,313 @@
+// Per-item pread + FNV-1a-64 on gfx950: the pread microbenchmark of section 6
+// (Fig. 5) issued at work-item, work-group or kernel granularity, strong or
+// relaxed, blocking or non-blocking, and a persistent form that drains the
+// items in one launch with double-buffered non-blocking group calls.
+//
+// Data path: the host pool preads each item into pinned host staging; the GPU
+// reads the staging bytes once over the host link with coalesced 16-byte
+// loads (each group of 4 lanes fetches one item's next 64 bytes), transposes
+// them through LDS, and every lane runs the FNV-1a chain of its own item.
+// FNV-1a is a serial byte chain, so one lane per item is the parallel grain.
+#include "gsys_device.hpp"
+#include "gsys.h"
+#include "kernels.hpp"
+
+namespace gsys_k {
+
+using namespace gsys;
+
+// h * 0x100000001b3 mod 2^64 written as (h << 40) + h * 0x1b3.
+__device__ __forceinline__ uint64_t fnv_byte(uint64_t h, uint32_t byte) {
+  h ^= byte;
+  return (h << 40) + h * 0x1b3ull;
+}
+
+__device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint32_t w, int nbytes) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j < nbytes) h = fnv_byte(h, (w >> (8 * j)) & 0xffu);
+  return h;
+}
+
+__device__ __forceinline__ uint64_t fnv_word4(uint64_t h, uint32_t w) {
+  h = fnv_byte(h, w & 0xffu);
+  h = fnv_byte(h, (w >> 8) & 0xffu);
+  h = fnv_byte(h, (w >> 16) & 0xffu);
+  return fnv_byte(h, w >> 24);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr uint32_t kRowStride = 80;  // 64 data bytes + 16 pad: conflict-free 16-byte LDS reads
+constexpr uint32_t kTileBytes = 64 * kRowStride;
+
+// All 64 lanes of the wave call this.  Lane l hashes `nbytes` bytes of its
+// item at staging address `src`.  `tile` is this wave's 5 KiB LDS tile.
+__device__ uint64_t wave_fnv(uint64_t src, uint32_t nbytes, uint32_t item_bytes, uint8_t* tile) {
+  const uint32_t lane = lane_id();
+  const uint32_t col = lane & 3u;
+  uint64_t rsrc[4];
+  uint32_t rlen[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = k * 16 + (int)(lane >> 2);
+    rsrc[k] = shfl64(src, r);
+    rlen[k] = (uint32_t)__shfl((int)nbytes, r, 64);
+  }
+  uint32_t maxlen = nbytes;
+  for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, (uint32_t)__shfl_xor((int)maxlen, o, 64));
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (uint32_t off = 0; off < maxlen && off < item_bytes; off += 64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t r = (uint32_t)k * 16 + (lane >> 2);
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (off < rlen[k]) v = *reinterpret_cast<const uint4*>(rsrc[k] + off + col * 16);
+      *reinterpret_cast<uint4*>(tile + r * kRowStride + col * 16) = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint8_t* row = tile + lane * kRowStride;
+    if (off + 64 <= nbytes) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint4 w = *reinterpret_cast<const uint4*>(row + q * 16);
+        h = fnv_word4(h, w.x);
+        h = fnv_word4(h, w.y);
+        h = fnv_word4(h, w.z);
+        h = fnv_word4(h, w.w);
+      }
+    } else if (off < nbytes) {
+      const uint32_t left = nbytes - off;
+      for (uint32_t q = 0; q < 16 && q * 4 < left; ++q) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(row + q * 4);
+        const int nb = (int)min(4u, left - q * 4);
+        h = fnv_word(h, w, nb);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return h;
+}
+
+struct FnvArgs {
+  gsys_dev_ctx c;
+  const uint64_t* offsets;
+  uint64_t n_items;
+  uint64_t staging;
+  gsys_iodesc* lists;
+  uint64_t* out_fnv;
+  int64_t* out_ret;
+  KState* ks;
+  int32_t fd;
+  uint32_t item_bytes;
+};
+
+__device__ __forceinline__ void consume_item(const FnvArgs& A, uint64_t item, bool valid,
+                                             int64_t ret, uint8_t* lds) {
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nbytes =
+      (valid && ret > 0) ? (uint32_t)min<int64_t>(ret, (int64_t)A.item_bytes) : 0u;
+  const uint64_t src = A.staging + (valid ? item : 0) * (uint64_t)A.item_bytes;
+  const uint64_t h = wave_fnv(src, nbytes, A.item_bytes, lds + wave * kTileBytes);
+  if (valid) {
+    A.out_fnv[item] = h;
+    A.out_ret[item] = ret;
+  }
+}
+
+// Plain form: one launch, one item per work-item, the call made at the
+// granularity / ordering / blocking of the template.
+template <G g, O o, B b>
+__global__ void fnv4k_plain(FnvArgs A) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint64_t first = (uint64_t)blockIdx.x * blockDim.x;
+  const uint64_t item = first + threadIdx.x;
+  const bool valid = item < A.n_items;
+  int64_t ret = 0;
+  if constexpr (g == G::WorkItem) {
+    if (valid) {
+      Args6 a{{(uint64_t)(int64_t)A.fd, A.staging + item * A.item_bytes, A.item_bytes,
+               A.offsets[item], 0, 0}};
+      Ticket tk;
+      ret = call_wi<b>(A.c, GSYS_NR_PREAD64, a, &tk);
+      if constexpr (b == B::NonBlocking) ret = ret ? ret : wait_wi(A.c, tk);
+    }
+  } else if constexpr (g == G::WorkGroup) {
+    gsys_iodesc* L = A.lists + first;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(blockDim.x, A.n_items - first);
+    if constexpr (o == O::Strong) {
+      // every work-item contributes its own descriptor; the barrier before
+      // the call makes all of them visible to the host
+      if (valid) {
+        gsys_iodesc d{A.offsets[item], threadIdx.x * A.item_bytes, (int32_t)A.item_bytes};
+        L[threadIdx.x] = d;
+      }
+    } else {
+      // relaxed consumer call: no barrier before it, so the designated
+      // caller's wavefront builds the list from the offset table itself
+      if (threadIdx.x < 64)
+        for (uint32_t i = threadIdx.x; i < cnt; i += 64)
+          L[i] = gsys_iodesc{A.offsets[first + i], i * A.item_bytes, (int32_t)A.item_bytes};
+    }
+    Args6 a{{(uint64_t)(int64_t)A.fd, (uint64_t)L, cnt, A.staging + first * A.item_bytes, 0, 0}};
+    Ticket tk{0, 0, 0};
+    int64_t r = call_wg<o, b>(A.c, GSYS_NR_PREAD64, GSYS_F_LIST, a, &tk);
+    if constexpr (b == B::NonBlocking) r = wait_wg(A.c, tk);
+    ret = valid ? (r < 0 ? r : (int64_t)__hip_atomic_load(&L[threadIdx.x].len_ret, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_SYSTEM))
+                : 0;
+  } else {
+    Ticket tk{0, 0, 0};
+    int64_t r = call_kernel<b>(
+        A.c, A.ks, GSYS_NR_PREAD64, GSYS_F_LIST,
+        [&]() {
+          for (uint64_t i = threadIdx.x; i < A.n_items; i += blockDim.x)
+            A.lists[i] = gsys_iodesc{A.offsets[i], (uint32_t)(i * A.item_bytes), (int32_t)A.item_bytes};
+        },
+        [&]() {
+          return Args6{{(uint64_t)(int64_t)A.fd, (uint64_t)A.lists, A.n_items, A.staging, 0, 0}};
+        },
+        &tk);
+    if constexpr (b == B::NonBlocking) r = r ? r : wait_kernel(A.c, tk);
+    ret = valid ? (r < 0 ? r : (int64_t)__hip_atomic_load(&A.lists[item].len_ret, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_SYSTEM))
+                : 0;
+  }
+  consume_item(A, item, valid, ret, lds);
+}
+
+// Persistent form: a co-resident grid; work-group w handles batches w,
+// w + grid, ...; each batch is one work-group call (relaxed consumer,
+// non-blocking) whose descriptor list the caller's wavefront builds.  The
+// call for the next batch is issued before waiting on the current one, so
+// host servicing overlaps the GPU's consumption.
+__device__ __forceinline__ Ticket issue_batch(const FnvArgs& A, uint64_t bt, uint32_t batch) {
+  const uint64_t first = bt * batch;
+  const uint32_t cnt = (uint32_t)min<uint64_t>(batch, A.n_items - first);
+  gsys_iodesc* L = A.lists + first;
+  if (threadIdx.x < 64)
+    for (uint32_t i = threadIdx.x; i < cnt; i += 64)
+      L[i] = gsys_iodesc{A.offsets[first + i], i * A.item_bytes, (int32_t)A.item_bytes};
+  Args6 a{{(uint64_t)(int64_t)A.fd, (uint64_t)L, cnt, A.staging + first * A.item_bytes, 0, 0}};
+  Ticket tk{0, 0, 0};
+  call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_PREAD64, GSYS_F_LIST, a, &tk);
+  return tk;
+}
+
+__global__ void fnv4k_persistent(FnvArgs A) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t batch = blockDim.x;
+  const uint64_t nb = (A.n_items + batch - 1) / batch;
+  uint64_t bt = blockIdx.x;
+  if (bt >= nb) return;
+  Ticket tk = issue_batch(A, bt, batch);
+  while (bt < nb) {
+    const uint64_t bn = bt + gridDim.x;
+    Ticket tkn{0, 0, 0};
+    if (bn < nb) tkn = issue_batch(A, bn, batch);
+    const int64_t r = wait_wg(A.c, tk);
+    const uint64_t item = bt * batch + threadIdx.x;
+    const bool valid = item < A.n_items;
+    const int64_t ret =
+        valid ? (r < 0 ? r : (int64_t)__hip_atomic_load(&A.lists[item].len_ret, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_SYSTEM))
+              : 0;
+    consume_item(A, item, valid, ret, lds);
+    bt = bn;
+    tk = tkn;
+  }
+}
+
+__global__ void zero_words(unsigned long long* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace gsys_k
+
+// ---------------------------------------------------------------- host side
+using namespace gsys_k;
+
+int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32_t item_bytes,
+               uint64_t staging, uint64_t lists, uint64_t out_fnv, uint64_t out_ret, uint32_t cell,
+               uint32_t form, uint32_t wg_size, void* stream) {
+  if (!ctx) return -EINVAL;
+  if (!n_items) return 0;
+  if (item_bytes == 0 || item_bytes % 64 || item_bytes > (1u << 20)) return -EINVAL;
+  if (!(wg_size == 64 || wg_size == 128 || wg_size == 256 || wg_size == 512 || wg_size == 1024))
+    return -EINVAL;
+  if (!offsets || !out_fnv || !out_ret) return -EINVAL;
+  if (n_items > (1ull << 32)) return -EINVAL;
+  const uint64_t stage_bytes = n_items * (uint64_t)item_bytes;
+  if (gsys_internal::check_host_range(ctx, staging, stage_bytes)) return -EFAULT;
+  if (gsys_internal::check_host_range(ctx, lists, n_items * sizeof(gsys_iodesc))) return -EFAULT;
+
+  FnvArgs A;
+  if (int e = gsys_device_ctx(ctx, &A.c)) return e;
+  A.offsets = (const uint64_t*)offsets;
+  A.n_items = n_items;
+  A.staging = staging;
+  A.lists = (gsys_iodesc*)lists;
+  A.out_fnv = (uint64_t*)out_fnv;
+  A.out_ret = (int64_t*)out_ret;
+  A.ks = (KState*)gsys_internal::kstate(ctx);
+  A.fd = fd;
+  A.item_bytes = item_bytes;
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t lds = (wg_size / 64) * kTileBytes;
+
+  if (form == GSYS_PERSISTENT || form == GSYS_GRAPH) {
+    const uint64_t nb = (n_items + wg_size - 1) / wg_size;
+    uint32_t grid = gsys_internal::resident_grid(ctx, (const void*)fnv4k_persistent, wg_size, lds);
+    if (grid == 0) return -ENODEV;
+    if ((uint64_t)grid > nb) grid = (uint32_t)nb;
+    const uint32_t req = gsys_internal::persistent_grid_override(ctx);
+    if (req && req < grid) grid = req;
+    void* args[] = {&A};
+    if (form == GSYS_GRAPH) {
+      const uint64_t key = gsys_internal::hash_words(
+          {0xF4Bull, (uint64_t)fd, offsets, n_items, item_bytes, staging, lists, out_fnv, out_ret,
+           wg_size, grid, (uint64_t)s});
+      return gsys_internal::launch_graph(ctx, key, (const void*)fnv4k_persistent, grid, wg_size, lds,
+                                         args, s);
+    }
+    return gsys_internal::launch(ctx, (const void*)fnv4k_persistent, grid, wg_size, lds, args, s);
+  }
+
+  const uint32_t gran = GSYS_CELL_GRAN(cell);
+  const bool strong = (cell & GSYS_CELL_STRONG) != 0;
+  const bool blocking = (cell & GSYS_CELL_BLOCKING) != 0;
+  const uint64_t grid64 = (n_items + wg_size - 1) / wg_size;
+  if (grid64 > 0x7fffffffull) return -EINVAL;
+  const uint32_t grid = (uint32_t)grid64;
+  const void* k = nullptr;
+  if (gran == GSYS_GRAN_WI) {
+    if (!strong) return -EINVAL;  // work-item calls are implicitly strong
+    k = blocking ? (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::Blocking>
+                 : (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::NonBlocking>;
+  } else if (gran == GSYS_GRAN_WG) {
+    if (strong)
+      k = blocking ? (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::Blocking>
+                   : (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::NonBlocking>;
+    else
+      k = blocking ? (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::Blocking>
+                   : (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::NonBlocking>;
+  } else if (gran == GSYS_GRAN_KERNEL) {
+    if (strong) return -EINVAL;  // kernel calls are relaxed only
+    if (stage_bytes > 0xffffffffull) return -EINVAL;  // descriptor offsets are 32-bit
+    k = blocking ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking>
+                 : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking>;
+    // fresh per-launch state for the kernel-granularity call site
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)A.ks,
+                       (uint32_t)(sizeof(KState) / 8));
+    if (hipGetLastError() != hipSuccess) return -ENODEV;
+  } else {
+    return -EINVAL;
+  }
+  void* args[] = {&A};
+  return gsys_internal::launch(ctx, k, grid, wg_size, lds, args, s);
+}

@@ -1,0 +1,30 @@
+// Internal helpers shared by the workload entry points (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <initializer_list>
+
+#include "gsys.h"
+
+namespace gsys_internal {
+
+// 0 if [dev, dev + bytes) lies inside one registered host buffer, else -EFAULT.
+int check_host_range(gsys_ctx* ctx, uint64_t dev, uint64_t bytes);
+// Device scratch for per-launch kernel-call state (256 bytes, zeroed by the
+// entry points before a launch that uses it).
+void* kstate(gsys_ctx* ctx);
+// Work-groups of `kernel` that fit on the device at once.
+uint32_t resident_grid(gsys_ctx* ctx, const void* kernel, uint32_t block, uint32_t lds);
+// A persistent grid size requested through GSYS_PERSISTENT_GRID (0 = none).
+uint32_t persistent_grid_override(gsys_ctx* ctx);
+uint64_t hash_words(std::initializer_list<uint64_t> w);
+int launch(gsys_ctx* ctx, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds,
+           void** args, hipStream_t s);
+// Capture the launch into a hipGraph the first time `key` is seen, replay it
+// afterwards.
+int launch_graph(gsys_ctx* ctx, uint64_t key, const void* kernel, uint32_t grid, uint32_t block,
+                 uint32_t lds, void** args, hipStream_t s);
+
+}  // namespace gsys_internal

@@ -1,0 +1,57 @@
+"""Driver of the per-item pread + FNV-1a workload (pread microbenchmark of
+section 6, Fig. 5).  Allocates the buffers the kernels need and launches them
+through the C ABI; device memory and streams come from PyTorch."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+from . import (Context, FD_READ, PLAIN, PERSISTENT, GRAPH, check, lib, cell_code,
+               _stream)
+
+
+class FnvRunner:
+    def __init__(self, ctx: Context, path: str, offsets: np.ndarray, item_bytes: int = 4096,
+                 wg_size: int = 256, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.path = path
+        self.fd = os.open(path, os.O_RDONLY)
+        ctx.allow_fd(self.fd, FD_READ)
+        self.n = int(len(offsets))
+        self.item_bytes = item_bytes
+        self.wg_size = wg_size
+        self.staging = ctx.host_alloc(max(1, self.n * item_bytes))
+        self.lists = ctx.host_alloc(max(16, self.n * 16))
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.offsets = torch.from_numpy(offs.view(np.int64)).to(device)
+        self.out_fnv = torch.zeros(max(1, self.n), dtype=torch.int64, device=device)
+        self.out_ret = torch.zeros(max(1, self.n), dtype=torch.int64, device=device)
+
+    def launch(self, cell: int = 0, form: int = PLAIN, stream=None):
+        return check(lib.gsys_fnv4k(self.ctx.h, self.fd, self.offsets.data_ptr(), self.n,
+                                    self.item_bytes, self.staging.dev, self.lists.dev,
+                                    self.out_fnv.data_ptr(), self.out_ret.data_ptr(), cell, form,
+                                    self.wg_size, _stream(stream)), "gsys_fnv4k")
+
+    def run(self, g="WI", o="strong", b="block", form=PLAIN, stream=None):
+        """Launch, wait for the GPU and drain the host pool."""
+        self.out_fnv.zero_()
+        self.out_ret.fill_(-12345)
+        self.launch(cell_code(g, o, b), form, stream)
+        self.torch.cuda.synchronize()
+        rc = self.ctx.wait(60_000_000_000)
+        if rc:
+            raise RuntimeError("drain failed: %d" % rc)
+        return self.result()
+
+    def result(self):
+        f = self.out_fnv.cpu().numpy().view(np.uint64)[:self.n].copy()
+        r = self.out_ret.cpu().numpy()[:self.n].copy()
+        return f, r
+
+    def close(self):
+        self.ctx.allow_fd(self.fd, 0)
+        os.close(self.fd)

@@ -1,0 +1,165 @@
+"""GPU parity of the per-item pread + FNV-1a workload against the oracle.
+
+Every cell of the granularity x ordering x blocking grid (8 legal cells,
+section 4.1) and the persistent / graph forms must give the oracle's vector
+bit for bit.  Calls go through the C ABI (gsys_fnv4k)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_06965_amd as g
+    ctx = g.Context(ring_slots=1 << 16, device_timeout_ns=60_000_000_000, flags=g.CFG_LEDGER,
+                    ledger_capacity=1 << 22)
+    yield g, ctx
+    assert ctx.shutdown() == 0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_tiny_plain_wi_strong_blocking(gs):
+    """1 work-group of 64 work-items, pread 4 KiB at 4096*i of a 256 KiB file."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = synth.random_file(1, 262144, name="c1_256k.bin")
+    offs = synth.tiny_offsets(64)
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, 4096)
+    r = FnvRunner(ctx, p, offs, 4096, wg_size=64)
+    say("tiny WI/strong/block")
+    f, ret = r.run("WI", "strong", "block")
+    assert (ret == 4096).all()
+    assert (f == want_fnv).all()
+    led = ctx.ledger(reset=True)
+    assert len(led) == 64 and len(set(led[:, 0].tolist())) == 64
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def mid(gs):
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    size = 64 << 20
+    p = synth.random_file(2, size, name="c2_64m.bin")
+    n = 16 * 256 + 37          # 16 full work-groups and a ragged tail
+    offs = synth.sweep_offsets(n, size // 4096)
+    want = oracle.pread_fnv(p, offs, 4096, threads=8)
+    r = FnvRunner(ctx, p, offs, 4096, wg_size=256)
+    yield r, want
+    r.close()
+
+
+@pytest.mark.parametrize("cell", [("WI", "strong", "block"), ("WI", "strong", "nonblock"),
+                                  ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
+                                  ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
+                                  ("K", "relaxed", "block"), ("K", "relaxed", "nonblock")])
+def test_all_legal_cells_match_oracle(gs, mid, cell):
+    g, ctx = gs
+    r, (want_fnv, want_ret) = mid
+    say("cell", cell, "n", r.n)
+    f, ret = r.run(*cell)
+    assert (ret == want_ret).all()
+    assert (f == want_fnv).all()
+    st = ctx.stats()
+    assert st["claimed"] == st["requests"] or st["claimed"] >= st["retired_lo"]
+
+
+@pytest.mark.parametrize("form", ["persistent", "graph"])
+def test_persistent_and_graph_forms(gs, mid, form):
+    g, ctx = gs
+    r, (want_fnv, want_ret) = mid
+    fm = g.PERSISTENT if form == "persistent" else g.GRAPH
+    for rep in range(2 if form == "graph" else 1):
+        say("form", form, "rep", rep)
+        f, ret = r.run(form=fm)
+        assert (ret == want_ret).all()
+        assert (f == want_fnv).all()
+
+
+def test_illegal_cells_rejected(gs, mid):
+    g, ctx = gs
+    r, _ = mid
+    with pytest.raises(g.GsysError):
+        r.launch(g.cell(g.GRAN_WI, False, True))       # work-item relaxed
+    with pytest.raises(g.GsysError):
+        r.launch(g.cell(g.GRAN_KERNEL, True, True))    # kernel strong
+
+
+def test_short_reads_and_small_items(gs, tmpdata):
+    """Reads that cross EOF return short counts; checksums cover what was read."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = os.path.join(tmpdata, "eof.bin")
+    data = np.random.default_rng(11).integers(0, 256, 100_000, dtype=np.uint8)
+    data.tofile(p)
+    offs = np.array([0, 99_990, 100_000, 200_000, 50_001, 96_000, 7, 99_999] * 40,
+                    dtype=np.uint64)
+    for item in (64, 4096):
+        want_fnv, want_ret = oracle.pread_fnv(p, offs, item)
+        r = FnvRunner(ctx, p, offs, item, wg_size=64)
+        for cell in (("WI", "strong", "block"), ("WG", "relaxed", "block"),
+                     ("K", "relaxed", "nonblock")):
+            say("eof", item, cell)
+            f, ret = r.run(*cell)
+            assert (ret == want_ret).all()
+            assert (f == want_fnv).all()
+        r.close()
+
+
+def test_single_item_and_revoked_fd(gs):
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = synth.random_file(1, 262144, name="c1_256k.bin")
+    offs = np.array([4096 * 5], dtype=np.uint64)
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, 4096)
+    r = FnvRunner(ctx, p, offs, 4096, wg_size=64)
+    f, ret = r.run("WG", "strong", "block")
+    assert ret[0] == 4096 and f[0] == want_fnv[0]
+    # revoked fd: every call completes with -EBADF, the checksum covers no bytes
+    ctx.allow_fd(r.fd, 0)
+    f, ret = r.run("WI", "strong", "block")
+    assert ret[0] == -9 and f[0] == 0xcbf29ce484222325
+    ctx.allow_fd(r.fd, g.FD_READ)
+    r.close()
+
+
+def test_full_sweep_sampled(gs):
+    """The microbenchmark sweep at its full size in the persistent form the
+    benchmark times: 262,144 preads of 4 KiB from a 1 GiB file; 4,096 sampled
+    items are recomputed by the oracle one by one, and the whole vector
+    matches the plain work-item form."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    size = 1 << 30
+    p = synth.random_file(2, size, name="c2_1g.bin")
+    n = 1024 * 256
+    offs = synth.sweep_offsets(n, size // 4096)
+    r = FnvRunner(ctx, p, offs, 4096, wg_size=256)
+    say("full persistent")
+    f, ret = r.run(form=g.PERSISTENT)
+    idx = np.random.default_rng(3).choice(n, 4096, replace=False)
+    want_fnv, want_ret = oracle.pread_fnv(p, offs[idx], 4096, threads=8)
+    assert (ret[idx] == want_ret).all() and (ret == 4096).all()
+    assert (f[idx] == want_fnv).all()
+    say("full WI plain")
+    f2, ret2 = r.run("WI", "strong", "block")
+    assert (f2 == f).all() and (ret2 == ret).all()
+    # equal offsets give equal checksums
+    _, first = np.unique(offs, return_index=True)
+    inv = np.unique(offs, return_inverse=True)[1]
+    assert (f == f[first][inv]).all()
+    r.close()

@@ -1,0 +1,278 @@
+"""Host service pool on the CPU, driven through the GPU's slot protocol by
+host threads (GSYS_CFG_NO_DEVICE contexts).  Results are checked against the
+oracle and against the file bytes; the ledger checks exactly-once service."""
+import ctypes as C
+import errno
+import os
+import socket
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1705_06965_amd as g
+
+
+@pytest.fixture(scope="module")
+def datafile(tmpdata):
+    os.environ["GSYS_DATA_DIR"] = tmpdata
+    p = synth.random_file(2, 4 << 20, name="pool_4m.bin")
+    return p
+
+
+def _ctx(**kw):
+    kw.setdefault("flags", 0)
+    kw["flags"] |= g.CFG_NO_DEVICE | g.CFG_NO_PIN | g.CFG_LEDGER
+    kw.setdefault("service_threads", 4)
+    return g.Context(**kw)
+
+
+def _run(ctx, fd, offs, threads, group, mode, item=4096):
+    n = len(offs)
+    buf = ctx.host_alloc(n * item)
+    lists = ctx.host_alloc(n * 16)
+    rets = np.zeros(n, dtype=np.int64)
+    offs = np.ascontiguousarray(offs, dtype=np.uint64)
+    rc = g.lib.gsys_test_emulate(ctx.h, threads, n // threads, group, mode, fd, buf.dev,
+                                 lists.dev, item, offs.ctypes.data, rets.ctypes.data,
+                                 20_000_000_000)
+    assert rc == 0, g.lib.gsys_strerror(rc)
+    return buf, rets
+
+
+@pytest.mark.parametrize("group,mode", [(64, g.EMU_BLOCKING), (8, 0), (1, g.EMU_BLOCKING),
+                                        (64, g.EMU_LIST | g.EMU_BLOCKING), (16, g.EMU_LIST)])
+def test_emulated_wavefronts_match_oracle(datafile, group, mode):
+    n_blocks = (4 << 20) // 4096
+    offs = synth.sweep_offsets(2048, n_blocks)
+    want_fnv, want_ret = oracle.pread_fnv(datafile, offs, 4096)
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=1024)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf, rets = _run(ctx, fd, offs, 8, group, mode)
+        assert (rets == want_ret).all()
+        data = buf.view(np.uint8).reshape(len(offs), 4096)
+        got = np.array([oracle.fnv1a64(data[i]) for i in range(len(offs))], dtype=np.uint64)
+        assert (got == want_fnv).all()
+        assert ctx.wait(5_000_000_000) == 0
+        led = ctx.ledger()
+        st = ctx.stats()
+        claimed = st["claimed"]
+        # exactly once: every claimed ticket serviced once, nothing else
+        assert len(led) == claimed
+        assert (np.sort(led[:, 0]) == np.arange(claimed, dtype=np.uint64)).all()
+        if mode & g.EMU_LIST:
+            assert claimed == len(offs) // group
+            assert st["host_calls"] <= len(offs)
+        else:
+            assert claimed == len(offs)
+            assert st["host_calls"] == len(offs)
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
+
+
+def test_tiny_ring_back_pressure_and_quiescence(datafile):
+    """D = 64 with 8 emulated wavefronts of 64: every claim wraps the ring."""
+    offs = synth.sweep_offsets(4096, 1024)
+    want_fnv, want_ret = oracle.pread_fnv(datafile, offs, 256)
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=64, service_threads=3)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf, rets = _run(ctx, fd, offs, 8, 64, g.EMU_BLOCKING, item=256)
+        assert (rets == 256).all()
+        data = buf.view(np.uint8).reshape(len(offs), 256)
+        for i in range(0, len(offs), 97):
+            assert oracle.fnv1a64(data[i]) == want_fnv[i]
+        assert ctx.wait(5_000_000_000) == 0
+        st = ctx.stats()
+        assert st["claimed"] == 4096 and st["retired_lo"] == 4096
+        ctl = np.zeros(64, dtype=np.uint64)
+        g.lib.gsys_test_ring_ctl(ctx.h, ctl.ctypes.data, 64)
+        # quiescent: every slot FREE for its next lap
+        t = np.arange(64, dtype=np.uint64) + np.uint64(4096)
+        assert (ctl == (t << np.uint64(3))).all()
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+
+
+def test_coalescing_merges_adjacent_reads(datafile):
+    offs = np.arange(1024, dtype=np.uint64) * np.uint64(4096)
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=4096, service_threads=2, coalesce_max=8, coalesce_window_ns=200_000)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf, rets = _run(ctx, fd, offs, 1, 64, g.EMU_BLOCKING)
+        assert (rets == 4096).all()
+        assert buf.view(np.uint8)[:4 << 20].tobytes() == open(datafile, "rb").read()
+        st = ctx.stats()
+        assert st["merged"] > 0
+        assert st["host_calls"] < 1024
+        assert sum(st["bundle_hist"][1:]) > 0
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+
+
+def test_short_reads_at_eof(tmpdata):
+    p = os.path.join(tmpdata, "short.bin")
+    data = np.random.default_rng(5).integers(0, 256, 10000, dtype=np.uint8).tobytes()
+    open(p, "wb").write(data)
+    offs = np.array([0, 4096, 8192, 9999, 10000, 12288, 5904, 5905], dtype=np.uint64)
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, 4096)
+    fd = os.open(p, os.O_RDONLY)
+    ctx = _ctx()
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        for mode in (g.EMU_BLOCKING, g.EMU_LIST | g.EMU_BLOCKING):
+            buf, rets = _run(ctx, fd, offs, 1, 8, mode)
+            assert rets.tolist() == want_ret.tolist()
+            d = buf.view(np.uint8).reshape(8, 4096)
+            for i in range(8):
+                assert oracle.fnv1a64(d[i, :max(0, rets[i])]) == want_fnv[i]
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+
+
+def _raw(ctx, nr, args, flags=g.F_BLOCKING):
+    a = np.array([int(x) & 0xFFFFFFFFFFFFFFFF for x in args] + [0] * (6 - len(args)),
+                 dtype=np.uint64)
+    r = np.zeros(1, dtype=np.int64)
+    rc = g.lib.gsys_test_raw_call(ctx.h, nr, flags, a.ctypes.data, r.ctypes.data, 5_000_000_000)
+    assert rc == 0
+    return int(r[0])
+
+
+def test_whitelist_rejects(datafile):
+    fd = os.open(datafile, os.O_RDONLY)
+    wfd = os.open(os.path.join(os.path.dirname(datafile), "w.bin"), os.O_RDWR | os.O_CREAT, 0o600)
+    ctx = _ctx(arena_bytes=8 << 20)
+    try:
+        buf = ctx.host_alloc(8192)
+        # fd not allowed yet
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 16, 0]) == -errno.EBADF
+        ctx.allow_fd(fd, g.FD_READ)
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 16, 0]) == 16
+        # read-only fd used for pwrite
+        assert _raw(ctx, g.NR_PWRITE64, [fd, buf.dev, 16, 0]) == -errno.EBADF
+        # range outside any registered buffer
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev + 8000, 4096, 0]) == -errno.EFAULT
+        assert _raw(ctx, g.NR_PREAD64, [fd, 0x1000, 16, 0]) == -errno.EFAULT
+        # calls outside the whitelist
+        for nr in (2, 3, 57, 59, 62):  # open, close, fork, execve, kill
+            assert _raw(ctx, nr, [0, 0, 0]) == -errno.EPERM
+        # madvise: only MADV_DONTNEED, only inside the arena
+        assert _raw(ctx, g.NR_MADVISE, [buf.dev & ~4095, 4096, 8]) == -errno.EINVAL  # MADV_FREE
+        assert _raw(ctx, g.NR_MADVISE, [buf.dev & ~4095, 4096, 4]) == -errno.EFAULT  # not arena
+        # revoke
+        ctx.allow_fd(fd, 0)
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 16, 0]) == -errno.EBADF
+        ctx.allow_fd(wfd, g.FD_WRITE)
+        buf.array[:16] = np.arange(16, dtype=np.uint8)
+        assert _raw(ctx, g.NR_PWRITE64, [wfd, buf.dev, 16, 100]) == 16
+        assert os.pread(wfd, 16, 100) == bytes(range(16))
+        st = ctx.stats()
+        assert st["rejected"] == 5
+        assert st["errno_hist"][0] == 5 and st["errno_hist"][1] >= 3
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+        os.close(wfd)
+
+
+def test_arena_mmap_madvise_munmap(datafile):
+    """mmap inside the arena, fill it with pread, read it back with pwrite,
+    madvise(MADV_DONTNEED) -> zero pages (madvise(2)), munmap."""
+    fd = os.open(datafile, os.O_RDONLY)
+    outp = os.path.join(os.path.dirname(datafile), "arena_out.bin")
+    wfd = os.open(outp, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+    ctx = _ctx(arena_bytes=16 << 20)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        ctx.allow_fd(wfd, g.FD_WRITE)
+        base = _raw(ctx, g.NR_MMAP, [0, 2 << 20, 3, 0x22, -1, 0])  # outside the arena
+        assert base == -errno.EFAULT
+        arena = ctx.device_ctx().arena
+        assert arena == ctx_arena_base(ctx)
+        # file-backed or shared mappings are refused
+        assert _raw(ctx, g.NR_MMAP, [arena, 2 << 20, 3, 0x01, fd, 0]) == -errno.EINVAL
+        addr = _raw(ctx, g.NR_MMAP, [arena, 2 << 20, 3, 0x22 | 0x10, -1, 0])
+        assert addr == arena
+        assert _raw(ctx, g.NR_PREAD64, [fd, addr, 2 << 20, 0]) == 2 << 20
+        assert _raw(ctx, g.NR_PWRITE64, [wfd, addr, 2 << 20, 0]) == 2 << 20
+        assert os.pread(wfd, 2 << 20, 0) == open(datafile, "rb").read(2 << 20)
+        assert _raw(ctx, g.NR_MADVISE, [addr, 2 << 20, 4], flags=0) == 0
+        assert _raw(ctx, g.NR_PWRITE64, [wfd, addr, 2 << 20, 0]) == 2 << 20
+        assert os.pread(wfd, 2 << 20, 0) == bytes(2 << 20)
+        assert _raw(ctx, g.NR_MUNMAP, [addr, 2 << 20]) == 0
+        # after munmap the range is reserved again: reading into it faults
+        assert _raw(ctx, g.NR_PREAD64, [fd, addr, 4096, 0]) == -errno.EFAULT
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+        os.close(wfd)
+
+
+def ctx_arena_base(ctx):
+    # the arena is the only 2 MiB-aligned PROT_NONE reservation of its size;
+    # read it from /proc/self/maps
+    want = ctx.cfg.arena_bytes
+    for line in open("/proc/self/maps"):
+        rng, perms = line.split()[:2]
+        lo, hi = (int(x, 16) for x in rng.split("-"))
+        if perms.startswith("---p") and hi - lo == want and lo % (2 << 20) == 0:
+            return lo
+    raise AssertionError("arena not found")
+
+
+def test_udp_loopback_sendto_recvfrom():
+    srv = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
+    srv.bind(("127.0.0.1", 0))
+    cli = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
+    cli.bind(("127.0.0.1", 0))
+    ctx = _ctx()
+    try:
+        ctx.allow_fd(srv.fileno(), g.FD_SOCK)
+        buf = ctx.host_alloc(4096)
+        # empty socket: recvfrom never blocks a poller
+        assert _raw(ctx, g.NR_RECVFROM, [srv.fileno(), buf.dev, 2048, 0, buf.dev + 2048, 0]) \
+            == -errno.EAGAIN
+        cli.sendto(b"hello gpu", srv.getsockname())
+        import time
+        time.sleep(0.05)
+        n = _raw(ctx, g.NR_RECVFROM, [srv.fileno(), buf.dev, 2048, 0, buf.dev + 2048, 0])
+        assert n == 9 and buf.array[:9].tobytes() == b"hello gpu"
+        # reply to the sender address that recvfrom filled in
+        buf.array[:5] = np.frombuffer(b"reply", dtype=np.uint8)
+        assert _raw(ctx, g.NR_SENDTO, [srv.fileno(), buf.dev, 5, 0, buf.dev + 2048, 16]) == 5
+        assert cli.recvfrom(64)[0] == b"reply"
+        # non-loopback destination refused
+        sa = buf.view(np.uint8, 16, 2048).copy()
+        sa[4:8] = [8, 8, 8, 8]
+        buf.array[3072:3088] = sa
+        assert _raw(ctx, g.NR_SENDTO, [srv.fileno(), buf.dev, 5, 0, buf.dev + 3072, 16]) \
+            == -errno.EINVAL
+    finally:
+        ctx.shutdown()
+        srv.close()
+        cli.close()
+
+
+def test_drain_times_out_on_unpublished_claims():
+    ctx = _ctx()
+    t = g.lib.gsys_test_claim_only(ctx.h, 3)
+    assert t == 0
+    assert ctx.wait(50_000_000) == -errno.ETIMEDOUT
+    assert ctx.shutdown(50_000_000) == -errno.ETIMEDOUT
+
+
+def test_exported_symbols_exist():
+    names = g.exported_symbols()
+    assert "gsys_init" in names and "gsys_fnv4k" in names and "gsys_test_emulate" in names
+    for n in names:
+        assert hasattr(g.lib, n), n
