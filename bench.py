@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark: GPU-issued pread calls serviced by the host pool on one MI355X.
+
+Workload (one step = one pass): the pread microbenchmark sweep of section 6 at
+its full size -- 1024 work-groups x 256 work-items, each work-item's item a
+4 KiB pread at a uniform random 4 KiB-aligned offset of a 1 GiB file of seeded
+random bytes on tmpfs, followed by the GPU's FNV-1a-64 of the bytes read.  The
+timed form is the persistent batched form (work-group list calls, relaxed,
+non-blocking, double-buffered, replayed from a hipGraph); the plain form
+(one launch, work-item granularity, strong, blocking) is timed beside it.
+
+Prints one JSON line.  value = host pread calls executed for GPU requests per
+second over the timed steps (inputs already resident: the file is in the page
+cache, offsets in HBM).  The roofline object covers the dominant kernel (the
+persistent kernel): algorithmic bytes are the 4 KiB payload of every call,
+which crosses the host link once, over the kernel's average duration measured
+with HIP events on its stream, against the PCIe 5.0 x16 per-direction link.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LINK_PEAK_GBPS = 63.0        # PCIe 5.0 x16: 32 GT/s x 16 lanes x 128/130 / 8, per direction
+N_WG, WG, ITEM = 1024, 256, 4096
+FILE_BYTES = 1 << 30
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="graph", choices=["graph", "persistent"])
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--service-threads", type=int, default=0)
+    ap.add_argument("--staging-mib", type=int, default=0,
+                    help="persistent form: staging ring size (0 = one slot per item)")
+    ap.add_argument("--only", default="", help="profiling aid: 'plain' or 'persistent' only")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(each GPU would run its own ring and host pool); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+
+    t_setup = time.time()
+    path = synth.random_file(2, FILE_BYTES, name="c2_1g.bin")
+    n = N_WG * WG
+    offs = synth.sweep_offsets(n, FILE_BYTES // ITEM)
+    # warm the page cache
+    with open(path, "rb") as f:
+        while f.read(64 << 20):
+            pass
+    print("setup %.1fs" % (time.time() - t_setup), file=sys.stderr, flush=True)
+
+    ctx = g.Context(ring_slots=1 << 18, service_threads=args.service_threads,
+                    device_timeout_ns=60_000_000_000)
+    r = FnvRunner(ctx, path, offs, ITEM, wg_size=WG, staging_bytes=args.staging_mib << 20)
+    rp = r if not args.staging_mib else FnvRunner(ctx, path, offs, ITEM, wg_size=WG)
+    stream = torch.cuda.current_stream()
+    form = g.GRAPH if args.form == "graph" else g.PERSISTENT
+
+    def step(cell, fm, ev=None):
+        runner = r if fm != g.PLAIN else rp
+        if ev:
+            ev[0].record(stream)
+        runner.launch(cell, fm, stream)
+        if ev:
+            ev[1].record(stream)
+        torch.cuda.synchronize()
+        rc = ctx.wait(60_000_000_000)
+        if rc:
+            raise RuntimeError("drain failed %d" % rc)
+
+    def timed(cell, fm, steps, warmup):
+        for _ in range(warmup):
+            step(cell, fm)
+        torch.cuda.synchronize()
+        ctx.stats(reset=True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        wall = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s0 = time.perf_counter()
+            step(cell, fm, evs[i])
+            wall.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        st = ctx.stats()
+        return total, wall, kern_ms, st
+
+    out = {}
+    persistent_cell = 0
+    if args.only != "plain":
+        total, wall, kern_ms, st = timed(persistent_cell, form, args.steps, args.warmup)
+        f, ret = r.result()
+        if not (ret == ITEM).all():
+            raise RuntimeError("persistent form: unexpected return values")
+        out["persistent"] = (total, wall, kern_ms, st)
+        print("persistent: %.2f ms/step, kernel %.2f ms, host calls %d" %
+              (1e3 * total / args.steps, np.mean(kern_ms), st["host_calls"]),
+              file=sys.stderr, flush=True)
+    plain_cell = g.cell_code("WI", "strong", "block")
+    if not args.no_plain and args.only != "persistent":
+        psteps = max(3, args.steps // 2)
+        total, wall, kern_ms, st = timed(plain_cell, g.PLAIN, psteps, 1)
+        f2, ret2 = rp.result()
+        out["plain"] = (total, wall, kern_ms, st)
+        print("plain: %.2f ms/step, kernel %.2f ms" % (1e3 * total / psteps, np.mean(kern_ms)),
+              file=sys.stderr, flush=True)
+        if "persistent" in out and not ((f2 == f).all() and (ret2 == ret).all()):
+            raise RuntimeError("plain and persistent forms disagree")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            of, orr = oracle.pread_fnv(path, offs, ITEM, threads=threads)
+        dt = time.perf_counter() - t0
+        if "persistent" in out and not (of == f).all():
+            raise RuntimeError("GPU checksums differ from the oracle")
+        cpu = {"value": round(reps * n / dt, 1), "unit": "syscalls/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "%d full passes of the sweep (%d preads of 4 KiB + FNV-1a each), "
+                         "items split over %d POSIX threads" % (reps, n, threads)}
+
+    key = "persistent" if "persistent" in out else "plain"
+    total, wall, kern_ms, st = out[key]
+    steps = len(wall)
+    calls_per_step = n
+    value = calls_per_step * steps / total
+    gbps = calls_per_step * ITEM * steps / total / 1e9
+    kavg_ms = float(np.mean(kern_ms))
+    achieved = calls_per_step * ITEM / (kavg_ms * 1e-3) / 1e9
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(value, 1),
+        "unit": "syscalls/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "pread sweep: 1024 work-groups x 256 work-items, one 4 KiB pread "
+                               "each at uniform random 4 KiB-aligned offsets of a 1 GiB "
+                               "seeded random file on tmpfs + FNV-1a-64 per item",
+                   "form": "persistent batched (%s)" % args.form,
+                   "calls_per_step": calls_per_step,
+                   "service_threads": int(ctx.cfg.service_threads) or (os.cpu_count() or 2) - 1,
+                   "staging_bytes": r.staging_bytes,
+                   "ring_slots": int(ctx.cfg.ring_slots)},
+        "pread_GBps": round(gbps, 2),
+        "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
+        "step_ms_p50": round(1e3 * percentile(wall, 50), 3),
+        "step_ms_p99": round(1e3 * percentile(wall, 99), 3),
+        "roofline": {"bound": "host-link", "achieved": round(achieved, 2),
+                     "peak": LINK_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / LINK_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "fnv4k_persistent", "kernel_ms": round(kavg_ms, 3),
+                     "bytes_per_launch": calls_per_step * ITEM},
+        "host": {"calls": st["host_calls"] // steps, "requests": st["requests"] // steps,
+                 "merged": st["merged"] // steps,
+                 "service_us_per_call": round(st["service_ns"] / max(1, st["host_calls"]) / 1e3, 3),
+                 "pool_busy_frac": round(st["service_ns"] / 1e9 / max(1e-9, total) /
+                                         max(1, int(ctx.cfg.service_threads) or
+                                             (os.cpu_count() or 2) - 1), 3)},
+    }
+    if "plain" in out and "persistent" in out:
+        pt, pw, pk, _ = out["plain"]
+        pv = calls_per_step * len(pw) / pt
+        res["plain_form"] = {"value": round(pv, 1), "unit": "syscalls/s",
+                             "ms_per_step": round(1e3 * pt / len(pw), 3),
+                             "kernel_ms": round(float(np.mean(pk)), 3)}
+        res["persistent_over_plain"] = round(value / pv, 3)
+    if cpu:
+        res["cpu_baseline"] = cpu
+    r.close()
+    if rp is not r:
+        rp.close()
+    ctx.shutdown()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,7 +168,8 @@ int gsys_stats_get(gsys_ctx *ctx, gsys_stats *out, int reset);
 
 /*
  * Ledger (GSYS_CFG_LEDGER): copy up to `max` records of serviced tickets,
- * oldest first, into out[4*i .. 4*i+3] = {ticket, nr, ret, args digest}.
+ * sorted by ticket, into out[6*i .. 6*i+5] = {ticket, nr, ret, args digest,
+ * service start (CLOCK_MONOTONIC ns), service end ns << 8 | poller index}.
  * Returns the number of records copied; reset != 0 clears the ledger.
  */
 int64_t gsys_ledger(gsys_ctx *ctx, uint64_t *out, uint64_t max, int reset);
@@ -202,8 +203,13 @@ const char *gsys_strerror(int code);
  * read and stores the call's return value in out_ret[i].
  *
  *   offsets   device address, uint64[n_items]
- *   staging   device address of a registered GSYS_BUF_HOST buffer of at least
- *             n_items * item_bytes bytes
+ *   staging   device address of a registered GSYS_BUF_HOST buffer of
+ *             `staging_bytes` bytes (0 = n_items * item_bytes).  The plain form
+ *             needs room for every item (item i lands at staging + i *
+ *             item_bytes).  The persistent forms also accept a smaller
+ *             staging ring: each resident work-group then owns two batch
+ *             buffers, and the grid shrinks to what the ring holds (at least
+ *             2 * wg_size * item_bytes bytes).
  *   lists     device address of a registered GSYS_BUF_HOST buffer of at least
  *             n_items * 16 bytes (descriptor lists of group calls)
  *   out_fnv   device address, uint64[n_items];  out_ret: int64[n_items]
@@ -218,8 +224,21 @@ const char *gsys_strerror(int code);
  * Errors: -EINVAL (shapes), -EFAULT (unregistered buffers), -ENODEV.
  */
 int gsys_fnv4k(gsys_ctx *ctx, int fd, uint64_t offsets, uint64_t n_items, uint32_t item_bytes,
-               uint64_t staging, uint64_t lists, uint64_t out_fnv, uint64_t out_ret,
-               uint32_t cell, uint32_t form, uint32_t wg_size, void *stream);
+               uint64_t staging, uint64_t staging_bytes, uint64_t lists, uint64_t out_fnv,
+               uint64_t out_ret, uint32_t cell, uint32_t form, uint32_t wg_size, void *stream);
+
+/*
+ * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
+ * host has already read every item into `staging` (any device-readable
+ * address: registered host memory or HBM); one kernel computes
+ * out_fnv[i] = FNV-1a-64 of the first rets[i] bytes (rets: device int64[n],
+ * values <= 0 hash nothing) of staging + i * item_bytes.  grid 0 = one
+ * work-group per wg_size items, otherwise a grid-stride loop over them.
+ * Errors: -EINVAL.
+ */
+int gsys_fnv4k_consume(gsys_ctx *ctx, uint64_t staging, uint64_t rets, uint64_t n_items,
+                       uint32_t item_bytes, uint64_t out_fnv, uint32_t wg_size, uint32_t grid,
+                       void *stream);
 
 #ifdef __cplusplus
 }

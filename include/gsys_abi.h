@@ -112,8 +112,8 @@ typedef struct gsys_dev_ctx {
     gsys_slot *ring;                 /* D slots, host-coherent                   */
     gsys_comp *comp;                 /* C records, host-coherent                 */
     unsigned long long *tail;        /* device memory: next ticket               */
-    unsigned long long *lo_cache;    /* device memory: cached retire watermark   */
-    const uint64_t *retired_lo;      /* host-coherent: every ticket below has retired */
+    const uint64_t *retired_lo;      /* host-coherent: every ticket below has retired
+                                        (maintained by the host for drain statistics) */
     uint64_t ring_mask;              /* D - 1                                    */
     uint64_t comp_mask;              /* C - 1                                    */
     uint64_t timeout_ticks;          /* device watchdog, 100 MHz ticks (0 = none) */

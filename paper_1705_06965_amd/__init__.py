@@ -73,7 +73,7 @@ class gsys_stats(C.Structure):
 
 class gsys_dev_ctx(C.Structure):
     _fields_ = [("ring", C.c_uint64), ("comp", C.c_uint64), ("tail", C.c_uint64),
-                ("lo_cache", C.c_uint64), ("retired_lo", C.c_uint64), ("ring_mask", C.c_uint64),
+                ("retired_lo", C.c_uint64), ("ring_mask", C.c_uint64),
                 ("comp_mask", C.c_uint64), ("timeout_ticks", C.c_uint64),
                 ("sleep_max", C.c_uint32), ("flags", C.c_uint32),
                 ("arena", C.c_uint64), ("arena_bytes", C.c_uint64)]
@@ -102,8 +102,10 @@ _SIGS = {
     "gsys_shutdown": (C.c_int, [_P, C.c_uint64]),
     "gsys_strerror": (C.c_char_p, [C.c_int]),
     "gsys_fnv4k": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint64,
-                             C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
-                             C.c_uint32, _P]),
+                             C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                             C.c_uint32, C.c_uint32, _P]),
+    "gsys_fnv4k_consume": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                     C.c_uint64, C.c_uint32, C.c_uint32, _P]),
     "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                     C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),
@@ -244,7 +246,7 @@ class Context:
         return d
 
     def ledger(self, max_records: int = 1 << 22, reset: bool = False) -> np.ndarray:
-        out = np.zeros((max_records, 4), dtype=np.uint64)
+        out = np.zeros((max_records, 6), dtype=np.uint64)
         n = check(int(lib.gsys_ledger(self.h, out.ctypes.data, max_records, int(reset))),
                   "gsys_ledger")
         return out[:n]
@@ -266,11 +268,12 @@ class Context:
         self.shutdown()
 
     # workloads -------------------------------------------------------------
-    def fnv4k(self, fd, offsets, n_items, item_bytes, staging, lists, out_fnv, out_ret,
-              cell=0, form=PLAIN, wg_size=256, stream=None):
+    def fnv4k(self, fd, offsets, n_items, item_bytes, staging, staging_bytes, lists, out_fnv,
+              out_ret, cell=0, form=PLAIN, wg_size=256, stream=None):
         return check(lib.gsys_fnv4k(self.h, fd, _ptr(offsets), n_items, item_bytes,
-                                    _ptr(staging), _ptr(lists), _ptr(out_fnv), _ptr(out_ret),
-                                    cell, form, wg_size, _stream(stream)), "gsys_fnv4k")
+                                    _ptr(staging), staging_bytes, _ptr(lists), _ptr(out_fnv),
+                                    _ptr(out_ret), cell, form, wg_size, _stream(stream)),
+                     "gsys_fnv4k")
 
 
 def exported_symbols():

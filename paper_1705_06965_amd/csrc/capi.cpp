@@ -27,11 +27,11 @@ struct gsys_ctx {
   uint64_t D = 0, C = 0;
   gsys_slot* ring = nullptr;       // host view
   gsys_comp* comp = nullptr;       // host view
-  uint64_t* host_words = nullptr;  // [0] retired_lo (own 256-byte line); NO_DEVICE: [32] tail, [48] lo_cache
+  uint64_t* host_words = nullptr;  // [0] retired_lo (own 256-byte line); NO_DEVICE: [32] tail
   gsys_slot* ring_dev = nullptr;
   gsys_comp* comp_dev = nullptr;
   uint64_t* retired_lo_dev = nullptr;
-  unsigned long long* dev_words = nullptr;  // [0] tail, [16] lo_cache, [32..63] kernel-call state
+  unsigned long long* dev_words = nullptr;  // [0] tail, [32..63] kernel-call state
   gsys_host::Pool* pool = nullptr;
   hipStream_t aux = nullptr;
   std::mutex mu;
@@ -157,7 +157,7 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
   c->D = cfg.ring_slots;
   c->C = 4 * c->D;
   c->grid_override = (uint32_t)env_u64("GSYS_PERSISTENT_GRID", 0);
-  c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", 16);
+  c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", 64);
   const uint64_t tmo = cfg.device_timeout_ns ? cfg.device_timeout_ns : 30000000000ull;
   c->timeout_ticks = tmo / 10;  // 100 MHz device wall clock
 
@@ -277,13 +277,7 @@ int gsys_device_ctx(gsys_ctx* c, gsys_dev_ctx* out) {
   memset(out, 0, sizeof *out);
   out->ring = c->ring_dev;
   out->comp = c->comp_dev;
-  if (c->no_device) {
-    out->tail = (unsigned long long*)&c->host_words[32];
-    out->lo_cache = (unsigned long long*)&c->host_words[48];
-  } else {
-    out->tail = c->dev_words;
-    out->lo_cache = c->dev_words + 16;
-  }
+  out->tail = c->no_device ? (unsigned long long*)&c->host_words[32] : c->dev_words;
   out->retired_lo = c->retired_lo_dev;
   out->ring_mask = c->D - 1;
   out->comp_mask = c->C - 1;
@@ -392,18 +386,19 @@ struct EmuShared {
   uint64_t timeout_ns;
 };
 
+// claim n tickets, then wait until each of their slots is free for this lap
 uint64_t emu_claim(const EmuShared& e, uint32_t n, int* err) {
   uint64_t t = __atomic_fetch_add((uint64_t*)e.d.tail, (uint64_t)n, __ATOMIC_RELAXED);
-  const uint64_t D = e.d.ring_mask + 1;
   const uint64_t t0 = now_ns();
-  for (;;) {
-    uint64_t lo = __atomic_load_n(e.d.retired_lo, __ATOMIC_ACQUIRE);
-    if (lo + D >= t + n) break;
-    if (now_ns() - t0 > e.timeout_ns) {
-      *err = -ETIMEDOUT;
-      break;
+  for (uint32_t i = 0; i < n && !*err; ++i) {
+    const uint64_t* ctl = &e.d.ring[(t + i) & e.d.ring_mask].ctl;
+    while (__atomic_load_n(ctl, __ATOMIC_ACQUIRE) != GSYS_CTL(t + i, GSYS_ST_FREE)) {
+      if (now_ns() - t0 > e.timeout_ns) {
+        *err = -ETIMEDOUT;
+        break;
+      }
+      std::this_thread::yield();
     }
-    std::this_thread::yield();
   }
   return t;
 }

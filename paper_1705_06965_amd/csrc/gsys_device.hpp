@@ -111,21 +111,23 @@ struct Waiter {
 };
 
 // ------------------------------------------------------------ ring protocol
-// Wait until tickets [t0, t0 + n) fit in the ring: every ticket below
-// t0 + n - D must have retired.  The host publishes a watermark; the device
-// keeps a cached copy so that the common case costs no host round trip.
-__device__ __forceinline__ int wait_ring_space(const gsys_dev_ctx& c, uint64_t t0, uint32_t n) {
-  const uint64_t D = c.ring_mask + 1;
-  const uint64_t need = t0 + n;  // need lo + D >= t0 + n
-  uint64_t lo = __hip_atomic_load(c.lo_cache, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (lo + D >= need) return 0;
+// Wait until slot t mod D is free for ticket t.  A fresh ring holds
+// FREE(t) for every t < D; later laps wait for the previous occupant to be
+// freed (by the GPU waiter for blocking calls, by the host for non-blocking
+// ones).  Each lane checks its own slot with one relaxed system-scope load,
+// so a full ring back-pressures exactly the callers that would overwrite a
+// live slot (section 5: if the slot is not free, the call is delayed).
+__device__ __forceinline__ int wait_slot_free(const gsys_dev_ctx& c, uint64_t t) {
+  if (t <= c.ring_mask) return 0;
+  const uint64_t* ctl = &c.ring[t & c.ring_mask].ctl;
+  const uint64_t want = GSYS_CTL(t, GSYS_ST_FREE);
+  uint64_t v = ld_sys(ctl);
+  if (v == want) return 0;
   Waiter w(c);
   for (;;) {
-    lo = ld_sys_acq(c.retired_lo);
-    __hip_atomic_fetch_max(c.lo_cache, (unsigned long long)lo, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    if (lo + D >= need) return 0;
     if (!w.pause()) return GSYS_ETIMEDOUT_RET;
+    v = ld_sys(ctl);
+    if (v == want) return 0;
   }
 }
 
@@ -146,17 +148,19 @@ __device__ __forceinline__ void publish(const gsys_dev_ctx& c, uint64_t t, uint1
 
 // Poll the completion record of claim group `head` until `n` members are done.
 // Returns 0, -ETIMEDOUT, or -EOVERFLOW if the record was reused by a later lap.
+// Polls use relaxed system-scope loads (they bypass the caches and cost no
+// cache maintenance); the caller issues one acquire fence after success.
 __device__ __forceinline__ int poll_group(const gsys_dev_ctx& c, uint64_t head, uint32_t n) {
   const uint64_t* st = &c.comp[head & c.comp_mask].stamp;
   const uint64_t want = GSYS_STAMP(head, n);
-  uint64_t v = ld_sys_acq(st);
+  uint64_t v = ld_sys(st);
   if (v == want) return 0;
   Waiter w(c);
   for (;;) {
     if (v == want) return 0;
     if ((v >> 8) > head) return GSYS_EOVERFLOW_RET;
     if (!w.pause()) return GSYS_ETIMEDOUT_RET;
-    v = ld_sys_acq(st);
+    v = ld_sys(st);
   }
 }
 
@@ -165,9 +169,13 @@ __device__ __forceinline__ int64_t read_ret(const gsys_dev_ctx& c, uint64_t t) {
 }
 
 // Blocking calls: the GPU frees the slot once it has the result (section 5).
+// The result was read before (the workgroup-scope release waits for this
+// wavefront's outstanding loads); nothing written here needs to reach the
+// host before the FREE mark, so no system-scope write-back is needed.
 __device__ __forceinline__ void free_slot(const gsys_dev_ctx& c, uint64_t t) {
   gsys_slot* s = c.ring + (t & c.ring_mask);
-  st_sys_rel(&s->ctl, GSYS_CTL(t + c.ring_mask + 1, GSYS_ST_FREE));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  st_sys(&s->ctl, GSYS_CTL(t + c.ring_mask + 1, GSYS_ST_FREE));
 }
 
 // Wave-level wait for the tickets held by the active lanes.  Lanes may hold
@@ -222,25 +230,24 @@ __device__ inline int64_t call_wi(const gsys_dev_ctx& c, uint16_t nr, const Args
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   const uint32_t leader = first_lane(m);
   uint64_t base = 0;
-  int err = 0;
-  if (lane_id() == leader) {
+  if (lane_id() == leader)
     base = __hip_atomic_fetch_add(c.tail, (unsigned long long)n, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
-    err = wait_ring_space(c, base, n);
-  }
   base = bcast64(base, leader);
-  err = __builtin_amdgcn_readlane(err, leader);
   Ticket tk{base + rank, rank, n};
-  if (err) {
-    // No room appeared before the watchdog: the tickets stay claimed but
-    // unpublished, so nothing can be serviced for them.
+  const int err = wait_slot_free(c, tk.t);
+  if (__ballot(err != 0)) {
+    // A slot stayed busy until the watchdog fired.  Nothing is published:
+    // the tickets stay claimed, so a drain of this context reports the loss.
     if (out) *out = Ticket{0, 0, 0};
-    return err;
+    return GSYS_ETIMEDOUT_RET;
   }
   const uint8_t fl = (uint8_t)((b == B::Blocking ? GSYS_F_BLOCKING : 0u) | GSYS_F_STRONG |
                                (role_of(nr) == Role::Producer ? GSYS_F_PRODUCER : 0u) |
                                (GSYS_GRAN_WI << GSYS_F_GRAN_SHIFT));
-  fence_release_sys();
+  // implicit strong ordering: the READY store is a system-scope release, so
+  // every write this wavefront made before the call is visible to the host
+  // before the request is
   publish(c, tk.t, nr, fl, n, rank, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
   if (out) *out = tk;
   if constexpr (b == B::Blocking) {
@@ -278,7 +285,7 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
   int64_t ret = GSYS_NOT_WAITED;
   if (threadIdx.x == 0) {
     uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int err = wait_ring_space(c, t, 1);
+    int err = wait_slot_free(c, t);
     if (err) {
       ret = err;
     } else {
@@ -286,7 +293,6 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
                                    (o == O::Strong ? GSYS_F_STRONG : 0u) |
                                    (producer ? GSYS_F_PRODUCER : 0u) | extra_flags |
                                    (GSYS_GRAN_WG << GSYS_F_GRAN_SHIFT));
-      if (!barrier_before) fence_release_sys();
       publish(c, t, nr, fl, 1, 0, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
       tk = Ticket{t, 0, 1};
       if constexpr (b == B::Blocking) {
@@ -388,7 +394,7 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
     if (threadIdx.x == 0) {
       Args6 a = make_args();
       uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int err = wait_ring_space(c, t, 1);
+      int err = wait_slot_free(c, t);
       if (err) {
         s_ret = err;
       } else {

@@ -96,6 +96,7 @@ Pool::~Pool() { stop_and_join(); }
 
 void Pool::start() {
   stop_.store(false);
+  next_stripe_.store((uint64_t)P_);
   for (int i = 0; i < P_; ++i) threads_.emplace_back([this, i] { poller(i); });
 }
 
@@ -451,8 +452,9 @@ void Pool::complete(uint64_t t, gsys_slot* s, int64_t ret) {
   }
 }
 
-void Pool::serve_bundle(Req* rq, int n) {
+void Pool::serve_bundle(Req* rq, int n, int poller) {
   const uint64_t t0 = now_ns();
+  uint64_t tprev = t0;
   uint64_t calls = 0, merged = 0;
   int i = 0;
   while (i < n) {
@@ -487,10 +489,12 @@ void Pool::serve_bundle(Req* rq, int n) {
           prefix += (uint64_t)lk;
           note_errno(rk);
           if (ledger_on_) {
+            const uint64_t te = now_ns();
             std::lock_guard<std::mutex> g(ledmu_);
             if (ledger_.size() < ledger_cap_)
               ledger_.push_back({rq[k].t, rq[k].s->nr, (uint64_t)rk,
-                                 mix64(rq[k].s->args[0] ^ mix64(rq[k].s->args[1] ^ mix64(rq[k].s->args[3])))});
+                                 mix64(rq[k].s->args[0] ^ mix64(rq[k].s->args[1] ^ mix64(rq[k].s->args[3]))),
+                                 tprev, (te << 8) | (uint64_t)(poller & 0xff)});
           }
           complete(rq[k].t, rq[k].s, rk);
         }
@@ -502,10 +506,13 @@ void Pool::serve_bundle(Req* rq, int n) {
     int64_t r = execute(s, &calls, &merged);
     if (!(s.flags & GSYS_F_LIST)) note_errno(r);
     if (ledger_on_) {
+      const uint64_t te = now_ns();
       std::lock_guard<std::mutex> g(ledmu_);
       if (ledger_.size() < ledger_cap_)
         ledger_.push_back({rq[i].t, s.nr, (uint64_t)r,
-                           mix64(s.args[0] ^ mix64(s.args[1] ^ mix64(s.args[3])))});
+                           mix64(s.args[0] ^ mix64(s.args[1] ^ mix64(s.args[3]))), tprev,
+                           (te << 8) | (uint64_t)(poller & 0xff)});
+      tprev = te;
     }
     complete(rq[i].t, rq[i].s, r);
     ++i;
@@ -519,14 +526,15 @@ void Pool::serve_bundle(Req* rq, int n) {
   serviced_.fetch_add((uint64_t)n, std::memory_order_acq_rel);
 }
 
-// Advance the retire watermark over slots freed for their next lap.
+// Advance the retire watermark: ticket lo has retired once its slot has been
+// freed for a later lap (the ticket in the control word only grows).
 void Pool::retire_scan() {
   if (retire_busy_.test_and_set(std::memory_order_acquire)) return;
   uint64_t lo = __atomic_load_n(retired_lo_, __ATOMIC_RELAXED);
   const uint64_t lo0 = lo;
-  for (int k = 0; k < 4096; ++k) {
+  for (uint64_t k = 0; k < D_; ++k) {
     const uint64_t c = ld_acq(&ring_[lo & (D_ - 1)].ctl);
-    if (c != GSYS_CTL(lo + D_, GSYS_ST_FREE)) break;
+    if (GSYS_CTL_TICKET(c) < lo + D_) break;
     ++lo;
   }
   if (lo != lo0) st_rel(retired_lo_, lo);
@@ -578,14 +586,17 @@ void Pool::poller(int idx) {
       if (K_ > 1) {
         // requests in ticket order; bundles of at most K
         std::sort(rq.begin(), rq.begin() + n, [](const Req& x, const Req& y) { return x.t < y.t; });
-        for (int i = 0; i < n; i += (int)K_) serve_bundle(&rq[i], std::min<int>((int)K_, n - i));
+        for (int i = 0; i < n; i += (int)K_)
+          serve_bundle(&rq[i], std::min<int>((int)K_, n - i), idx);
       } else {
-        for (int i = 0; i < n; ++i) serve_bundle(&rq[i], 1);
+        for (int i = 0; i < n; ++i) serve_bundle(&rq[i], 1, idx);
       }
       idle = 0;
     }
     if (done == full) {
-      s += (uint64_t)P_;
+      // the next unowned stripe goes to whichever poller finishes first, so
+      // long requests (group calls) spread evenly over the pool
+      s = next_stripe_.fetch_add(1, std::memory_order_relaxed);
       done = 0;
       continue;
     }
@@ -649,10 +660,12 @@ int64_t Pool::ledger(uint64_t* out, uint64_t max, int reset) {
     std::vector<LedgerRec> v(ledger_.begin(), ledger_.begin() + n);
     std::sort(v.begin(), v.end(), [](const LedgerRec& x, const LedgerRec& y) { return x.ticket < y.ticket; });
     for (uint64_t i = 0; i < n; ++i) {
-      out[4 * i] = v[i].ticket;
-      out[4 * i + 1] = v[i].nr;
-      out[4 * i + 2] = v[i].ret;
-      out[4 * i + 3] = v[i].digest;
+      out[6 * i] = v[i].ticket;
+      out[6 * i + 1] = v[i].nr;
+      out[6 * i + 2] = v[i].ret;
+      out[6 * i + 3] = v[i].digest;
+      out[6 * i + 4] = v[i].t_start;
+      out[6 * i + 5] = v[i].t_end_poller;
     }
   }
   if (reset) ledger_.clear();

@@ -6,10 +6,12 @@
 // (section 5).  Here P pinned user-space threads poll the slot ring instead
 // (section 3 treats interrupts versus polling as orthogonal; section 9 names
 // the user-mode service thread of earlier GPU file and network systems).
-// Tickets are dealt to pollers in stripes of `stripe` consecutive tickets,
-// stripe s going to poller s mod P, so a wavefront's 64 work-item calls are
-// serviced by several threads at once while a kernel-granularity call is one
-// unit of work for one thread (section 6, Fig. 5).
+// Tickets are dealt to pollers in stripes of `stripe` consecutive tickets;
+// a poller that has serviced every ticket of its stripe takes the next
+// unowned stripe.  A wavefront's 64 work-item calls are thus serviced by
+// several threads at once, long group calls spread evenly over the pool, and
+// a kernel-granularity call is one unit of work for one thread (section 6,
+// Fig. 5).
 //
 // Exactly-once: a poller takes a request only by compare-and-swap of the
 // slot's control word from READY to PROCESSING (section 5).
@@ -39,7 +41,7 @@ struct Buf {
 };
 
 struct LedgerRec {
-  uint64_t ticket, nr, ret, digest;
+  uint64_t ticket, nr, ret, digest, t_start, t_end_poller;  // t_end << 8 | poller
 };
 
 class Pool {
@@ -76,7 +78,7 @@ class Pool {
     gsys_slot* s;
   };
   void poller(int idx);
-  void serve_bundle(Req* rq, int n);
+  void serve_bundle(Req* rq, int n, int poller);
   int64_t execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
   int64_t exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
   void complete(uint64_t t, gsys_slot* s, int64_t ret);
@@ -98,6 +100,7 @@ class Pool {
   std::vector<std::thread> threads_;
   std::atomic<bool> stop_{false};
   std::atomic<uint64_t> serviced_{0};
+  std::atomic<uint64_t> next_stripe_{0};  // stripes are taken in order by whichever poller is free
   std::atomic_flag retire_busy_ = ATOMIC_FLAG_INIT;
 
   std::vector<std::atomic<uint8_t>> fdperm_;

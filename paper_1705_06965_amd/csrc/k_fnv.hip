@@ -5,12 +5,14 @@
 //
 // Data path: the host pool preads each item into pinned host staging; the GPU
 // reads the staging bytes once over the host link with coalesced 16-byte
-// loads (each group of 4 lanes fetches one item's next 64 bytes), transposes
+// loads (each group of 16 lanes fetches one item's next 256 bytes), transposes
 // them through LDS, and every lane runs the FNV-1a chain of its own item.
 // FNV-1a is a serial byte chain, so one lane per item is the parallel grain.
 #include "gsys_device.hpp"
 #include "gsys.h"
 #include "kernels.hpp"
+
+#include <algorithm>
 
 namespace gsys_k {
 
@@ -42,38 +44,68 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-constexpr uint32_t kRowStride = 80;  // 64 data bytes + 16 pad: conflict-free 16-byte LDS reads
-constexpr uint32_t kTileBytes = 64 * kRowStride;
+// Per step every row (item) of the wave contributes CH contiguous bytes:
+// CH/16 lanes x 16 B per row, 1024/CH rows per load instruction, CH/16
+// instructions for the 64 rows.  The next step's loads are issued before the
+// current step is hashed, so the host-link round trip overlaps the FNV chain.
+// Rows of a wavefront are consecutive items, so row r starts at
+// row0 + r * item_bytes; each row's byte count sits in LDS next to the tile.
+template <uint32_t CH>
+struct Tile {
+  static constexpr uint32_t kLanesPerRow = CH / 16;
+  static constexpr uint32_t kRowsPerLoad = 64 / kLanesPerRow;
+  static constexpr uint32_t kLoads = 64 / kRowsPerLoad;
+  static constexpr uint32_t kRowStride = CH + 16;  // pad: conflict-free 16-byte LDS reads
+  static constexpr uint32_t kBytes = 64 * kRowStride + 64 * 4;
+};
 
-// All 64 lanes of the wave call this.  Lane l hashes `nbytes` bytes of its
-// item at staging address `src`.  `tile` is this wave's 5 KiB LDS tile.
-__device__ uint64_t wave_fnv(uint64_t src, uint32_t nbytes, uint32_t item_bytes, uint8_t* tile) {
+// 256-byte rows for work-groups of up to 256 work-items; 128-byte rows for
+// larger work-groups (fewer registers per lane are available there).  Rows of
+// 256 bytes read host staging at the link's rate (57 GB/s measured on MI355X
+// against 42 GB/s for 128-byte rows): each row's request covers two
+// 128-byte lines.
+template <uint32_t WGMAX>
+constexpr uint32_t chunk_for() { return WGMAX <= 256 ? 256u : 128u; }
+
+// All 64 lanes of the wave call this.  Lane l hashes `nbytes` bytes of item
+// row0 + l * item_bytes.  `tile` is this wave's LDS tile.
+template <uint32_t CH>
+__device__ uint64_t wave_fnv_t(uint64_t row0, uint32_t nbytes, uint32_t item_bytes, uint8_t* tile) {
+  using T = Tile<CH>;
   const uint32_t lane = lane_id();
-  const uint32_t col = lane & 3u;
-  uint64_t rsrc[4];
-  uint32_t rlen[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int r = k * 16 + (int)(lane >> 2);
-    rsrc[k] = shfl64(src, r);
-    rlen[k] = (uint32_t)__shfl((int)nbytes, r, 64);
-  }
+  const uint32_t col = lane % T::kLanesPerRow;
+  const uint32_t rsub = lane / T::kLanesPerRow;
+  uint32_t* rlen = reinterpret_cast<uint32_t*>(tile + 64 * T::kRowStride);
+  rlen[lane] = nbytes;
   uint32_t maxlen = nbytes;
   for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, (uint32_t)__shfl_xor((int)maxlen, o, 64));
+  if (maxlen > item_bytes) maxlen = item_bytes;
+  __builtin_amdgcn_wave_barrier();
   uint64_t h = 0xcbf29ce484222325ull;
-  for (uint32_t off = 0; off < maxlen && off < item_bytes; off += 64) {
+  uint4 v[T::kLoads];
+  auto load = [&](uint32_t off) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t r = (uint32_t)k * 16 + (lane >> 2);
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (off < rlen[k]) v = *reinterpret_cast<const uint4*>(rsrc[k] + off + col * 16);
-      *reinterpret_cast<uint4*>(tile + r * kRowStride + col * 16) = v;
+    for (uint32_t k = 0; k < T::kLoads; ++k) {
+      const uint32_t r = k * T::kRowsPerLoad + rsub;
+      v[k] = make_uint4(0, 0, 0, 0);
+      // a row is read only where it holds bytes, inside its own item slot
+      if (off < rlen[r] && off + col * 16 < item_bytes)
+        v[k] = *reinterpret_cast<const uint4*>(row0 + (uint64_t)r * item_bytes + off + col * 16);
+    }
+  };
+  if (maxlen) load(0);
+  for (uint32_t off = 0; off < maxlen; off += CH) {
+#pragma unroll
+    for (uint32_t k = 0; k < T::kLoads; ++k) {
+      const uint32_t r = k * T::kRowsPerLoad + rsub;
+      *reinterpret_cast<uint4*>(tile + r * T::kRowStride + col * 16) = v[k];
     }
     __builtin_amdgcn_wave_barrier();
-    const uint8_t* row = tile + lane * kRowStride;
-    if (off + 64 <= nbytes) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    if (off + CH < maxlen) load(off + CH);  // prefetch the next step
+    const uint8_t* row = tile + lane * T::kRowStride;
+    if (off + CH <= nbytes) {
+#pragma unroll 2
+      for (uint32_t q = 0; q < CH / 16; ++q) {
         const uint4 w = *reinterpret_cast<const uint4*>(row + q * 16);
         h = fnv_word4(h, w.x);
         h = fnv_word4(h, w.y);
@@ -82,7 +114,7 @@ __device__ uint64_t wave_fnv(uint64_t src, uint32_t nbytes, uint32_t item_bytes,
       }
     } else if (off < nbytes) {
       const uint32_t left = nbytes - off;
-      for (uint32_t q = 0; q < 16 && q * 4 < left; ++q) {
+      for (uint32_t q = 0; q < CH / 4 && q * 4 < left; ++q) {
         const uint32_t w = *reinterpret_cast<const uint32_t*>(row + q * 4);
         const int nb = (int)min(4u, left - q * 4);
         h = fnv_word(h, w, nb);
@@ -104,15 +136,26 @@ struct FnvArgs {
   KState* ks;
   int32_t fd;
   uint32_t item_bytes;
+  uint32_t ring;  // persistent forms: 1 = each work-group owns two batch buffers
 };
 
+// Staging address of item `item` of batch `bt` (slot = item - bt * batch).
+__device__ __forceinline__ uint64_t stage_addr(const FnvArgs& A, uint64_t bt, uint32_t batch,
+                                               uint64_t item) {
+  if (!A.ring) return A.staging + item * A.item_bytes;
+  const uint64_t buf = (uint64_t)blockIdx.x * 2 + (bt / gridDim.x) % 2;
+  return A.staging + (buf * batch + (item - bt * batch)) * A.item_bytes;
+}
+
+// `row0` is the staging address of the item of lane 0 of this wavefront; the
+// wavefront's items follow it at item_bytes apart.
+template <uint32_t CH>
 __device__ __forceinline__ void consume_item(const FnvArgs& A, uint64_t item, bool valid,
-                                             int64_t ret, uint8_t* lds) {
+                                             int64_t ret, uint8_t* lds, uint64_t row0) {
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t nbytes =
       (valid && ret > 0) ? (uint32_t)min<int64_t>(ret, (int64_t)A.item_bytes) : 0u;
-  const uint64_t src = A.staging + (valid ? item : 0) * (uint64_t)A.item_bytes;
-  const uint64_t h = wave_fnv(src, nbytes, A.item_bytes, lds + wave * kTileBytes);
+  const uint64_t h = wave_fnv_t<CH>(row0, nbytes, A.item_bytes, lds + wave * Tile<CH>::kBytes);
   if (valid) {
     A.out_fnv[item] = h;
     A.out_ret[item] = ret;
@@ -121,8 +164,9 @@ __device__ __forceinline__ void consume_item(const FnvArgs& A, uint64_t item, bo
 
 // Plain form: one launch, one item per work-item, the call made at the
 // granularity / ordering / blocking of the template.
-template <G g, O o, B b>
-__global__ void fnv4k_plain(FnvArgs A) {
+template <G g, O o, B b, uint32_t WGMAX>
+__global__ __launch_bounds__(WGMAX, WGMAX <= 256 ? 2 : 4) void fnv4k_plain(FnvArgs A) {
+  constexpr uint32_t CH = chunk_for<WGMAX>();
   extern __shared__ __align__(16) uint8_t lds[];
   const uint64_t first = (uint64_t)blockIdx.x * blockDim.x;
   const uint64_t item = first + threadIdx.x;
@@ -177,7 +221,8 @@ __global__ void fnv4k_plain(FnvArgs A) {
                                                           __HIP_MEMORY_SCOPE_SYSTEM))
                 : 0;
   }
-  consume_item(A, item, valid, ret, lds);
+  const uint64_t row0 = A.staging + (first + (threadIdx.x & ~63u)) * A.item_bytes;
+  consume_item<CH>(A, item, valid, ret, lds, row0);
 }
 
 // Persistent form: a co-resident grid; work-group w handles batches w,
@@ -192,13 +237,15 @@ __device__ __forceinline__ Ticket issue_batch(const FnvArgs& A, uint64_t bt, uin
   if (threadIdx.x < 64)
     for (uint32_t i = threadIdx.x; i < cnt; i += 64)
       L[i] = gsys_iodesc{A.offsets[first + i], i * A.item_bytes, (int32_t)A.item_bytes};
-  Args6 a{{(uint64_t)(int64_t)A.fd, (uint64_t)L, cnt, A.staging + first * A.item_bytes, 0, 0}};
+  Args6 a{{(uint64_t)(int64_t)A.fd, (uint64_t)L, cnt, stage_addr(A, bt, batch, first), 0, 0}};
   Ticket tk{0, 0, 0};
   call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_PREAD64, GSYS_F_LIST, a, &tk);
   return tk;
 }
 
-__global__ void fnv4k_persistent(FnvArgs A) {
+template <uint32_t WGMAX>
+__global__ __launch_bounds__(WGMAX, WGMAX <= 256 ? 2 : 4) void fnv4k_persistent(FnvArgs A) {
+  constexpr uint32_t CH = chunk_for<WGMAX>();
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t batch = blockDim.x;
   const uint64_t nb = (A.n_items + batch - 1) / batch;
@@ -216,9 +263,34 @@ __global__ void fnv4k_persistent(FnvArgs A) {
         valid ? (r < 0 ? r : (int64_t)__hip_atomic_load(&A.lists[item].len_ret, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_SYSTEM))
               : 0;
-    consume_item(A, item, valid, ret, lds);
+    const uint64_t row0 = stage_addr(A, bt, batch, bt * batch + (threadIdx.x & ~63u));
+    consume_item<CH>(A, item, valid, ret, lds, row0);
+    // the buffer of batch bt is reused by batch bt + 2 * grid, issued in the
+    // next iteration: every lane must be done reading it first
+    __syncthreads();
     bt = bn;
     tk = tkn;
+  }
+}
+
+// Kernel-split form: the host has already read every item (section 2,
+// Fig. 1 left); a plain kernel checksums staging.  rets[i] is the byte count
+// of item i (<= 0: no bytes).
+template <uint32_t WGMAX, uint32_t CH>
+__global__ __launch_bounds__(WGMAX, WGMAX <= 256 ? 2 : 4) void fnv4k_consume(
+    uint64_t staging, const int64_t* rets, uint64_t n_items, uint32_t item_bytes,
+    uint64_t* out_fnv) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t wave = threadIdx.x >> 6;
+  for (uint64_t first = (uint64_t)blockIdx.x * blockDim.x; first < n_items;
+       first += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t item = first + threadIdx.x;
+    const bool valid = item < n_items;
+    const int64_t ret = valid ? rets[item] : 0;
+    const uint32_t nbytes = ret > 0 ? (uint32_t)min<int64_t>(ret, (int64_t)item_bytes) : 0u;
+    const uint64_t row0 = staging + (first + (threadIdx.x & ~63u)) * (uint64_t)item_bytes;
+    const uint64_t h = wave_fnv_t<CH>(row0, nbytes, item_bytes, lds + wave * Tile<CH>::kBytes);
+    if (valid) out_fnv[item] = h;
   }
 }
 
@@ -233,8 +305,8 @@ __global__ void zero_words(unsigned long long* p, uint32_t n) {
 using namespace gsys_k;
 
 int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32_t item_bytes,
-               uint64_t staging, uint64_t lists, uint64_t out_fnv, uint64_t out_ret, uint32_t cell,
-               uint32_t form, uint32_t wg_size, void* stream) {
+               uint64_t staging, uint64_t staging_bytes, uint64_t lists, uint64_t out_fnv,
+               uint64_t out_ret, uint32_t cell, uint32_t form, uint32_t wg_size, void* stream) {
   if (!ctx) return -EINVAL;
   if (!n_items) return 0;
   if (item_bytes == 0 || item_bytes % 64 || item_bytes > (1u << 20)) return -EINVAL;
@@ -243,7 +315,12 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
   if (!offsets || !out_fnv || !out_ret) return -EINVAL;
   if (n_items > (1ull << 32)) return -EINVAL;
   const uint64_t stage_bytes = n_items * (uint64_t)item_bytes;
-  if (gsys_internal::check_host_range(ctx, staging, stage_bytes)) return -EFAULT;
+  if (!staging_bytes) staging_bytes = stage_bytes;
+  if (gsys_internal::check_host_range(ctx, staging, staging_bytes)) return -EFAULT;
+  const bool persistent = form == GSYS_PERSISTENT || form == GSYS_GRAPH;
+  const uint64_t batch_bytes = (uint64_t)wg_size * item_bytes;
+  if (staging_bytes < stage_bytes && (!persistent || staging_bytes < 2 * batch_bytes))
+    return -EINVAL;
   if (gsys_internal::check_host_range(ctx, lists, n_items * sizeof(gsys_iodesc))) return -EFAULT;
 
   FnvArgs A;
@@ -257,25 +334,33 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
   A.ks = (KState*)gsys_internal::kstate(ctx);
   A.fd = fd;
   A.item_bytes = item_bytes;
+  A.ring = 0;
   hipStream_t s = (hipStream_t)stream;
-  const uint32_t lds = (wg_size / 64) * kTileBytes;
+  const bool small = wg_size <= 256;
+  const uint32_t lds = (wg_size / 64) * (small ? Tile<256>::kBytes : Tile<128>::kBytes);
 
   if (form == GSYS_PERSISTENT || form == GSYS_GRAPH) {
     const uint64_t nb = (n_items + wg_size - 1) / wg_size;
-    uint32_t grid = gsys_internal::resident_grid(ctx, (const void*)fnv4k_persistent, wg_size, lds);
+    const void* kp = small ? (const void*)fnv4k_persistent<256> : (const void*)fnv4k_persistent<1024>;
+    uint32_t grid = gsys_internal::resident_grid(ctx, kp, wg_size, lds);
     if (grid == 0) return -ENODEV;
     if ((uint64_t)grid > nb) grid = (uint32_t)nb;
     const uint32_t req = gsys_internal::persistent_grid_override(ctx);
     if (req && req < grid) grid = req;
+    if (staging_bytes < stage_bytes) {
+      // staging ring: two batch buffers per resident work-group
+      A.ring = 1;
+      const uint64_t fit = staging_bytes / (2 * batch_bytes);
+      if ((uint64_t)grid > fit) grid = (uint32_t)fit;
+    }
     void* args[] = {&A};
     if (form == GSYS_GRAPH) {
       const uint64_t key = gsys_internal::hash_words(
-          {0xF4Bull, (uint64_t)fd, offsets, n_items, item_bytes, staging, lists, out_fnv, out_ret,
-           wg_size, grid, (uint64_t)s});
-      return gsys_internal::launch_graph(ctx, key, (const void*)fnv4k_persistent, grid, wg_size, lds,
-                                         args, s);
+          {0xF4Bull, (uint64_t)fd, offsets, n_items, item_bytes, staging, staging_bytes, lists,
+           out_fnv, out_ret, wg_size, grid, (uint64_t)s});
+      return gsys_internal::launch_graph(ctx, key, kp, grid, wg_size, lds, args, s);
     }
-    return gsys_internal::launch(ctx, (const void*)fnv4k_persistent, grid, wg_size, lds, args, s);
+    return gsys_internal::launch(ctx, kp, grid, wg_size, lds, args, s);
   }
 
   const uint32_t gran = GSYS_CELL_GRAN(cell);
@@ -287,20 +372,20 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
   const void* k = nullptr;
   if (gran == GSYS_GRAN_WI) {
     if (!strong) return -EINVAL;  // work-item calls are implicitly strong
-    k = blocking ? (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::Blocking>
-                 : (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::NonBlocking>;
+    k = blocking ? (small ? (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::Blocking, 256> : (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::Blocking, 1024>)
+                 : (small ? (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::NonBlocking, 256> : (const void*)fnv4k_plain<G::WorkItem, O::Strong, B::NonBlocking, 1024>);
   } else if (gran == GSYS_GRAN_WG) {
     if (strong)
-      k = blocking ? (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::Blocking>
-                   : (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::NonBlocking>;
+      k = blocking ? (small ? (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::Blocking, 256> : (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::Blocking, 1024>)
+                   : (small ? (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::NonBlocking, 256> : (const void*)fnv4k_plain<G::WorkGroup, O::Strong, B::NonBlocking, 1024>);
     else
-      k = blocking ? (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::Blocking>
-                   : (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::NonBlocking>;
+      k = blocking ? (small ? (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::Blocking, 256> : (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::Blocking, 1024>)
+                   : (small ? (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::NonBlocking, 256> : (const void*)fnv4k_plain<G::WorkGroup, O::Relaxed, B::NonBlocking, 1024>);
   } else if (gran == GSYS_GRAN_KERNEL) {
     if (strong) return -EINVAL;  // kernel calls are relaxed only
     if (stage_bytes > 0xffffffffull) return -EINVAL;  // descriptor offsets are 32-bit
-    k = blocking ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking>
-                 : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking>;
+    k = blocking ? (small ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking, 256> : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking, 1024>)
+                 : (small ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking, 256> : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking, 1024>);
     // fresh per-launch state for the kernel-granularity call site
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)A.ks,
                        (uint32_t)(sizeof(KState) / 8));
@@ -310,4 +395,21 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
   }
   void* args[] = {&A};
   return gsys_internal::launch(ctx, k, grid, wg_size, lds, args, s);
+}
+
+int gsys_fnv4k_consume(gsys_ctx* ctx, uint64_t staging, uint64_t rets, uint64_t n_items,
+                       uint32_t item_bytes, uint64_t out_fnv, uint32_t wg_size, uint32_t grid,
+                       void* stream) {
+  if (!ctx || !staging || !rets || !out_fnv) return -EINVAL;
+  if (!n_items) return 0;
+  if (item_bytes == 0 || item_bytes % 64 || item_bytes > (1u << 20)) return -EINVAL;
+  if (!(wg_size == 64 || wg_size == 128 || wg_size == 256 || wg_size == 512 || wg_size == 1024))
+    return -EINVAL;
+  const uint64_t nb = (n_items + wg_size - 1) / wg_size;
+  if (!grid || grid > nb) grid = (uint32_t)std::min<uint64_t>(nb, 0x7fffffffull);
+  const bool small = wg_size <= 256;
+  const uint32_t lds = (wg_size / 64) * (small ? Tile<256>::kBytes : Tile<128>::kBytes);
+  void* args[] = {&staging, &rets, &n_items, &item_bytes, &out_fnv};
+  const void* k = small ? (const void*)fnv4k_consume<256, 256> : (const void*)fnv4k_consume<1024, 128>;
+  return gsys_internal::launch(ctx, k, grid, wg_size, lds, args, (hipStream_t)stream);
 }

@@ -13,7 +13,7 @@ from . import (Context, FD_READ, PLAIN, PERSISTENT, GRAPH, check, lib, cell_code
 
 class FnvRunner:
     def __init__(self, ctx: Context, path: str, offsets: np.ndarray, item_bytes: int = 4096,
-                 wg_size: int = 256, device: str = "cuda"):
+                 wg_size: int = 256, device: str = "cuda", staging_bytes: int = 0):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -23,7 +23,8 @@ class FnvRunner:
         self.n = int(len(offsets))
         self.item_bytes = item_bytes
         self.wg_size = wg_size
-        self.staging = ctx.host_alloc(max(1, self.n * item_bytes))
+        self.staging_bytes = staging_bytes or max(1, self.n * item_bytes)
+        self.staging = ctx.host_alloc(self.staging_bytes)
         self.lists = ctx.host_alloc(max(16, self.n * 16))
         offs = np.ascontiguousarray(offsets, dtype=np.uint64)
         self.offsets = torch.from_numpy(offs.view(np.int64)).to(device)
@@ -32,7 +33,8 @@ class FnvRunner:
 
     def launch(self, cell: int = 0, form: int = PLAIN, stream=None):
         return check(lib.gsys_fnv4k(self.ctx.h, self.fd, self.offsets.data_ptr(), self.n,
-                                    self.item_bytes, self.staging.dev, self.lists.dev,
+                                    self.item_bytes, self.staging.dev, self.staging_bytes,
+                                    self.lists.dev,
                                     self.out_fnv.data_ptr(), self.out_ret.data_ptr(), cell, form,
                                     self.wg_size, _stream(stream)), "gsys_fnv4k")
 

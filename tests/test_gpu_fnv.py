@@ -90,6 +90,26 @@ def test_persistent_and_graph_forms(gs, mid, form):
         assert (f == want_fnv).all()
 
 
+@pytest.mark.parametrize("ring_batches", [4, 6])
+def test_persistent_staging_ring(gs, mid, ring_batches):
+    """A staging ring smaller than the data: each resident work-group reuses
+    two batch buffers, so batches share memory across iterations."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    r0, (want_fnv, want_ret) = mid
+    offs = r0.offsets.cpu().numpy().view(np.uint64)
+    r = FnvRunner(ctx, r0.path, offs, 4096, wg_size=256,
+                  staging_bytes=ring_batches * 256 * 4096)
+    for fm in (g.PERSISTENT, g.GRAPH, g.GRAPH):
+        say("staging ring", ring_batches, fm)
+        f, ret = r.run(form=fm)
+        assert (ret == want_ret).all()
+        assert (f == want_fnv).all()
+    with pytest.raises(g.GsysError):
+        r.launch(g.cell_code("WI", "strong", "block"), g.PLAIN)  # plain needs every item
+    r.close()
+
+
 def test_illegal_cells_rejected(gs, mid):
     g, ctx = gs
     r, _ = mid
