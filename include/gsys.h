@@ -227,6 +227,42 @@ int gsys_fnv4k(gsys_ctx *ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
                uint64_t staging, uint64_t staging_bytes, uint64_t lists, uint64_t out_fnv,
                uint64_t out_ret, uint32_t cell, uint32_t form, uint32_t wg_size, void *stream);
 
+/* One chunk of a file for gsys_wordscan. */
+typedef struct gsys_chunk {
+    int32_t  fd;       /* allowed for GSYS_FD_READ                     */
+    uint32_t file;     /* row of the counts matrix                     */
+    uint64_t off;      /* file offset of the chunk                     */
+    uint32_t len;      /* chunk bytes (<= chunk_max)                   */
+    uint32_t pad;
+} gsys_chunk;
+
+/*
+ * Word search (the wordcount case study of section 7.1): counts[f * nq + q] =
+ * number of tokens of file f equal to query q, a token being a maximal run of
+ * bytes other than space (0x20) and newline (0x0a), compared exactly.
+ *
+ *   chunks    device gsys_chunk[n_chunks]: every file cut into chunks of at
+ *             most chunk_max bytes that cover it exactly (a token belongs to
+ *             the chunk in which it starts; each chunk's pread also fetches
+ *             the byte before it and 16 bytes after it)
+ *   queries   device uint8[nq * 16], query q in bytes [16q, 16q + qlens[q]);
+ *             1 <= qlens[q] <= 16, no delimiter bytes, all distinct;
+ *             1 <= nq <= 64
+ *   counts    device uint32[nfiles * nq], zeroed by the call
+ *   staging   registered GSYS_BUF_HOST buffer of staging_bytes; the plain
+ *             form needs n_chunks * cbuf bytes, the persistent forms 2 * cbuf
+ *             per resident work-group (the grid shrinks to fit), with
+ *             cbuf = round_up(chunk_max + 64, 16)
+ *   form      GSYS_PLAIN: one work-group per chunk, blocking relaxed
+ *             work-group pread (the paper's setting); GSYS_PERSISTENT /
+ *             GSYS_GRAPH: resident work-groups take chunks from a device work
+ *             counter and prefetch the next chunk with a non-blocking call
+ * Errors: -EINVAL (shapes), -EFAULT (staging not registered), -ENODEV.
+ */
+int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t chunk_max,
+                  uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts, uint32_t nfiles,
+                  uint64_t staging, uint64_t staging_bytes, uint32_t form, void *stream);
+
 /*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable

@@ -106,6 +106,9 @@ _SIGS = {
                              C.c_uint32, C.c_uint32, _P]),
     "gsys_fnv4k_consume": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                                      C.c_uint64, C.c_uint32, C.c_uint32, _P]),
+    "gsys_wordscan": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64,
+                                C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
+                                C.c_uint32, _P]),
     "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                     C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),

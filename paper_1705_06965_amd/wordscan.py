@@ -1,0 +1,95 @@
+"""Driver of the word-search workload (wordcount case study, section 7.1):
+builds the chunk table, allocates staging and launches gsys_wordscan."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+from . import FD_READ, PERSISTENT, PLAIN, check, lib, _stream
+
+CHUNK_DTYPE = np.dtype([("fd", "<i4"), ("file", "<u4"), ("off", "<u8"), ("len", "<u4"),
+                        ("pad", "<u4")])
+
+
+def chunk_table(fds, sizes, chunk_max: int) -> np.ndarray:
+    """Every file cut into chunks of at most chunk_max bytes covering it
+    exactly, in file order (an empty file has no chunk)."""
+    rows = []
+    for f, (fd, size) in enumerate(zip(fds, sizes)):
+        size = int(size)
+        off = 0
+        while off < size:
+            ln = min(chunk_max, size - off)
+            rows.append((int(fd), f, off, ln, 0))
+            off += ln
+    return np.array(rows, dtype=CHUNK_DTYPE)
+
+
+def staging_bytes(chunk_max: int, n_buffers: int) -> int:
+    return ((chunk_max + 64 + 15) // 16 * 16) * n_buffers
+
+
+class WordScanRunner:
+    def __init__(self, ctx, paths, queries, chunk_max: int = 1 << 20, device: str = "cuda",
+                 persistent_buffers: int = 256):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.fds = [os.open(p, os.O_RDONLY) for p in paths]
+        for fd in self.fds:
+            ctx.allow_fd(fd, FD_READ)
+        self.sizes = np.array([os.fstat(fd).st_size for fd in self.fds], dtype=np.uint64)
+        self.nfiles = len(paths)
+        self.nq = len(queries)
+        self.chunk_max = chunk_max
+        tab = chunk_table(self.fds, self.sizes, chunk_max)
+        self.n_chunks = len(tab)
+        self.total_bytes = int(self.sizes.sum())
+        self.chunks = torch.from_numpy(tab.view(np.uint8).copy()).to(device)
+        q = np.zeros((self.nq, 16), dtype=np.uint8)
+        ql = np.zeros(self.nq, dtype=np.uint32)
+        for i, w in enumerate(queries):
+            if not 1 <= len(w) <= 16 or b" " in w or b"\n" in w:
+                raise ValueError("query %r: 1..16 bytes without delimiters" % (w,))
+            q[i, :len(w)] = np.frombuffer(w, dtype=np.uint8)
+            ql[i] = len(w)
+        self.queries = torch.from_numpy(q).to(device)
+        self.qlens = torch.from_numpy(ql.view(np.int32)).to(device)
+        self.counts = torch.zeros(max(1, self.nfiles * self.nq), dtype=torch.int32, device=device)
+        self.persistent_bytes = staging_bytes(chunk_max, min(persistent_buffers,
+                                                             2 * max(1, self.n_chunks)))
+        self.plain_bytes = staging_bytes(chunk_max, max(1, self.n_chunks))
+        self.staging_p = ctx.host_alloc(self.persistent_bytes)
+        self.staging_w = None
+
+    def launch(self, form=PERSISTENT, stream=None):
+        if form == PLAIN:
+            if self.staging_w is None:
+                self.staging_w = self.ctx.host_alloc(self.plain_bytes)
+            st, sb = self.staging_w, self.plain_bytes
+        else:
+            st, sb = self.staging_p, self.persistent_bytes
+        return check(lib.gsys_wordscan(self.ctx.h, self.chunks.data_ptr(), self.n_chunks,
+                                       self.chunk_max, self.queries.data_ptr(),
+                                       self.qlens.data_ptr(), self.nq, self.counts.data_ptr(),
+                                       self.nfiles, st.dev, sb, form, _stream(stream)),
+                     "gsys_wordscan")
+
+    def run(self, form=PERSISTENT, stream=None):
+        self.launch(form, stream)
+        self.torch.cuda.synchronize()
+        rc = self.ctx.wait(60_000_000_000)
+        if rc:
+            raise RuntimeError("drain failed: %d" % rc)
+        return self.result()
+
+    def result(self):
+        return self.counts.cpu().numpy().view(np.uint32)[:self.nfiles * self.nq] \
+            .reshape(self.nfiles, self.nq).copy()
+
+    def close(self):
+        for fd in self.fds:
+            self.ctx.allow_fd(fd, 0)
+            os.close(fd)
+        self.fds = []
