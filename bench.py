@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--staging-mib", type=int, default=0,
                     help="persistent form: staging ring size (0 = one slot per item)")
     ap.add_argument("--only", default="", help="profiling aid: 'plain' or 'persistent' only")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "wordscan"],
+                    help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
+                         "word search over 2,000 files")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -97,6 +100,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 1 << 30, "copies": 3}))
         return
+    if args.workload == "wordscan":
+        return run_wordscan(args)
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
@@ -246,6 +251,105 @@ def main():
     r.close()
     if rp is not r:
         rp.close()
+    ctx.shutdown()
+    print(json.dumps(res), flush=True)
+
+
+def run_wordscan(args):
+    """Word search: 2,000 files (log-normal sizes, median 64 KiB, cap 8 MiB) of
+    Zipf(1.1) words from a 50k-word vocabulary; 64 queries; 1 MiB chunks.
+    value = scanned file bytes per second (GB/s) over the timed passes."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    t0 = time.time()
+    c = synth.wordcount_corpus()
+    for p in c.paths:
+        with open(p, "rb") as f:
+            f.read()
+    print("corpus %d files %.1f MiB, setup %.1fs" % (len(c.paths), c.total_bytes / 2**20,
+                                                     time.time() - t0), file=sys.stderr, flush=True)
+    ctx = g.Context(ring_slots=1 << 16, service_threads=args.service_threads,
+                    device_timeout_ns=60_000_000_000)
+    r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20)
+    stream = torch.cuda.current_stream()
+
+    def timed(form, steps, warmup):
+        for _ in range(warmup):
+            r.launch(form, stream)
+            torch.cuda.synchronize()
+            ctx.wait(60_000_000_000)
+        ctx.stats(reset=True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        wall = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s0 = time.perf_counter()
+            evs[i][0].record(stream)
+            r.launch(form, stream)
+            evs[i][1].record(stream)
+            torch.cuda.synchronize()
+            if ctx.wait(60_000_000_000):
+                raise RuntimeError("drain failed")
+            wall.append(time.perf_counter() - s0)
+        total = time.perf_counter() - t0
+        return total, wall, [a.elapsed_time(b) for a, b in evs], ctx.stats()
+
+    tp = timed(g.PERSISTENT, args.steps, args.warmup)
+    counts = r.result()
+    tw = None
+    if not args.no_plain:
+        tw = timed(g.PLAIN, max(3, args.steps // 2), 1)
+        if not (r.result() == counts).all():
+            raise RuntimeError("plain and persistent forms disagree")
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        t1 = time.perf_counter()
+        want = oracle.wordcount(c.paths, c.queries, threads=threads)
+        dt = time.perf_counter() - t1
+        if not (want == counts).all():
+            raise RuntimeError("GPU counts differ from the oracle")
+        cpu = {"value": round(c.total_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": threads,
+               "kind": "oracle", "sample": "one full pass over the 2,000-file corpus "
+                                           "(files split over %d POSIX threads)" % threads}
+    total, wall, kern_ms, st = tp
+    steps = len(wall)
+    gbps = c.total_bytes * steps / total / 1e9
+    kavg = float(np.mean(kern_ms))
+    link_bytes = st["bytes_in"] / steps        # bytes the host delivered per pass
+    achieved = link_bytes / (kavg * 1e-3) / 1e9
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(gbps, 3), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * total / steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "word search: 2,000 files, log-normal sizes (median 64 KiB, "
+                               "sigma 1, cap 8 MiB), Zipf(1.1) words from a 50k vocabulary, "
+                               "64 queries, 1 MiB chunk preads", "form": "persistent",
+                   "files": len(c.paths), "bytes": c.total_bytes, "chunks": r.n_chunks},
+        "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
+        "syscalls_per_s": round(st["host_calls"] / total, 1),
+        "step_ms_p50": round(1e3 * percentile(wall, 50), 3),
+        "step_ms_p99": round(1e3 * percentile(wall, 99), 3),
+        "roofline": {"bound": "host-link", "achieved": round(achieved, 2), "peak": LINK_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / LINK_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "wordscan_persistent", "kernel_ms": round(kavg, 3),
+                     "bytes_per_launch": int(link_bytes)},
+    }
+    if tw:
+        pt, pw, pk, _ = tw
+        res["plain_form"] = {"value": round(c.total_bytes * len(pw) / pt / 1e9, 3), "unit": "GB/s",
+                             "ms_per_step": round(1e3 * pt / len(pw), 3)}
+    if cpu:
+        res["cpu_baseline"] = cpu
+    r.close()
     ctx.shutdown()
     print(json.dumps(res), flush=True)
 

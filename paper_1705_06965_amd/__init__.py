@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgsys.so")
+LIB_PATH = os.environ.get("GSYS_LIB") or os.path.join(_HERE, "libgsys.so")
 
 ABI_VERSION = 1
 

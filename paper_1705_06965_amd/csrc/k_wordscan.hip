@@ -7,13 +7,18 @@
 // Files are cut into chunks of at most chunk_max bytes.  A chunk is read with
 // one pread that also fetches the byte before it (to tell whether the chunk
 // starts inside a token) and OVERLAP bytes after it (to finish the last
-// token); a token belongs to the chunk in which it starts.  Chunks are taken
-// from a device work counter.  Each chunk is scanned from LDS: the work-group
-// streams 16 KiB sub-blocks of host staging into LDS with fully coalesced
-// 16-byte loads, every lane scans a 64-byte stretch (finishing the token it
-// opened past the stretch), and a completed token of at most OVERLAP bytes
-// is looked up in an LDS hash table of the queries by FNV-1a-64 and confirmed
-// byte by byte; matches are counted with LDS atomics and flushed per chunk.
+// token); a token belongs to the chunk in which it starts.  The persistent
+// form takes chunks from a device work counter and prefetches the next one.
+//
+// Each chunk is scanned from LDS in 16 KiB sub-blocks, streamed from host
+// staging with fully coalesced 16-byte loads (the next sub-block's loads are
+// in flight while the current one is scanned).  Every lane owns a 64-byte
+// stretch: it builds a 64-bit delimiter mask with byte-parallel compares,
+// walks the token starts in its stretch with count-trailing-zeros, and for a
+// token of at most 16 bytes assembles its bytes from aligned LDS words with
+// alignbyte.  The (zero-padded) 16 bytes and the length are looked up in an
+// LDS hash table of the queries and compared exactly; matches are counted in
+// per-wavefront LDS counters and added to counts[file] once per chunk.
 #include "gsys_device.hpp"
 #include "gsys.h"
 #include "kernels.hpp"
@@ -30,15 +35,10 @@ constexpr uint32_t kSB = kWG * kSeg;          // 16 KiB sub-block
 constexpr uint32_t kOverlap = 16;             // max query length and read-ahead
 constexpr uint32_t kHead = 16;                // staging bytes before chunk byte 0
 constexpr uint32_t kCopy = kSB + 48;          // LDS bytes per sub-block (look-behind + halo)
+constexpr uint32_t kCopyVec = kCopy / 16;     // 16-byte loads per sub-block
+constexpr uint32_t kPerLane = (kCopyVec + kWG - 1) / kWG;
 constexpr uint32_t kMaxQ = 64;
 constexpr uint32_t kTab = 128;                // query hash table slots
-
-__device__ __forceinline__ bool is_delim(uint32_t b) { return b == 0x20u || b == 0x0au; }
-
-__device__ __forceinline__ uint64_t fnv_byte(uint64_t h, uint32_t byte) {
-  h ^= byte;
-  return (h << 40) + h * 0x1b3ull;
-}
 
 struct WsArgs {
   gsys_dev_ctx c;
@@ -47,7 +47,7 @@ struct WsArgs {
   const uint32_t* qlens;
   uint32_t* counts;         // nfiles x nq
   unsigned int* work;       // device work counter (zeroed per launch)
-  uint64_t staging;         // 2 buffers per work-group of `cbuf` bytes
+  uint64_t staging;         // chunk buffers of `cbuf` bytes
   uint32_t cbuf;
   uint32_t n_chunks;
   uint32_t nq;
@@ -55,59 +55,67 @@ struct WsArgs {
 
 struct Shared {
   uint8_t buf[kCopy];
-  uint64_t thash[kTab];
-  int32_t tq[kTab];
-  uint8_t qb[kMaxQ * 16];
-  uint32_t ql[kMaxQ];
-  uint32_t cnt[kMaxQ];
+  uint4 qw[kTab];           // query bytes per slot, zero-padded to 16
+  uint32_t tkey[kTab];      // hash key per slot; 0 = empty
+  int32_t tq[kTab];         // query index | length << 16 per slot
+  uint32_t cnt[kWG / 64][kMaxQ];
   uint32_t next;
 };
 
+// Key of a token or query: its (zero-padded) 16 bytes and length mixed into
+// 32 bits; never 0.  Equal strings have equal keys; a key match is confirmed
+// by comparing all 16 bytes and the length.
+__device__ __forceinline__ uint32_t token_key(uint4 w, uint32_t len) {
+  uint32_t h = len * 0x9e3779b1u;
+  h = (h ^ w.x) * 0x85ebca6bu;
+  h = (h ^ (h >> 15) ^ w.y) * 0xc2b2ae35u;
+  h = (h ^ (h >> 13) ^ w.z) * 0x27d4eb2fu;
+  h = (h ^ (h >> 16) ^ w.w) * 0x165667b1u;
+  h ^= h >> 15;
+  return h | 1u;
+}
+
+__device__ __forceinline__ uint32_t mask_bytes(uint32_t x, int32_t keep) {
+  // keep the low `keep` bytes of x (keep <= 0: none, >= 4: all)
+  return keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u)));
+}
+
 __device__ void build_table(const WsArgs& A, Shared& S) {
-  for (uint32_t i = threadIdx.x; i < kMaxQ * 16 / 4; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(S.qb)[i] =
-        i * 4 < A.nq * 16 ? reinterpret_cast<const uint32_t*>(A.queries)[i] : 0u;
-  for (uint32_t i = threadIdx.x; i < kMaxQ; i += blockDim.x) {
-    S.ql[i] = i < A.nq ? A.qlens[i] : 0u;
-    S.cnt[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kTab; i += blockDim.x) {
+    S.tkey[i] = 0;
+    S.tq[i] = -1;
   }
-  for (uint32_t i = threadIdx.x; i < kTab; i += blockDim.x) S.tq[i] = -1;
+  for (uint32_t i = threadIdx.x; i < (kWG / 64) * kMaxQ; i += blockDim.x) (&S.cnt[0][0])[i] = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (uint32_t q = 0; q < A.nq; ++q) {
-      uint64_t h = 0xcbf29ce484222325ull;
-      for (uint32_t k = 0; k < S.ql[q]; ++k) h = fnv_byte(h, S.qb[q * 16 + k]);
-      uint32_t s = (uint32_t)(h ^ (h >> 29)) & (kTab - 1);
-      while (S.tq[s] >= 0) s = (s + 1) & (kTab - 1);
-      S.tq[s] = (int32_t)q;
-      S.thash[s] = h;
+      const uint32_t len = A.qlens[q];
+      const uint32_t* qp = reinterpret_cast<const uint32_t*>(A.queries + q * 16);
+      uint4 w = make_uint4(mask_bytes(qp[0], (int32_t)len), mask_bytes(qp[1], (int32_t)len - 4),
+                           mask_bytes(qp[2], (int32_t)len - 8), mask_bytes(qp[3], (int32_t)len - 12));
+      const uint32_t k = token_key(w, len);
+      uint32_t s = k & (kTab - 1);
+      while (S.tkey[s]) s = (s + 1) & (kTab - 1);
+      S.tkey[s] = k;
+      S.tq[s] = (int32_t)(q | (len << 16));
+      S.qw[s] = w;
     }
   }
   __syncthreads();
 }
 
-// token [start, start + len) of the LDS buffer (buffer index, not position)
-__device__ __forceinline__ void probe(Shared& S, uint64_t h, uint32_t len, uint32_t start) {
-  uint32_t s = (uint32_t)(h ^ (h >> 29)) & (kTab - 1);
-  for (uint32_t n = 0; n < kTab; ++n) {
-    const int32_t q = S.tq[s];
-    if (q < 0) return;
-    if (S.thash[s] == h && S.ql[q] == len) {
-      bool eq = true;
-      for (uint32_t k = 0; k < len; ++k) eq &= S.buf[start + k] == S.qb[q * 16 + k];
-      if (eq) {
-        atomicAdd(&S.cnt[q], 1u);
-        return;
-      }
-    }
-    s = (s + 1) & (kTab - 1);
-  }
+// 4-bit mask of the bytes of x equal to space or newline (bit j = byte j).
+__device__ __forceinline__ uint32_t delim4(uint32_t x) {
+  auto zero_bytes = [](uint32_t v) {  // 0x80 in every byte of v that is zero
+    return ~(((v & 0x7f7f7f7fu) + 0x7f7f7f7fu) | v) & 0x80808080u;
+  };
+  const uint32_t z = zero_bytes(x ^ 0x20202020u) | zero_bytes(x ^ 0x0a0a0a0au);
+  return ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u);
 }
 
-// Issue the pread of chunk `ci` into staging buffer `slot` (work-group
-// granularity, relaxed: a consumer call, non-blocking).  The buffer holds
-// byte k of the chunk at kHead + k and the byte before the chunk at
-// kHead - 1.
+// Staging buffer `slot` holds one chunk: byte k of the chunk at kHead + k and
+// the byte before the chunk at kHead - 1.  Issue its pread (work-group
+// granularity, relaxed: a consumer call, non-blocking).
 __device__ Ticket issue_chunk(const WsArgs& A, uint32_t ci, uint64_t slot) {
   const gsys_chunk ch = A.chunks[ci];
   const uint32_t lb = ch.off > 0 ? 1u : 0u;
@@ -118,6 +126,19 @@ __device__ Ticket issue_chunk(const WsArgs& A, uint32_t ci, uint64_t slot) {
   return tk;
 }
 
+// Load this lane's share of the sub-block at chunk byte sb0 (staging bytes
+// [sb0, sb0 + kCopy) of the chunk buffer) into registers.
+__device__ __forceinline__ void load_sub(const uint8_t* stg, uint32_t cbuf, uint32_t sb0,
+                                         uint4 (&v)[kPerLane]) {
+#pragma unroll
+  for (uint32_t k = 0; k < kPerLane; ++k) {
+    const uint32_t i = threadIdx.x + k * kWG;
+    v[k] = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
+    if (i < kCopyVec && sb0 + i * 16 + 16 <= cbuf)
+      v[k] = *reinterpret_cast<const uint4*>(stg + sb0 + i * 16);
+  }
+}
+
 __device__ void scan_chunk(const WsArgs& A, Shared& S, uint32_t ci, uint64_t slot, int64_t ret) {
   const gsys_chunk ch = A.chunks[ci];
   const uint32_t lb = ch.off > 0 ? 1u : 0u;
@@ -125,44 +146,80 @@ __device__ void scan_chunk(const WsArgs& A, Shared& S, uint32_t ci, uint64_t slo
   const int64_t ext = ret > (int64_t)lb ? ret - (int64_t)lb : 0;
   const bool lb_ok = lb && ret >= 1;
   const uint8_t* stg = reinterpret_cast<const uint8_t*>(A.staging) + slot * A.cbuf;
+  const uint32_t wave = threadIdx.x >> 6;
+  uint4 v[kPerLane];
+  if (ch.len) load_sub(stg, A.cbuf, 0, v);
   for (uint32_t sb0 = 0; sb0 < ch.len; sb0 += kSB) {
     // LDS buf[i] = staging[sb0 + i], i.e. chunk position sb0 + i - kHead
-    for (uint32_t i = threadIdx.x; i < kCopy / 16; i += blockDim.x) {
-      uint4 v = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
-      if (sb0 + i * 16 + 16 <= A.cbuf) v = *reinterpret_cast<const uint4*>(stg + sb0 + i * 16);
-      *reinterpret_cast<uint4*>(S.buf + i * 16) = v;
+#pragma unroll
+    for (uint32_t k = 0; k < kPerLane; ++k) {
+      const uint32_t i = threadIdx.x + k * kWG;
+      if (i < kCopyVec) *reinterpret_cast<uint4*>(S.buf + i * 16) = v[k];
     }
     __syncthreads();
+    if (sb0 + kSB < ch.len) load_sub(stg, A.cbuf, sb0 + kSB, v);  // in flight during the scan
     const int64_t sb_ext = ext - (int64_t)sb0;                   // valid positions: p < sb_ext
     const uint32_t own = min(kSB, ch.len - sb0);                 // tokens may start at p < own
     const uint32_t p0 = threadIdx.x * kSeg;
     if (p0 < own) {
-      const uint32_t own_end = min(p0 + kSeg, own);
-      auto byte_at = [&](int64_t p) -> uint32_t {
-        if (p < 0) return (sb0 == 0 && !lb_ok) ? 0x20u : S.buf[kHead + p];
-        return p < sb_ext ? S.buf[kHead + p] : 0x20u;
-      };
-      bool skip = !is_delim(byte_at((int64_t)p0 - 1));  // a token that started before p0
-      uint32_t len = 0, start = 0;
-      uint64_t h = 0;
-      for (uint32_t p = p0; p < own_end + kOverlap; ++p) {
-        if (p >= own_end && len == 0 && !skip) break;
-        const uint32_t b = byte_at(p);
-        if (is_delim(b)) {
-          if (len && !skip && len <= kOverlap) probe(S, h, len, kHead + start);
-          skip = false;
-          len = 0;
-          if (p >= own_end) break;
-        } else if (skip) {
-          // still inside the previous stretch's token
-        } else {
-          if (len == 0) {
-            if (p >= own_end) break;
-            h = 0xcbf29ce484222325ull;
-            start = p;
+      // delimiter masks: bit i of dlo = position p0 + i, bit i of dhi =
+      // position p0 + 64 + i (read-ahead); bytes past the valid extent count
+      // as delimiters, and so does position 80 (a sentinel)
+      const uint32_t* bw = reinterpret_cast<const uint32_t*>(S.buf + kHead + p0);
+      uint64_t dlo = 0;
+      uint32_t dhi = 0;
+#pragma unroll
+      for (uint32_t d = 0; d < 16; ++d) dlo |= (uint64_t)delim4(bw[d]) << (4 * d);
+#pragma unroll
+      for (uint32_t d = 0; d < 4; ++d) dhi |= delim4(bw[16 + d]) << (4 * d);
+      const int64_t vlen = sb_ext - (int64_t)p0;  // valid bytes from p0 on
+      if (vlen < 64) dlo |= vlen <= 0 ? ~0ull : (~0ull << vlen);
+      if (vlen < 80) dhi |= vlen <= 64 ? 0xffffu : (0xffffu << (vlen - 64));
+      dhi |= 1u << 16;
+      uint32_t prev_delim;  // position p0 - 1
+      if (sb0 == 0 && p0 == 0) prev_delim = lb_ok ? (delim4(S.buf[kHead - 1]) & 1u) : 1u;
+      else if ((int64_t)p0 - 1 >= sb_ext) prev_delim = 1u;
+      else prev_delim = delim4(S.buf[kHead + p0 - 1]) & 1u;
+      const uint32_t own_n = min(kSeg, own - p0);
+      const uint64_t own_mask = own_n >= 64 ? ~0ull : ((1ull << own_n) - 1ull);
+      uint64_t starts = ~dlo & ((dlo << 1) | prev_delim) & own_mask;
+      while (starts) {
+        const uint32_t s = (uint32_t)__builtin_ctzll(starts);
+        starts &= starts - 1;
+        // first delimiter at or after s
+        const uint64_t after = s < 64 ? (dlo >> s) : 0ull;
+        uint32_t len;
+        if (after) len = (uint32_t)__builtin_ctzll(after);
+        else len = (64 - s) + (uint32_t)__builtin_ctz(dhi);
+        if (len > kOverlap) continue;
+        // the token's bytes, from aligned LDS words
+        const uint32_t bpos = kHead + p0 + s;
+        const uint32_t* aw = reinterpret_cast<const uint32_t*>(S.buf + (bpos & ~3u));
+        const uint32_t sh = bpos & 3u;
+        const uint32_t a0 = aw[0], a1 = aw[1], a2 = aw[2], a3 = aw[3], a4 = aw[4];
+        uint4 w = make_uint4(__builtin_amdgcn_alignbyte(a1, a0, sh),
+                             __builtin_amdgcn_alignbyte(a2, a1, sh),
+                             __builtin_amdgcn_alignbyte(a3, a2, sh),
+                             __builtin_amdgcn_alignbyte(a4, a3, sh));
+        w.x = mask_bytes(w.x, (int32_t)len);
+        w.y = mask_bytes(w.y, (int32_t)len - 4);
+        w.z = mask_bytes(w.z, (int32_t)len - 8);
+        w.w = mask_bytes(w.w, (int32_t)len - 12);
+        const uint32_t k = token_key(w, len);
+        uint32_t t = k & (kTab - 1);
+        for (uint32_t n = 0; n < kTab; ++n) {
+          const uint32_t tk = S.tkey[t];
+          if (!tk) break;
+          if (tk == k) {
+            const uint4 q = S.qw[t];
+            const int32_t tq = S.tq[t];
+            if (q.x == w.x && q.y == w.y && q.z == w.z && q.w == w.w &&
+                (uint32_t)(tq >> 16) == len) {
+              atomicAdd(&S.cnt[wave][tq & 0xffff], 1u);
+              break;
+            }
           }
-          h = fnv_byte(h, b);
-          ++len;
+          t = (t + 1) & (kTab - 1);
         }
       }
     }
@@ -170,9 +227,13 @@ __device__ void scan_chunk(const WsArgs& A, Shared& S, uint32_t ci, uint64_t slo
   }
   // flush this chunk's counts
   for (uint32_t q = threadIdx.x; q < A.nq; q += blockDim.x) {
-    const uint32_t v = S.cnt[q];
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kWG / 64; ++w) {
+      v += S.cnt[w][q];
+      S.cnt[w][q] = 0;
+    }
     if (v) atomicAdd(&A.counts[(uint64_t)ch.file * A.nq + q], v);
-    S.cnt[q] = 0;
   }
   __syncthreads();
 }

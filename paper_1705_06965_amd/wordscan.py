@@ -32,7 +32,7 @@ def staging_bytes(chunk_max: int, n_buffers: int) -> int:
 
 class WordScanRunner:
     def __init__(self, ctx, paths, queries, chunk_max: int = 1 << 20, device: str = "cuda",
-                 persistent_buffers: int = 256):
+                 persistent_buffers: int = 0):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -57,6 +57,8 @@ class WordScanRunner:
         self.queries = torch.from_numpy(q).to(device)
         self.qlens = torch.from_numpy(ql.view(np.int32)).to(device)
         self.counts = torch.zeros(max(1, self.nfiles * self.nq), dtype=torch.int32, device=device)
+        if not persistent_buffers:
+            persistent_buffers = int(os.environ.get("GSYS_WS_BUFFERS", "256"))
         self.persistent_bytes = staging_bytes(chunk_max, min(persistent_buffers,
                                                              2 * max(1, self.n_chunks)))
         self.plain_bytes = staging_bytes(chunk_max, max(1, self.n_chunks))
