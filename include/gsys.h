@@ -264,6 +264,53 @@ int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
                   uint64_t staging, uint64_t staging_bytes, uint32_t form, void *stream);
 
 /*
+ * Key-value GET server (the network case study of section 7.3: GPU
+ * recvfrom / sendto at work-group granularity, blocking, relaxed).
+ *
+ * gsys_kv_build fills `table` (device, cap x 32-byte buckets) with the n keys
+ * (device uint8[n * 16]); voff / vlen (device uint64[n] / uint32[n]) locate
+ * each value in a device heap, 16-byte aligned, at most 1024 bytes.  Open
+ * addressing: bucket = floor(FNV-1a-64(key) * cap / 2^64), linear probing.
+ * Keys must be distinct; n <= cap.
+ *
+ * gsys_kv_serve launches the persistent server on the UDP socket `fd`
+ * (allowed with GSYS_FD_SOCK, bound by the caller to 127.0.0.1).  Request
+ * datagram (32 B): u64 id; u8 op (1 = GET); u8 pad[7]; u8 key[16].  Reply
+ * (16 + len B): u64 id; u8 status (0 hit, 1 miss, 2 bad request); u8 pad;
+ * u16 len; u32 pad; value[len]; sent to the request's source address.
+ * Each work-group receives up to `batch` (<= 256) datagrams per recvfrom
+ * list call.  io: registered GSYS_BUF_HOST region of io_bytes, at least
+ * gsys_kv_io_bytes() per work-group (the grid shrinks to fit; grid 0 =
+ * as many as fit and are resident).  stop: registered host word; the server
+ * exits when it reads nonzero, or after lifetime_ms (0 = 60 s).  served:
+ * device uint64 incremented by the number of datagrams answered.
+ * Returns after the launch; the caller sets *stop and synchronises.
+ * Errors: -EINVAL, -EFAULT, -ENODEV.
+ */
+int gsys_kv_build(gsys_ctx *ctx, uint64_t table, uint64_t cap, uint64_t keys, uint64_t voff,
+                  uint64_t vlen, uint64_t n, void *stream);
+uint64_t gsys_kv_io_bytes(void);
+int gsys_kv_serve(gsys_ctx *ctx, int fd, uint64_t table, uint64_t cap, uint64_t heap, uint64_t io,
+                  uint64_t io_bytes, uint64_t stop, uint64_t served, uint32_t batch, uint32_t grid,
+                  uint64_t lifetime_ms, void *stream);
+
+/*
+ * UDP load generator for the key-value server (the CPU load generator of
+ * section 7.3).  `threads` client threads, each with its own loopback socket
+ * and a contiguous slice of the n requests (req_len bytes each, request k
+ * must carry id k + 1 in its first 8 bytes), keep up to `window` requests
+ * outstanding, store reply k at replies + k * reply_stride (its length in
+ * reply_len[k], and the time from first send to reply in lat_ns[k] if
+ * lat_ns is not NULL), and retransmit after rto_ns (0 = 20 ms).  Returns the
+ * number of requests answered, or -errno (-ETIMEDOUT after timeout_ns, 0 =
+ * 60 s) when some are missing.  *retransmits (if not NULL) counts resends.
+ */
+int64_t gsys_kv_loadgen(uint32_t server_port, const uint8_t *reqs, uint32_t req_len, uint64_t n,
+                        uint32_t threads, uint32_t window, uint64_t rto_ns, uint64_t timeout_ns,
+                        uint8_t *replies, uint32_t reply_stride, uint32_t *reply_len,
+                        uint64_t *lat_ns, uint64_t *retransmits);
+
+/*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable
  * address: registered host memory or HBM); one kernel computes

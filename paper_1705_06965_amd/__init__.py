@@ -109,13 +109,21 @@ _SIGS = {
     "gsys_wordscan": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64,
                                 C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
                                 C.c_uint32, _P]),
+    "gsys_kv_build": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                C.c_uint64, _P]),
+    "gsys_kv_io_bytes": (C.c_uint64, []),
+    "gsys_kv_serve": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
+                                C.c_uint64, _P]),
+    "gsys_kv_loadgen": (C.c_int64, [C.c_uint32, _P, C.c_uint32, C.c_uint64, C.c_uint32,
+                                    C.c_uint32, C.c_uint64, C.c_uint64, _P, C.c_uint32, _P, _P,
+                                    _P]),
     "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                     C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),
     "gsys_test_claim_only": (C.c_int64, [_P, C.c_uint32]),
     "gsys_test_ring_ctl": (C.c_int, [_P, _P, C.c_uint64]),
 }
-_OPTIONAL = {"gsys_wordscan", "gsys_kvget", "gsys_serve"}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libgsys.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)

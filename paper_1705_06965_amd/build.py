@@ -18,7 +18,7 @@ ARCH = os.environ.get("GSYS_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["k_fnv.hip", "k_wordscan.hip", "k_kv.hip", "k_serve.hip"]
 HOST_HIP_SOURCES = ["capi.cpp"]      # host code that calls the HIP runtime
-HOST_SOURCES = ["host_pool.cpp"]     # plain C++17 + POSIX
+HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp"]     # plain C++17 + POSIX
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

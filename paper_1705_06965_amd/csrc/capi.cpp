@@ -39,6 +39,7 @@ struct gsys_ctx {
   uint8_t* arena = nullptr;
   uint64_t arena_bytes = 0;
   uint64_t timeout_ticks = 0;
+  uint64_t wall_khz = 100000;
   uint32_t sleep_max = 16;
   uint32_t grid_override = 0;
   int cu_count = 0;
@@ -174,8 +175,10 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
     c->cu_count = prop.multiProcessorCount;
     int wall_khz = 0;
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess &&
-        wall_khz > 0)
+        wall_khz > 0) {
       c->timeout_ticks = (uint64_t)((double)tmo * 1e-9 * (double)wall_khz * 1e3);
+      c->wall_khz = (uint64_t)wall_khz;
+    }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void**)&c->dev_words, 64 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->dev_words, 0, 64 * sizeof(unsigned long long)) != hipSuccess ||
@@ -544,6 +547,8 @@ uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t
 }
 
 uint32_t persistent_grid_override(gsys_ctx* c) { return c->grid_override; }
+
+uint64_t ticks_per_ms(gsys_ctx* c) { return c->wall_khz; }
 
 uint64_t hash_words(std::initializer_list<uint64_t> w) {
   uint64_t h = 0x9e3779b97f4a7c15ull;

@@ -1,0 +1,259 @@
+// Key-value GET server on the GPU over loopback UDP: the network case study
+// of section 7.3 (a server whose GPU part receives and answers datagrams with
+// recvfrom / sendto at work-group granularity, blocking, relaxed), serving GET
+// requests from a GPU-resident hash table instead of echoing.
+//
+// Request datagram (32 B): u64 id; u8 op (1 = GET); u8 pad[7]; u8 key[16].
+// Reply datagram (16 + len B): u64 id; u8 status (0 hit, 1 miss, 2 bad
+// request); u8 pad; u16 len; u32 pad; value[len].  A request of any other
+// length or op gets status 2 with the id taken from its first 8 bytes (0 if
+// shorter).
+//
+// Table: open addressing in HBM, bucket = floor(hash * cap / 2^64) with
+// hash = FNV-1a-64 of the key, linear probing; 32-byte buckets.  Values live
+// in an HBM heap, each 16-byte aligned.
+//
+// Server loop of one work-group: a recvfrom list call of 256 datagrams
+// (relaxed consumer, blocking: the group waits for it), lookups by every lane
+// that got a datagram, replies copied by whole wavefronts into pinned host
+// staging (one reply per step, 64 lanes x 16 B, coalesced), then a sendto
+// list call (relaxed producer, blocking: the barrier comes before it and only
+// the caller's wavefront waits).
+#include "gsys_device.hpp"
+#include "gsys.h"
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace gsys_kv {
+
+using namespace gsys;
+
+constexpr uint32_t kWG = 256;
+constexpr uint32_t kReqBuf = 64;              // bytes per received datagram slot
+constexpr uint32_t kRepBuf = 1040;            // bytes per reply slot (16 + 1024)
+
+struct Bucket {
+  uint64_t k0, k1;   // key bytes 0..7, 8..15 (little-endian words)
+  uint64_t voff;     // heap offset (16-byte aligned)
+  uint32_t vlen;
+  uint32_t used;
+};
+static_assert(sizeof(Bucket) == 32, "bucket is 32 bytes");
+
+// Per-work-group I/O region in pinned host memory.
+constexpr uint32_t kOffRecvList = 0;
+constexpr uint32_t kOffSendList = kOffRecvList + kWG * sizeof(gsys_netdesc);
+constexpr uint32_t kOffRecv = kOffSendList + kWG * sizeof(gsys_netdesc);
+constexpr uint32_t kOffSend = kOffRecv + kWG * kReqBuf;
+constexpr uint32_t kIoBytes = kOffSend + kWG * kRepBuf;
+
+__device__ __forceinline__ uint64_t fnv16(uint64_t k0, uint64_t k1) {
+  uint64_t h = 0xcbf29ce484222325ull;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    h ^= (k0 >> (8 * i)) & 0xffu;
+    h *= 0x100000001b3ull;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    h ^= (k1 >> (8 * i)) & 0xffu;
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+__global__ void zero_u64(uint64_t* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void kv_build(Bucket* tab, uint64_t cap, const uint8_t* keys, const uint64_t* voff,
+                         const uint32_t* vlen, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k0 = reinterpret_cast<const uint64_t*>(keys)[2 * i];
+  const uint64_t k1 = reinterpret_cast<const uint64_t*>(keys)[2 * i + 1];
+  uint64_t b = __umul64hi(fnv16(k0, k1), cap);
+  for (uint64_t n_probe = 0; n_probe < cap; ++n_probe) {
+    if (atomicCAS(&tab[b].used, 0u, 1u) == 0u) {
+      tab[b].k0 = k0;
+      tab[b].k1 = k1;
+      tab[b].voff = voff[i];
+      tab[b].vlen = vlen[i];
+      return;
+    }
+    b = b + 1 == cap ? 0 : b + 1;
+  }
+}
+
+struct KvArgs {
+  gsys_dev_ctx c;
+  const Bucket* tab;
+  uint64_t cap;
+  const uint8_t* heap;
+  uint64_t io;                     // base of the work-groups' I/O regions
+  const uint64_t* stop;            // host-coherent: nonzero = exit
+  unsigned long long* served;      // device: datagrams answered
+  uint64_t lifetime_ticks;         // the server exits after this long regardless
+  int32_t fd;
+  uint32_t batch;                  // datagrams per recvfrom list (<= 256)
+};
+
+__global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
+  __shared__ int s_stop;
+  uint8_t* io = reinterpret_cast<uint8_t*>(A.io) + (uint64_t)blockIdx.x * kIoBytes;
+  gsys_netdesc* rl = reinterpret_cast<gsys_netdesc*>(io + kOffRecvList);
+  gsys_netdesc* sl = reinterpret_cast<gsys_netdesc*>(io + kOffSendList);
+  uint8_t* rbuf = io + kOffRecv;
+  uint8_t* sbuf = io + kOffSend;
+  const uint64_t rbase = A.io + (uint64_t)blockIdx.x * kIoBytes + kOffRecv;
+  const uint64_t sbase = A.io + (uint64_t)blockIdx.x * kIoBytes + kOffSend;
+  const uint32_t lane = lane_id();
+  const uint32_t tid = threadIdx.x;
+  uint32_t idle = 0;
+  const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
+  for (;;) {
+    if (tid == 0) s_stop = ld_sys(A.stop) != 0 || wall_clock64() > t_end;
+    __syncthreads();
+    if (s_stop) break;
+    // receive list: the caller's wavefront writes it (consumer call: no
+    // barrier before it)
+    if (tid < 64)
+      for (uint32_t i = tid; i < A.batch; i += 64) {
+        gsys_netdesc d{};
+        d.buf_off = i * kReqBuf;
+        d.len_ret = (int32_t)kReqBuf;
+        rl[i] = d;
+      }
+    Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)rl, A.batch, rbase, 0, 0}};
+    call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra);
+    // datagrams arrive as a prefix of the list (the host stops at -EAGAIN)
+    int32_t got = tid < A.batch ? __hip_atomic_load(&rl[tid].len_ret, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_SYSTEM)
+                                : -1;
+    const bool have = got >= 0;
+    const uint32_t n = (uint32_t)__syncthreads_count(have);
+    if (n == 0) {
+      // empty socket: back off before asking again
+      if (tid == 0) {
+        const uint32_t reps = 1u << min(idle, 8u);
+        for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(8);
+      }
+      ++idle;
+      continue;
+    }
+    idle = 0;
+    // parse and look up
+    uint64_t id = 0, voff = 0;
+    uint32_t status = 2, vlen = 0;
+    if (have) {
+      const uint8_t* q = rbuf + tid * kReqBuf;
+      const uint4 w0 = *reinterpret_cast<const uint4*>(q);
+      const uint4 w1 = *reinterpret_cast<const uint4*>(q + 16);
+      if (got >= 8) id = ((uint64_t)w0.y << 32) | w0.x;
+      if (got == 32 && (w0.z & 0xffu) == 1u) {
+        const uint64_t k0 = ((uint64_t)w1.y << 32) | w1.x;
+        const uint64_t k1 = ((uint64_t)w1.w << 32) | w1.z;
+        uint64_t b = __umul64hi(fnv16(k0, k1), A.cap);
+        status = 1;
+        for (uint64_t p = 0; p < A.cap; ++p) {
+          const Bucket* bk = A.tab + b;
+          if (!bk->used) break;
+          if (bk->k0 == k0 && bk->k1 == k1) {
+            status = 0;
+            voff = bk->voff;
+            vlen = bk->vlen;
+            break;
+          }
+          b = b + 1 == A.cap ? 0 : b + 1;
+        }
+      }
+      // reply descriptor: back to the sender recvfrom reported
+      gsys_netdesc d;
+      d.buf_off = tid * kRepBuf;
+      d.len_ret = (int32_t)(16 + vlen);
+      d.addr_len = rl[tid].addr_len;
+      d.pad = 0;
+      const uint4 a = *reinterpret_cast<const uint4*>(rl[tid].addr);
+      *reinterpret_cast<uint4*>(d.addr) = a;
+      sl[tid] = d;
+    }
+    // replies: one wavefront copies one reply per step, 16 B per lane
+    uint64_t m = __ballot(have);
+    while (m) {
+      const uint32_t j = first_lane(m);
+      m &= m - 1;
+      const uint64_t jid = bcast64(id, j);
+      const uint64_t jvoff = bcast64(voff, j);
+      const uint32_t jst = __builtin_amdgcn_readlane(status, j);
+      const uint32_t jlen = __builtin_amdgcn_readlane(vlen, j);
+      uint8_t* dst = sbuf + (uint64_t)((tid & ~63u) + j) * kRepBuf;
+      const uint32_t chunks = 1 + (jlen + 15) / 16;
+      for (uint32_t c = lane; c < chunks; c += 64) {
+        uint4 v;
+        if (c == 0) {
+          v = make_uint4((uint32_t)jid, (uint32_t)(jid >> 32), jst | (jlen << 16), 0u);
+        } else {
+          v = *reinterpret_cast<const uint4*>(A.heap + jvoff + 16 * (c - 1));
+        }
+        *reinterpret_cast<uint4*>(dst + 16 * c) = v;
+      }
+    }
+    // send the replies (producer call: every lane's reply is released before)
+    Args6 sa{{(uint64_t)(int64_t)A.fd, (uint64_t)sl, n, sbase, 0, 0}};
+    call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa);
+    if (tid == 0) atomicAdd(A.served, (unsigned long long)n);
+    // the caller's wavefront waited for the sends; the rest wait here before
+    // the buffers are reused
+    __syncthreads();
+  }
+}
+
+}  // namespace gsys_kv
+
+using namespace gsys_kv;
+
+int gsys_kv_build(gsys_ctx* ctx, uint64_t table, uint64_t cap, uint64_t keys, uint64_t voff,
+                  uint64_t vlen, uint64_t n, void* stream) {
+  if (!ctx || !table || !cap || (n && (!keys || !voff || !vlen))) return -EINVAL;
+  if (n > cap) return -EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(zero_u64, dim3((uint32_t)std::min<uint64_t>((cap + 255) / 256, 65535)),
+                     dim3(256), 0, s, (uint64_t*)table, cap * 4);
+  if (n)
+    hipLaunchKernelGGL(kv_build, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, (Bucket*)table,
+                       cap, (const uint8_t*)keys, (const uint64_t*)voff, (const uint32_t*)vlen, n);
+  return hipGetLastError() == hipSuccess ? 0 : -ENODEV;
+}
+
+uint64_t gsys_kv_io_bytes(void) { return kIoBytes; }
+
+int gsys_kv_serve(gsys_ctx* ctx, int fd, uint64_t table, uint64_t cap, uint64_t heap, uint64_t io,
+                  uint64_t io_bytes, uint64_t stop, uint64_t served, uint32_t batch, uint32_t grid,
+                  uint64_t lifetime_ms, void* stream) {
+  if (!ctx || !table || !cap || !heap || !stop || !served) return -EINVAL;
+  if (batch == 0 || batch > kWG) return -EINVAL;
+  if (gsys_internal::check_host_range(ctx, io, io_bytes)) return -EFAULT;
+  if (gsys_internal::check_host_range(ctx, stop, 8)) return -EFAULT;
+  uint32_t fit = (uint32_t)std::min<uint64_t>(io_bytes / kIoBytes, 0x7fffffffull);
+  uint32_t res = gsys_internal::resident_grid(ctx, (const void*)kv_serve, kWG, 0);
+  if (!res) return -ENODEV;
+  if (!grid || grid > fit) grid = fit;
+  if (grid > res) grid = res;
+  if (!grid) return -EINVAL;
+  KvArgs A;
+  if (int e = gsys_device_ctx(ctx, &A.c)) return e;
+  A.tab = (const Bucket*)table;
+  A.cap = cap;
+  A.heap = (const uint8_t*)heap;
+  A.io = io;
+  A.stop = (const uint64_t*)stop;
+  A.served = (unsigned long long*)served;
+  A.fd = fd;
+  A.batch = batch;
+  A.lifetime_ticks = gsys_internal::ticks_per_ms(ctx) * (lifetime_ms ? lifetime_ms : 60000);
+  void* args[] = {&A};
+  return gsys_internal::launch(ctx, (const void*)kv_serve, grid, kWG, 0, args, (hipStream_t)stream);
+}

@@ -1,0 +1,82 @@
+"""GPU parity of the key-value GET server (network case study, section 7.3):
+every reply byte-exact against the oracle's reply for that request id,
+including misses and malformed requests."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_06965_amd as g
+    ctx = g.Context(ring_slots=1 << 14, device_timeout_ns=30_000_000_000)
+    yield g, ctx
+    assert ctx.shutdown() == 0
+
+
+@pytest.mark.parametrize("grid,batch", [(1, 256), (8, 64), (32, 256)])
+def test_kv_replies_match_oracle(gs, grid, batch):
+    g, ctx = gs
+    from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
+    kv = synth.kv_set(n_keys=20000, n_req=40000, miss_every=16)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=grid, batch=batch)
+    reqs = make_requests(kv.req_keys)
+    reqs[7, 8] = 9                      # bad op -> status 2
+    say("kv grid", grid, "batch", batch)
+    srv.start(lifetime_ms=60_000)
+    try:
+        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=4, window=64)
+    finally:
+        srv.stop()
+    assert got == len(reqs)
+    served = int(srv.served.cpu().item())
+    assert served >= len(reqs)
+    bad = 0
+    for k in range(len(reqs)):
+        want = ix.reply(reqs[k].tobytes())
+        if rlen[k] != len(want) or replies[k, :rlen[k]].tobytes() != want:
+            bad += 1
+    assert bad == 0
+    srv.close()
+    ix.close()
+
+
+def test_kv_short_and_long_datagrams(gs):
+    """Datagrams that are not 32 bytes get status 2 with their id."""
+    g, ctx = gs
+    import socket
+    from paper_1705_06965_amd.kv import KVServer
+    kv = synth.kv_set(n_keys=1000, n_req=10)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=2, batch=32)
+    cli = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
+    cli.bind(("127.0.0.1", 0))
+    cli.settimeout(5.0)
+    srv.start(lifetime_ms=30_000)
+    try:
+        for d in (b"\x05" * 4, (77).to_bytes(8, "little") + b"\x01" * 8,
+                  (78).to_bytes(8, "little") + b"\x01" + bytes(7) + kv.keys[3].tobytes() + b"xx",
+                  (79).to_bytes(8, "little") + b"\x01" + bytes(7) + kv.keys[3].tobytes()):
+            cli.sendto(d, ("127.0.0.1", srv.port))
+            rep = cli.recv(2048)
+            assert rep == ix.reply(d[:64]), d
+    finally:
+        srv.stop()
+    cli.close()
+    srv.close()
+    ix.close()
