@@ -61,6 +61,9 @@ def lib() -> C.CDLL:
                                       C.c_void_p, C.c_uint64]
         L.oracle_release.restype = C.c_int
         L.oracle_release.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_release_job.restype = C.c_int
+        L.oracle_release_job.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.c_uint64,
+                                         C.c_void_p]
         del u8p
         _lib = L
     return _lib
@@ -165,3 +168,10 @@ def release(nbytes: int, stamp: bytes):
     after = np.zeros((pages, 64), dtype=np.uint8)
     rc = lib().oracle_release(nbytes, _p(s), _p(before), _p(after))
     return rc, before, after
+
+
+def release_job(stamp_fd: int, stamp_off: int, page: int, out_fd: int, out_off: int):
+    """(rc, rets[6]) of one serving-mix memory-release job on the CPU."""
+    rets = np.zeros(6, dtype=np.int64)
+    rc = lib().oracle_release_job(stamp_fd, stamp_off, page, out_fd, out_off, _p(rets))
+    return rc, rets

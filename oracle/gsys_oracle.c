@@ -7,8 +7,9 @@
  *
  * What it computes.  The paper's mechanism forwards a system call made by a
  * GPU work-item, work-group or kernel to the CPU, which executes exactly the
- * call that was requested and hands back its return value (section 3, Fig. 2;
- * section 5, "traditional function-like semantics").  The result of a GPU
+ * call that was requested and hands back its return value, keeping the
+ * semantics of an ordinary function call (section 3, Fig. 2; section 5).
+ * The result of a GPU
  * program that uses such calls is therefore defined as the result of the CPU
  * issuing the same calls itself.  This file is that definition written out:
  * it calls pread/pwrite/recvfrom/sendto/mmap/madvise/munmap directly, in the
@@ -317,5 +318,36 @@ int oracle_release(uint64_t bytes, const uint8_t *stamp, uint8_t *before,
     if (madvise(m, bytes, MADV_DONTNEED) != 0) { int e = errno; munmap(m, bytes); return -e; }
     for (uint64_t p = 0; p < pages; p++) memcpy(after + p * 64, m + p * 4096, 64);
     if (munmap(m, bytes) != 0) return -errno;
+    return 0;
+}
+
+/*
+ * One memory-release job of the serving mix (section 7.2 uses madvise from
+ * the GPU to hand memory back): mmap 2 MiB of private anonymous memory; fill
+ * it with pread from the stamp file at stamp_off; pwrite the first 64 bytes
+ * of page `page` to out_fd at out_off; madvise(MADV_DONTNEED); pwrite the
+ * first 64 bytes of page 0 to out_off + 64; munmap.  The output file then
+ * holds the stamp bytes followed by 64 zero bytes (madvise(2): private
+ * anonymous pages read back as zeros).  rets[0..5] receive the six return
+ * values.  Returns 0 or the first -errno.
+ */
+int oracle_release_job(int stamp_fd, uint64_t stamp_off, uint32_t page, int out_fd,
+                       uint64_t out_off, int64_t *rets)
+{
+    const uint64_t bytes = 2u << 20;
+    uint8_t *m = (uint8_t *)mmap(NULL, bytes, PROT_READ | PROT_WRITE,
+                                 MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (m == MAP_FAILED) { rets[0] = -errno; return (int)rets[0]; }
+    rets[0] = 0;
+    ssize_t r = pread(stamp_fd, m, bytes, (off_t)stamp_off);
+    rets[1] = r < 0 ? -errno : r;
+    r = pwrite(out_fd, m + (uint64_t)page * 4096, 64, (off_t)out_off);
+    rets[2] = r < 0 ? -errno : r;
+    rets[3] = madvise(m, bytes, MADV_DONTNEED) == 0 ? 0 : -errno;
+    r = pwrite(out_fd, m, 64, (off_t)(out_off + 64));
+    rets[4] = r < 0 ? -errno : r;
+    rets[5] = munmap(m, bytes) == 0 ? 0 : -errno;
+    for (int i = 0; i < 6; i++)
+        if (rets[i] < 0) return (int)rets[i];
     return 0;
 }

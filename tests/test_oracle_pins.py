@@ -180,3 +180,28 @@ def test_release_zero_pages_after_dontneed():
         want[0] ^= p & 0xFF
         assert before[p].tobytes() == bytes(want)
     assert not after.any()
+
+
+def test_release_job_stamp_then_zeros(tmpdata):
+    """mmap / pread / pwrite / madvise(MADV_DONTNEED) / pwrite / munmap: the
+    output file holds the stamped bytes of the chosen page, then zeros."""
+    stamp = np.random.default_rng(21).integers(0, 256, 3 << 20, dtype=np.uint8).tobytes()
+    sp = _write(tmpdata, "stamp.bin", stamp)
+    op = os.path.join(tmpdata, "rel_out.bin")
+    sfd = os.open(sp, os.O_RDONLY)
+    ofd = os.open(op, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+    try:
+        for page, soff, ooff in ((0, 0, 0), (511, 4096 * 7, 128), (37, 12345, 4096)):
+            rc, rets = oracle.release_job(sfd, soff, page, ofd, ooff)
+            assert rc == 0
+            assert rets.tolist() == [0, 2 << 20, 64, 0, 64, 0]
+            got = os.pread(ofd, 128, ooff)
+            assert got[:64] == stamp[soff + 4096 * page: soff + 4096 * page + 64]
+            assert got[64:] == bytes(64)
+        # a stamp read past EOF reads fewer bytes; the readback shows it
+        rc, rets = oracle.release_job(sfd, len(stamp) - 4096, 1, ofd, 8192)
+        assert rets[1] == 4096
+        assert os.pread(ofd, 64, 8192) == bytes(64)
+    finally:
+        os.close(sfd)
+        os.close(ofd)
