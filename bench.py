@@ -55,7 +55,8 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/gsys_device.hpp",
+KERNEL_SOURCES = ("paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp",
+                  "paper_1705_06965_amd/csrc/gsys_device.hpp",
                   "include/gsys_abi.h")
 PROFILE = "profiles/fnv4k_persistent_pread_sweep_1g.md"
 

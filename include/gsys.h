@@ -310,6 +310,56 @@ int64_t gsys_kv_loadgen(uint32_t server_port, const uint8_t *reqs, uint32_t req_
                         uint8_t *replies, uint32_t reply_stride, uint32_t *reply_len,
                         uint64_t *lat_ns, uint64_t *retransmits);
 
+/* Serving job record (64 bytes, in host-coherent memory). */
+#define GSYS_JOB_SCAN    0u
+#define GSYS_JOB_PWRITE  1u
+#define GSYS_JOB_RELEASE 2u
+typedef struct gsys_job {
+    uint32_t kind;     /* GSYS_JOB_*                                                  */
+    int32_t  fd;       /* scan: input file; pwrite / release: output file            */
+    uint64_t off;      /* scan / pwrite: file offset; release: output offset (128 B) */
+    uint64_t len;      /* scan: bytes (multiple of 4096); pwrite: bytes;
+                          release: index of the 2 MiB arena block                    */
+    uint64_t src;      /* scan: first digest index; pwrite: offset in the content
+                          pool; release: offset in the stamp file                    */
+    int32_t  aux_fd;   /* release: stamp file                                         */
+    uint32_t page;     /* release: page (0..511) whose first 64 bytes are read back   */
+    uint64_t done;     /* 0 until the GPU finishes the job                            */
+    int64_t  result;   /* scan: bytes read or the first -errno; pwrite: its return
+                          value; release: 0 or the first -errno                       */
+    uint64_t pad;
+} gsys_job;
+
+/*
+ * Serving (continuous batching): run n jobs arriving at arrival_ns[i] after
+ * the start (open loop).  A job is admitted once it has arrived and fewer
+ * than max_inflight admitted jobs are unfinished; latency_ns[i] is the time
+ * from its scheduled arrival to the host seeing it done (queueing included).
+ *
+ * Scan jobs pread their range in 1 MiB pieces (the next piece is prefetched
+ * with a non-blocking call) and store FNV-1a-64 of every 4 KiB block to
+ * digests[src + block].  Pwrite jobs copy content[src .. src + len) (device)
+ * to staging and pwrite it.  Release jobs (the madvise use of section 7.2)
+ * mmap arena block `len` (2 MiB, the context's arena), pread it full from
+ * aux_fd at src, pwrite the first 64 bytes of page `page` to fd at off,
+ * madvise(MADV_DONTNEED), pwrite the first 64 bytes of page 0 to off + 64
+ * (zeros) and munmap.  All calls are work-group granularity, relaxed.
+ *
+ *   form      GSYS_PERSISTENT: resident work-groups claim jobs as they are
+ *             posted; GSYS_PLAIN: one single-work-group launch per job on
+ *             `stream`, in arrival order
+ *   jobs_dev / jobs_host: the same gsys_job[n] in a registered host buffer
+ *             (filled by the caller; done / result are written here)
+ *   staging   registered host buffer, 2 MiB per work-group (the persistent
+ *             grid shrinks to fit; 0 = as many as are resident)
+ * Blocks until every job is done (or timeout_ns, 0 = 120 s: -ETIMEDOUT).
+ * Errors: -EINVAL, -EFAULT, -ENODEV, -ETIMEDOUT.
+ */
+int gsys_serve_run(gsys_ctx *ctx, uint32_t form, uint64_t jobs_dev, void *jobs_host, uint32_t n,
+                   const uint64_t *arrival_ns, uint32_t max_inflight, uint64_t digests,
+                   uint64_t content, uint64_t staging, uint64_t staging_bytes, uint32_t grid,
+                   uint64_t timeout_ns, uint64_t *latency_ns, void *stream);
+
 /*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable

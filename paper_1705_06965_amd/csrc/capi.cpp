@@ -45,6 +45,8 @@ struct gsys_ctx {
   int cu_count = 0;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
+  void* ctl_host = nullptr;
+  void* ctl_dev = nullptr;
 };
 
 namespace {
@@ -123,6 +125,7 @@ void destroy(gsys_ctx* c) {
   host_coherent_free(c, c->ring);
   host_coherent_free(c, c->comp);
   host_coherent_free(c, c->host_words);
+  host_coherent_free(c, c->ctl_host);
   if (c->arena) munmap(c->arena, c->arena_bytes);
   delete c;
 }
@@ -549,6 +552,16 @@ uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t
 uint32_t persistent_grid_override(gsys_ctx* c) { return c->grid_override; }
 
 uint64_t ticks_per_ms(gsys_ctx* c) { return c->wall_khz; }
+
+int control_page(gsys_ctx* c, void** host, uint64_t* dev) {
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->ctl_host) {
+    if (int e = host_coherent(c, 4096, &c->ctl_host, &c->ctl_dev)) return e;
+  }
+  *host = c->ctl_host;
+  *dev = (uint64_t)c->ctl_dev;
+  return 0;
+}
 
 uint64_t hash_words(std::initializer_list<uint64_t> w) {
   uint64_t h = 0x9e3779b97f4a7c15ull;

@@ -1,0 +1,311 @@
+// Serving form: jobs of uneven size arrive over time and are admitted while
+// others are running on the GPU (continuous batching).  Job kinds:
+//   scan    pread a 4 KiB-aligned range of a file in 1 MiB pieces and store
+//           the FNV-1a-64 of every 4 KiB block (the pread microbenchmark's
+//           call and consumer, section 6);
+//   pwrite  copy bytes from an HBM pool to staging and pwrite them (a
+//           producer call, section 4.1);
+//   release mmap a 2 MiB block of the reserved arena, fill it with pread,
+//           pwrite one page's first 64 bytes back, madvise(MADV_DONTNEED),
+//           pwrite page 0's first 64 bytes (now zeros), munmap: the memory
+//           hand-back of section 7.2.
+// Every call is made at work-group granularity with relaxed ordering (the
+// paper's choice for its case studies); scans prefetch the next piece with a
+// non-blocking call.
+//
+// Persistent form: resident work-groups claim posted jobs from a device
+// counter (the host driver posts a job by raising a counter in host-coherent
+// memory) and mark each job done with a system-scope release store.  Plain
+// form: one single-work-group launch per job.
+#include "gsys_device.hpp"
+#include "fnv_wave.hpp"
+#include "gsys.h"
+#include "kernels.hpp"
+
+#include <errno.h>
+#include <sys/mman.h>
+#include <time.h>
+#include <immintrin.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace gsys_sv {
+
+using namespace gsys;
+using gsys_k::Tile;
+using gsys_k::wave_fnv_t;
+
+constexpr uint32_t kWG = 256;
+constexpr uint32_t kPiece = 1u << 20;          // scan read size (256 blocks of 4 KiB)
+constexpr uint32_t kBlock = 4096;
+constexpr uint64_t kRelBytes = 2ull << 20;
+
+struct SvArgs {
+  gsys_dev_ctx c;
+  gsys_job* jobs;               // host-coherent job records
+  const uint64_t* ctl;          // host-coherent: [0] jobs posted, [1] stop
+  unsigned int* next;           // device: next job to claim
+  uint64_t* digests;            // device: scan digests
+  const uint8_t* content;       // device: pwrite content pool
+  uint64_t staging;             // host: 2 x 1 MiB per work-group
+  uint64_t lifetime_ticks;
+};
+
+__device__ int64_t scan_job(const SvArgs& A, const gsys_job& J, uint8_t* lds, uint64_t stg0,
+                            uint64_t stg1) {
+  const uint64_t blocks = J.len / kBlock;
+  const uint64_t pieces = (J.len + kPiece - 1) / kPiece;
+  int64_t total = 0;
+  int64_t err = 0;
+  auto issue = [&](uint64_t p) {
+    const uint64_t bytes = std::min<uint64_t>(kPiece, J.len - p * kPiece);
+    Args6 a{{(uint64_t)(int64_t)J.fd, (p & 1) ? stg1 : stg0, bytes, J.off + p * kPiece, 0, 0}};
+    Ticket tk{0, 0, 0};
+    call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_PREAD64, 0, a, &tk);
+    return tk;
+  };
+  Ticket tk = pieces ? issue(0) : Ticket{0, 0, 0};
+  for (uint64_t p = 0; p < pieces; ++p) {
+    Ticket tn{0, 0, 0};
+    if (p + 1 < pieces) tn = issue(p + 1);
+    const int64_t r = wait_wg(A.c, tk);
+    if (r < 0 && !err) err = r;
+    if (r > 0) total += r;
+    const uint64_t blk = p * (kPiece / kBlock) + threadIdx.x;
+    const int64_t have = r - (int64_t)threadIdx.x * kBlock;
+    const uint32_t nbytes = r <= 0 || have <= 0 ? 0u : (uint32_t)std::min<int64_t>(have, kBlock);
+    const uint64_t base = (p & 1) ? stg1 : stg0;
+    const uint64_t row0 = base + (uint64_t)(threadIdx.x & ~63u) * kBlock;
+    const uint64_t h = wave_fnv_t<256>(row0, nbytes, kBlock, lds + (threadIdx.x >> 6) * Tile<256>::kBytes);
+    if (blk < blocks) A.digests[J.src + blk] = h;
+    // the buffer of piece p is refilled by piece p + 2, issued next iteration
+    __syncthreads();
+    tk = tn;
+  }
+  return err ? err : total;
+}
+
+__device__ int64_t pwrite_job(const SvArgs& A, const gsys_job& J, uint64_t stg0) {
+  uint8_t* dst = reinterpret_cast<uint8_t*>(stg0);
+  const uint8_t* src = A.content + J.src;
+  const uint64_t n16 = J.len / 16;
+  if ((J.src & 15) == 0) {
+    for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (uint64_t i = n16 * 16 + threadIdx.x; i < J.len; i += blockDim.x) dst[i] = src[i];
+  } else {
+    for (uint64_t i = threadIdx.x; i < J.len; i += blockDim.x) dst[i] = src[i];
+  }
+  Args6 a{{(uint64_t)(int64_t)J.fd, stg0, J.len, J.off, 0, 0}};
+  // producer call: every lane's copy is released before it; only the
+  // caller's wavefront waits for the result
+  const int64_t r = call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_PWRITE64, 0, a);
+  __syncthreads();  // the staging buffer is reused by the next job
+  return r;
+}
+
+__device__ int64_t release_job(const SvArgs& A, const gsys_job& J) {
+  const uint64_t addr = A.c.arena + J.len * kRelBytes;
+  int64_t first = 0;
+  auto note = [&](int64_t r) {
+    if (r < 0 && !first) first = r;
+  };
+  int64_t r = call_wg<O::Relaxed, B::Blocking>(
+      A.c, GSYS_NR_MMAP, 0,
+      Args6{{addr, kRelBytes, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_FIXED,
+             (uint64_t)(int64_t)-1, 0}});
+  note(r);
+  if (r >= 0 && (uint64_t)r != addr) note(-EFAULT);
+  if (r < 0) return first;
+  note(call_wg<O::Relaxed, B::Blocking>(
+      A.c, GSYS_NR_PREAD64, 0, Args6{{(uint64_t)(int64_t)J.aux_fd, addr, kRelBytes, J.src, 0, 0}}));
+  note(call_wg<O::Relaxed, B::Blocking>(
+      A.c, GSYS_NR_PWRITE64, 0,
+      Args6{{(uint64_t)(int64_t)J.fd, addr + (uint64_t)J.page * kBlock, 64, J.off, 0, 0}}));
+  note(call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_MADVISE, 0,
+                                        Args6{{addr, kRelBytes, MADV_DONTNEED, 0, 0, 0}}));
+  note(call_wg<O::Relaxed, B::Blocking>(
+      A.c, GSYS_NR_PWRITE64, 0, Args6{{(uint64_t)(int64_t)J.fd, addr, 64, J.off + 64, 0, 0}}));
+  note(call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_MUNMAP, 0,
+                                        Args6{{addr, kRelBytes, 0, 0, 0, 0}}));
+  // producer calls are weak-block: only the caller's wavefront holds their
+  // results, so the verdict is the designated caller's
+  return first;
+}
+
+__device__ void run_job(const SvArgs& A, uint32_t j, uint8_t* lds, uint64_t stg0, uint64_t stg1) {
+  __shared__ int64_t s_res;
+  fence_acquire_sys();
+  gsys_job J;
+  {
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(A.jobs + j);
+    uint64_t v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = ld_sys(w + i);
+    __builtin_memcpy(&J, v, sizeof J);
+  }
+  int64_t res;
+  if (J.kind == GSYS_JOB_SCAN) res = scan_job(A, J, lds, stg0, stg1);
+  else if (J.kind == GSYS_JOB_PWRITE) res = pwrite_job(A, J, stg0);
+  else if (J.kind == GSYS_JOB_RELEASE) res = release_job(A, J);
+  else res = -EINVAL;
+  if (threadIdx.x == 0) s_res = res;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    gsys_job* jp = A.jobs + j;
+    __hip_atomic_store((uint64_t*)&jp->result, (uint64_t)s_res, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+    // every output of the job (digests in HBM, file writes done by the host)
+    // is complete before the host sees `done`
+    __threadfence();
+    st_sys_rel(&jp->done, 1);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void serve_persistent(SvArgs A) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ int s_job;
+  const uint64_t stg0 = A.staging + (uint64_t)blockIdx.x * 2 * kPiece;
+  const uint64_t stg1 = stg0 + kPiece;
+  const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int got = -1;
+      uint32_t idle = 0;
+      for (;;) {
+        const unsigned int nj = __hip_atomic_load(A.next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t posted = ld_sys(&A.ctl[0]);
+        if (nj < posted) {
+          unsigned int exp = nj;
+          if (__hip_atomic_compare_exchange_strong(A.next, &exp, nj + 1, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            got = (int)nj;
+            break;
+          }
+          continue;
+        }
+        if (ld_sys(&A.ctl[1]) || wall_clock64() > t_end) break;
+        const uint32_t reps = 1u << min(idle, 5u);
+        for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(4);
+        ++idle;
+      }
+      s_job = got;
+    }
+    __syncthreads();
+    const int j = s_job;
+    __syncthreads();
+    if (j < 0) break;
+    run_job(A, (uint32_t)j, lds, stg0, stg1);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void serve_one(SvArgs A, uint32_t j) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  run_job(A, j, lds, A.staging, A.staging + kPiece);
+}
+
+__global__ void zero_u32(unsigned int* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+}  // namespace gsys_sv
+
+using namespace gsys_sv;
+
+int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_host, uint32_t n,
+                   const uint64_t* arrival_ns, uint32_t max_inflight, uint64_t digests,
+                   uint64_t content, uint64_t staging, uint64_t staging_bytes, uint32_t grid,
+                   uint64_t timeout_ns, uint64_t* latency_ns, void* stream) {
+  if (!ctx || !jobs_dev || !jobs_host || !arrival_ns || !latency_ns || !max_inflight) return -EINVAL;
+  if (form != GSYS_PLAIN && form != GSYS_PERSISTENT) return -EINVAL;
+  if (gsys_internal::check_host_range(ctx, jobs_dev, (uint64_t)n * sizeof(gsys_job))) return -EFAULT;
+  if (gsys_internal::check_host_range(ctx, staging, staging_bytes)) return -EFAULT;
+  if (staging_bytes < 2ull * kPiece) return -EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  gsys_job* jobs = (gsys_job*)jobs_host;
+  uint64_t* ctl_h = nullptr;
+  uint64_t ctl_d = 0;
+  if (int e = gsys_internal::control_page(ctx, (void**)&ctl_h, &ctl_d)) return e;
+  SvArgs A;
+  if (int e = gsys_device_ctx(ctx, &A.c)) return e;
+  A.jobs = (gsys_job*)jobs_dev;
+  A.ctl = (const uint64_t*)ctl_d;
+  A.next = (unsigned int*)gsys_internal::kstate(ctx) + 12;
+  A.digests = (uint64_t*)digests;
+  A.content = (const uint8_t*)content;
+  A.staging = staging;
+  const uint64_t tmo = timeout_ns ? timeout_ns : 120000000000ull;
+  A.lifetime_ticks = gsys_internal::ticks_per_ms(ctx) * (tmo / 1000000ull + 1000);
+  for (uint32_t i = 0; i < n; ++i) {
+    __atomic_store_n(&jobs[i].done, 0ull, __ATOMIC_RELAXED);
+    latency_ns[i] = ~0ull;
+  }
+  __atomic_store_n(&ctl_h[0], 0ull, __ATOMIC_RELEASE);
+  __atomic_store_n(&ctl_h[1], 0ull, __ATOMIC_RELEASE);
+  hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, A.next, 1u);
+  const uint32_t lds = (kWG / 64) * Tile<256>::kBytes;
+  if (form == GSYS_PERSISTENT) {
+    uint32_t res = gsys_internal::resident_grid(ctx, (const void*)serve_persistent, kWG, lds);
+    if (!res) return -ENODEV;
+    const uint64_t fit = staging_bytes / (2ull * kPiece);
+    if (!grid || grid > res) grid = res;
+    if (grid > fit) grid = (uint32_t)fit;
+    void* args[] = {&A};
+    if (int e = gsys_internal::launch(ctx, (const void*)serve_persistent, grid, kWG, lds, args, s))
+      return e;
+  } else if (hipStreamSynchronize(s) != hipSuccess) {
+    return -ENODEV;
+  }
+  const uint64_t t0 = now_ns();
+  const uint64_t deadline = t0 + tmo;
+  uint32_t posted = 0, completed = 0, oldest = 0;
+  int rc = 0;
+  std::vector<uint8_t> seen(n, 0);
+  while (completed < n) {
+    const uint64_t t = now_ns();
+    bool progress = false;
+    while (posted < n && t0 + arrival_ns[posted] <= t && posted - completed < max_inflight) {
+      if (form == GSYS_PERSISTENT) {
+        __atomic_store_n(&ctl_h[0], (uint64_t)posted + 1, __ATOMIC_RELEASE);
+      } else {
+        SvArgs B = A;
+        uint32_t jj = posted;
+        void* args[] = {&B, &jj};
+        if (hipLaunchKernel((const void*)serve_one, dim3(1), dim3(kWG), args, lds, s) != hipSuccess) {
+          rc = -ENODEV;
+          break;
+        }
+      }
+      ++posted;
+      progress = true;
+    }
+    if (rc) break;
+    const uint64_t t2 = now_ns();
+    for (uint32_t i = oldest; i < posted; ++i) {
+      if (!seen[i] && __atomic_load_n(&jobs[i].done, __ATOMIC_ACQUIRE)) {
+        seen[i] = 1;
+        latency_ns[i] = t2 - (t0 + arrival_ns[i]);
+        ++completed;
+        progress = true;
+      }
+    }
+    while (oldest < posted && seen[oldest]) ++oldest;
+    if (t2 > deadline) {
+      rc = -ETIMEDOUT;
+      break;
+    }
+    if (!progress) _mm_pause();
+  }
+  __atomic_store_n(&ctl_h[1], 1ull, __ATOMIC_RELEASE);
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = -ENODEV;
+  return rc;
+}

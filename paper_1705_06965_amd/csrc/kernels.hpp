@@ -20,6 +20,8 @@ uint32_t resident_grid(gsys_ctx* ctx, const void* kernel, uint32_t block, uint32
 // A persistent grid size requested through GSYS_PERSISTENT_GRID (0 = none).
 uint32_t persistent_grid_override(gsys_ctx* ctx);
 uint64_t hash_words(std::initializer_list<uint64_t> w);
+// A context-owned page of host-coherent memory for driver control words.
+int control_page(gsys_ctx* ctx, void** host, uint64_t* dev);
 // Device wall-clock ticks per millisecond.
 uint64_t ticks_per_ms(gsys_ctx* ctx);
 int launch(gsys_ctx* ctx, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds,

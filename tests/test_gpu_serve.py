@@ -1,0 +1,155 @@
+"""GPU parity of the serving mix: every job's outputs (scan digests, pwrite
+file bytes, release readbacks and return values) equal the oracle's, in the
+mix and alone, in the persistent and plain forms."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_06965_amd as g
+    ctx = g.Context(ring_slots=1 << 16, device_timeout_ns=60_000_000_000, arena_bytes=16 << 30)
+    yield g, ctx
+    assert ctx.shutdown() == 0
+
+
+def sub_stream(js, idx):
+    idx = np.asarray(idx)
+    arr = js.arrival_ns[idx] - js.arrival_ns[idx[0]]
+    return synth.JobStream(kind=js.kind[idx], arrival_ns=arr, arg_off=js.arg_off[idx],
+                           arg_len=js.arg_len[idx], content_off=js.content_off[idx],
+                           content=js.content)
+
+
+def check_outputs(sr, js, res, dig, in_path, out_path, label):
+    data = synth.file_bytes(in_path)
+    out = np.fromfile(out_path, dtype=np.uint8)
+    jobs = sr.jobs_np
+    n_scan = n_pw = n_rel = 0
+    for i in range(len(js.kind)):
+        k = int(js.kind[i])
+        if k == 0:
+            ln, off = int(jobs["len"][i]), int(jobs["off"][i])
+            assert res[i] == ln, (label, i, res[i])
+            nb = ln // 4096
+            offs = off + 4096 * np.arange(nb, dtype=np.uint64)
+            want, _ = oracle.pread_fnv(in_path, offs, 4096)
+            d0 = int(sr.digest_start[i])
+            assert (dig[d0:d0 + nb] == want).all(), (label, i)
+            n_scan += 1
+        elif k == 1:
+            ln, off, src = int(jobs["len"][i]), int(jobs["off"][i]), int(jobs["src"][i])
+            assert res[i] == ln, (label, i, res[i])
+            assert (out[off:off + ln] == js.content[src:src + ln]).all(), (label, i)
+            n_pw += 1
+        else:
+            assert res[i] == 0, (label, i, res[i])
+            off, src, pg = int(jobs["off"][i]), int(jobs["src"][i]), int(jobs["page"][i])
+            stamp = data[src + 4096 * pg: src + 4096 * pg + 64]
+            assert (out[off:off + 64] == stamp).all(), (label, i)
+            assert not out[off + 64:off + 128].any(), (label, i)
+            n_rel += 1
+    return n_scan, n_pw, n_rel
+
+
+@pytest.fixture(scope="module")
+def mix(gs, tmpdata):
+    in_path = synth.random_file(5, 64 << 20, name="c5_in_64m.bin")
+    js = synth.job_stream(n_jobs=600, rate_per_s=20000, scan_file_bytes=64 << 20,
+                          scan_max_log2_pages=8, pwrite_max_pages=64, arena_blocks=8192)
+    return js, in_path
+
+
+@pytest.mark.parametrize("form", ["persistent", "plain"])
+def test_mix_matches_oracle(gs, mix, tmpdata, form):
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    out_path = os.path.join(tmpdata, "serve_out_%s.bin" % form)
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("serve", form, "jobs", sr.n)
+    res, dig, lat = sr.run(g.PERSISTENT if form == "persistent" else g.PLAIN, max_inflight=64,
+                           staging_bytes=(2 << 20) * 32)
+    sr.close()
+    counts = check_outputs(sr, js, res, dig, in_path, out_path, form)
+    assert min(counts) > 0
+    assert (lat != np.uint64(2**64 - 1)).all()
+
+
+def test_jobs_alone_equal_in_mix(gs, mix, tmpdata):
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    out_mix = os.path.join(tmpdata, "serve_mix.bin")
+    sr = ServeRun(ctx, js, in_path, out_mix)
+    res, dig, _ = sr.run(g.PERSISTENT, max_inflight=128, staging_bytes=(2 << 20) * 32)
+    sr.close()
+    out_m = np.fromfile(out_mix, dtype=np.uint8)
+    for i in (0, 1, 2, 17, 101, 333, 599):
+        one = sub_stream(js, [i])
+        out1 = os.path.join(tmpdata, "serve_one_%d.bin" % i)
+        s1 = ServeRun(ctx, one, in_path, out1)
+        r1, d1, _ = s1.run(g.PERSISTENT, max_inflight=1, staging_bytes=(2 << 20) * 4)
+        s1.close()
+        assert r1[0] == res[i]
+        k = int(js.kind[i])
+        if k == 0:
+            nb = int(js.arg_len[i]) // 4096
+            d0 = int(sr.digest_start[i])
+            assert (d1[:nb] == dig[d0:d0 + nb]).all()
+        elif k == 1:
+            off, ln = int(js.arg_off[i]), int(js.arg_len[i])
+            o1 = np.fromfile(out1, dtype=np.uint8)
+            assert (o1[off:off + ln] == out_m[off:off + ln]).all()
+        else:
+            o1 = np.fromfile(out1, dtype=np.uint8)
+            j1 = s1.jobs_np[0]
+            jm = sr.jobs_np[i]
+            # the same stamp page and source offset read back the same bytes
+            if int(j1["src"]) == int(jm["src"]) and int(j1["page"]) == int(jm["page"]):
+                assert (o1[int(j1["off"]):int(j1["off"]) + 128] ==
+                        out_m[int(jm["off"]):int(jm["off"]) + 128]).all()
+
+
+def test_release_readback_matches_oracle_release_job(gs, mix, tmpdata):
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    rel = np.nonzero(js.kind == 2)[0][:5]
+    sub = sub_stream(js, rel)
+    out_g = os.path.join(tmpdata, "rel_gpu.bin")
+    sr = ServeRun(ctx, sub, in_path, out_g)
+    res, _, _ = sr.run(g.PERSISTENT, max_inflight=4, staging_bytes=(2 << 20) * 4)
+    sr.close()
+    out_o = os.path.join(tmpdata, "rel_oracle.bin")
+    ifd = os.open(in_path, os.O_RDONLY)
+    ofd = os.open(out_o, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+    try:
+        for j in range(len(rel)):
+            rec = sr.jobs_np[j]
+            rc, rets = oracle.release_job(ifd, int(rec["src"]), int(rec["page"]), ofd,
+                                          int(rec["off"]))
+            assert rc == 0 and res[j] == 0
+    finally:
+        os.close(ifd)
+        os.close(ofd)
+    a = np.fromfile(out_g, dtype=np.uint8)
+    b = np.fromfile(out_o, dtype=np.uint8)
+    lo = int(sr.jobs_np["off"].min())
+    assert (a[lo:] == b[lo:]).all()
