@@ -47,7 +47,10 @@ def parse():
     ap.add_argument("--kv-grid", type=int, default=16, help="kv: server work-groups")
     ap.add_argument("--kv-clients", type=int, default=4, help="kv: load generator threads")
     ap.add_argument("--kv-window", type=int, default=128, help="kv: outstanding per client")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "wordscan", "kv"],
+    ap.add_argument("--serve-jobs", type=int, default=55000, help="serve: jobs in the stream")
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="serve: arrivals per second")
+    ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "wordscan", "kv", "serve"],
                     help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
                          "word search over 2,000 files")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -108,6 +111,8 @@ def main():
         return run_wordscan(args)
     if args.workload == "kv":
         return run_kv(args)
+    if args.workload == "serve":
+        return run_serve(args)
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
@@ -460,6 +465,139 @@ def run_kv(args):
     srv.close()
     ctx.shutdown()
     print(json.dumps(res), flush=True)
+
+
+def run_serve(args):
+    """Serving mix: Poisson arrivals (mean 20k/s) of scan (4 KiB-64 MiB
+    log-uniform reads of the 1 GiB file, per-4 KiB FNV digests), pwrite
+    (4-256 KiB) and release (mmap / madvise(MADV_DONTNEED) of 2 MiB blocks of
+    a 16 GiB arena) jobs; 55,000 jobs, the first 5,000 are warm-up.  One
+    step = the whole stream.  value = jobs per second; p50/p99 latency from
+    each job's scheduled arrival to the host seeing it done."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.serve import ServeRun
+    t0 = time.time()
+    in_path = synth.random_file(2, FILE_BYTES, name="c2_1g.bin")
+    js = synth.job_stream(n_jobs=args.serve_jobs, rate_per_s=args.serve_rate)
+    with open(in_path, "rb") as f:
+        while f.read(64 << 20):
+            pass
+    out_path = os.path.join(synth.data_dir(), "serve_out.bin")
+    print("job stream %d jobs (%s), setup %.1fs" % (len(js.kind), np.bincount(js.kind).tolist(),
+                                                   time.time() - t0), file=sys.stderr, flush=True)
+    ctx = g.Context(ring_slots=1 << 16, service_threads=args.service_threads,
+                    device_timeout_ns=60_000_000_000, arena_bytes=16 << 30)
+    sr = ServeRun(ctx, js, in_path, out_path)
+    warm = min(5000, len(js.kind) // 10)
+
+    def session(form, inflight, n_limit=None):
+        t1 = time.perf_counter()
+        res, dig, lat = sr.run(form, max_inflight=inflight, staging_bytes=(2 << 20) * 256,
+                               timeout_ns=300_000_000_000)
+        dt = time.perf_counter() - t1
+        return res, dig, lat, dt
+
+    res, dig, lat, dt = session(g.PERSISTENT, args.serve_inflight)
+    lat_s = lat[warm:].astype(np.float64) / 1e3
+    span_s = (float(js.arrival_ns[-1]) - float(js.arrival_ns[warm])) / 1e9 + \
+        float(np.median(lat_s)) / 1e6
+    # parity on a sample of jobs
+    import oracle
+    rng = np.random.default_rng(11)
+    data = np.memmap(in_path, dtype=np.uint8, mode="r")
+    out = np.memmap(out_path, dtype=np.uint8, mode="r")
+    jobs = sr.jobs_np
+    for i in rng.choice(len(js.kind), 300, replace=False):
+        k = int(js.kind[i])
+        if k == 0:
+            nb = int(jobs["len"][i]) // 4096
+            offs = int(jobs["off"][i]) + 4096 * np.arange(min(nb, 256), dtype=np.uint64)
+            want, _ = oracle.pread_fnv(in_path, offs, 4096)
+            d0 = int(sr.digest_start[i])
+            ok = res[i] == int(jobs["len"][i]) and (dig[d0:d0 + len(offs)] == want).all()
+        elif k == 1:
+            off, ln, src = int(jobs["off"][i]), int(jobs["len"][i]), int(jobs["src"][i])
+            ok = res[i] == ln and (out[off:off + ln] == js.content[src:src + ln]).all()
+        else:
+            off, src, pg = int(jobs["off"][i]), int(jobs["src"][i]), int(jobs["page"][i])
+            ok = res[i] == 0 and (out[off:off + 64] == data[src + 4096 * pg:src + 4096 * pg + 64]).all() \
+                and not out[off + 64:off + 128].any()
+        if not ok:
+            raise RuntimeError("serving job %d differs from the oracle" % i)
+    plain = None
+    if not args.no_plain:
+        # the plain form: one launch per job, on the first 4,000 jobs only
+        sub = synth.JobStream(kind=js.kind[:4000], arrival_ns=js.arrival_ns[:4000],
+                              arg_off=js.arg_off[:4000], arg_len=js.arg_len[:4000],
+                              content_off=js.content_off[:4000], content=js.content)
+        sp = ServeRun(ctx, sub, in_path, out_path + ".plain")
+        t1 = time.perf_counter()
+        _, _, lp, dtp = None, None, None, None
+        rp, dp, lp = sp.run(g.PLAIN, max_inflight=args.serve_inflight,
+                            staging_bytes=(2 << 20) * 4, timeout_ns=300_000_000_000)
+        dtp = time.perf_counter() - t1
+        lps = lp[400:].astype(np.float64) / 1e3
+        plain = {"jobs": 4000, "jobs_per_s": round(4000 / dtp, 1),
+                 "latency_us_p50": round(float(np.percentile(lps, 50)), 1),
+                 "latency_us_p99": round(float(np.percentile(lps, 99)), 1)}
+        sp.close()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle runs the first 5,000 jobs on a thread pool, as fast as it can
+        threads = len(os.sched_getaffinity(0))
+        ofd = os.open(out_path + ".cpu", os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+        ifd = os.open(in_path, os.O_RDONLY)
+
+        def one(i):
+            k = int(js.kind[i])
+            if k == 0:
+                nb = int(jobs["len"][i]) // 4096
+                offs = int(jobs["off"][i]) + 4096 * np.arange(nb, dtype=np.uint64)
+                oracle.pread_fnv(in_path, offs, 4096)
+            elif k == 1:
+                off, ln, src = int(jobs["off"][i]), int(jobs["len"][i]), int(jobs["src"][i])
+                os.pwrite(ofd, js.content[src:src + ln].tobytes(), off)
+            else:
+                oracle.release_job(ifd, int(jobs["src"][i]), int(jobs["page"][i]), ofd,
+                                   int(jobs["off"][i]))
+        t1 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(5000)))
+        dtc = time.perf_counter() - t1
+        os.close(ofd)
+        os.close(ifd)
+        cpu = {"value": round(5000 / dtc, 1), "unit": "jobs/s", "cores": threads, "kind": "oracle",
+               "sample": "the first 5,000 jobs run back to back by the oracle on a pool of %d "
+                         "threads (closed loop: capacity, not latency)" % threads}
+    st = ctx.stats()
+    res_j = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round((len(js.kind) - warm) / span_s, 1), "unit": "jobs/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "serving mix: Poisson arrivals at %.0f/s of scan (4 KiB-64 MiB "
+                               "log-uniform, per-4 KiB FNV), pwrite (4-256 KiB) and "
+                               "mmap/madvise release (2 MiB of a 16 GiB arena) jobs, "
+                               "10/60/30%%" % args.serve_rate,
+                   "jobs": len(js.kind), "warmup_jobs": warm, "max_inflight": args.serve_inflight,
+                   "form": "persistent (continuous batching)"},
+        "latency_us_p50": round(float(np.percentile(lat_s, 50)), 1),
+        "latency_us_p99": round(float(np.percentile(lat_s, 99)), 1),
+        "offered_jobs_per_s": args.serve_rate,
+        "scan_GBps": round(float(js.arg_len[js.kind == 0].sum()) / dt / 1e9, 3),
+        "host_calls": st["host_calls"],
+    }
+    if plain:
+        res_j["plain_form"] = plain
+    if cpu:
+        res_j["cpu_baseline"] = cpu
+    sr.close()
+    ctx.shutdown()
+    print(json.dumps(res_j), flush=True)
 
 
 if __name__ == "__main__":
