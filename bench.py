@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--form", default="graph", choices=["graph", "persistent"])
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--service-threads", type=int, default=0)
+    ap.add_argument("--service-threads", type=int, default=-1,
+                    help="host pollers (-1: the autotuned value, 0: cores - 1)")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="sweep: ignore the autotuned knobs and use the defaults")
     ap.add_argument("--staging-mib", type=int, default=0,
                     help="persistent form: staging ring size (0 = one slot per item)")
     ap.add_argument("--only", default="", help="profiling aid: 'plain' or 'persistent' only")
@@ -127,10 +130,17 @@ def main():
             pass
     print("setup %.1fs" % (time.time() - t_setup), file=sys.stderr, flush=True)
 
-    ctx = g.Context(ring_slots=1 << 18, service_threads=args.service_threads,
-                    device_timeout_ns=60_000_000_000)
-    r = FnvRunner(ctx, path, offs, ITEM, wg_size=WG, staging_bytes=args.staging_mib << 20)
-    rp = r if not args.staging_mib else FnvRunner(ctx, path, offs, ITEM, wg_size=WG)
+    from paper_1705_06965_amd import autotune
+    tp = dict(autotune.DEFAULTS) if args.no_tuned else autotune.load("sweep")
+    if args.service_threads >= 0:
+        tp["service_threads"] = args.service_threads
+    ctx = g.Context(ring_slots=tp["ring_slots"], service_threads=tp["service_threads"],
+                    coalesce_max=tp["coalesce_max"], coalesce_window_ns=tp["coalesce_window_ns"],
+                    sleep_max=tp["sleep_max"], device_timeout_ns=60_000_000_000)
+    r = FnvRunner(ctx, path, offs, ITEM, wg_size=tp["wg_size"],
+                  staging_bytes=args.staging_mib << 20)
+    rp = r if (not args.staging_mib and tp["wg_size"] == WG) else \
+        FnvRunner(ctx, path, offs, ITEM, wg_size=WG)
     stream = torch.cuda.current_stream()
     form = g.GRAPH if args.form == "graph" else g.PERSISTENT
 
@@ -232,6 +242,7 @@ def main():
                    "calls_per_step": calls_per_step,
                    "service_threads": int(ctx.cfg.service_threads) or (os.cpu_count() or 2) - 1,
                    "staging_bytes": r.staging_bytes,
+                   "tuned": {k: v for k, v in tp.items()},
                    "ring_slots": int(ctx.cfg.ring_slots)},
         "pread_GBps": round(gbps, 2),
         "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
@@ -282,7 +293,7 @@ def run_wordscan(args):
             f.read()
     print("corpus %d files %.1f MiB, setup %.1fs" % (len(c.paths), c.total_bytes / 2**20,
                                                      time.time() - t0), file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=args.service_threads,
+    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
                     device_timeout_ns=60_000_000_000)
     r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20)
     stream = torch.cuda.current_stream()
@@ -382,7 +393,7 @@ def run_kv(args):
     reqs = make_requests(kv.req_keys)
     print("kv set %d keys, %d requests, setup %.1fs" % (len(kv.keys), len(reqs), time.time() - t0),
           file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=args.service_threads,
+    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
                     device_timeout_ns=60_000_000_000)
     srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=args.kv_grid)
     steps = max(1, min(args.steps, 3))
@@ -489,7 +500,7 @@ def run_serve(args):
     out_path = os.path.join(synth.data_dir(), "serve_out.bin")
     print("job stream %d jobs (%s), setup %.1fs" % (len(js.kind), np.bincount(js.kind).tolist(),
                                                    time.time() - t0), file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=args.service_threads,
+    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
                     device_timeout_ns=60_000_000_000, arena_bytes=16 << 30)
     sr = ServeRun(ctx, js, in_path, out_path)
     warm = min(5000, len(js.kind) // 10)

@@ -53,7 +53,9 @@ typedef struct gsys_config {
     uint64_t device_timeout_ns;  /* GPU watchdog on every wait (0 = 30 s)             */
     int32_t  first_cpu;          /* pin pollers to cores first_cpu.. (-1 = 1..P)      */
     uint32_t ledger_capacity;    /* ledger records kept (0 = 1<<20)                   */
-    uint32_t reserved[4];
+    uint32_t sleep_max;          /* GPU wait backoff cap, in s_sleep steps of ~256
+                                    clocks doubled up to this count (0 = 64)           */
+    uint32_t reserved[3];
 } gsys_config;
 
 /*

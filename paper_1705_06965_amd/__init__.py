@@ -61,7 +61,7 @@ class gsys_config(C.Structure):
                 ("stripe", C.c_uint32), ("flags", C.c_uint32),
                 ("arena_bytes", C.c_uint64), ("device_timeout_ns", C.c_uint64),
                 ("first_cpu", C.c_int32), ("ledger_capacity", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("sleep_max", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class gsys_stats(C.Structure):
@@ -203,7 +203,7 @@ class Context:
 
     def __init__(self, ring_slots=0, service_threads=0, coalesce_max=1, coalesce_window_ns=0,
                  stripe=0, flags=0, arena_bytes=0, device_timeout_ns=0, first_cpu=-1, device=0,
-                 ledger_capacity=0):
+                 ledger_capacity=0, sleep_max=0):
         cfg = gsys_config()
         cfg.abi_version = ABI_VERSION
         cfg.device = device
@@ -217,6 +217,7 @@ class Context:
         cfg.device_timeout_ns = device_timeout_ns
         cfg.first_cpu = first_cpu
         cfg.ledger_capacity = ledger_capacity
+        cfg.sleep_max = sleep_max
         h = C.c_void_p()
         check(lib.gsys_init(C.byref(cfg), C.byref(h)), "gsys_init")
         self.h = h.value

@@ -1,0 +1,115 @@
+"""Autotuner of the batching form: picks the host pool and launch knobs for
+the pread sweep by measurement and caches them as JSON keyed by workload,
+device and host core count.
+
+Knobs (searched one at a time, each keeping the best value so far):
+  service_threads P   host pollers
+  wg_size W           work-items per group call = descriptors per ring entry
+  sleep_max           GPU wait backoff cap
+  ring_slots D        slot ring depth
+  coalesce (K, T)     host coalescing bundle size and window (section 4.2)
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+DEFAULTS = {"service_threads": 0, "wg_size": 256, "sleep_max": 64, "ring_slots": 1 << 18,
+            "coalesce_max": 1, "coalesce_window_ns": 0}
+SPACE = [("service_threads", [12, 13, 14, 15]),
+         ("wg_size", [64, 128, 256]),
+         ("sleep_max", [16, 64, 256, 1024]),
+         ("ring_slots", [1 << 12, 1 << 16, 1 << 18]),
+         ("coalesce", [(1, 0), (8, 2000), (32, 5000)])]
+
+
+def host_key(workload: str) -> str:
+    try:
+        import torch
+        dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # noqa: BLE001 - no GPU: key without a device name
+        dev = "nodev"
+    return "%s/%s/cores%d" % (workload, dev, len(os.sched_getaffinity(0)))
+
+
+def load(workload: str = "sweep") -> dict:
+    try:
+        with open(CACHE) as f:
+            d = json.load(f)
+        return dict(DEFAULTS, **d.get(host_key(workload), {}).get("params", {}))
+    except (OSError, ValueError):
+        return dict(DEFAULTS)
+
+
+def measure_sweep(params: dict, path: str, offs, steps: int = 3) -> float:
+    """Host calls per second of the persistent sweep with `params`."""
+    import torch
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+    ctx = g.Context(ring_slots=params["ring_slots"], service_threads=params["service_threads"],
+                    coalesce_max=params["coalesce_max"],
+                    coalesce_window_ns=params["coalesce_window_ns"],
+                    sleep_max=params["sleep_max"], device_timeout_ns=60_000_000_000)
+    try:
+        r = FnvRunner(ctx, path, offs, 4096, wg_size=params["wg_size"])
+        for _ in range(2):
+            r.launch(0, g.GRAPH)
+            torch.cuda.synchronize()
+            ctx.wait()
+        t = time.perf_counter()
+        for _ in range(steps):
+            r.launch(0, g.GRAPH)
+            torch.cuda.synchronize()
+            ctx.wait()
+        dt = time.perf_counter() - t
+        r.close()
+        return len(offs) * steps / dt
+    finally:
+        ctx.shutdown()
+
+
+def tune_sweep(path: str, offs, log=print) -> dict:
+    best = dict(DEFAULTS)
+    best_v = measure_sweep(best, path, offs)
+    log("defaults: %.0f calls/s" % best_v)
+    trials = [(dict(best), best_v)]
+    for knob, values in SPACE:
+        for v in values:
+            p = dict(best)
+            if knob == "coalesce":
+                p["coalesce_max"], p["coalesce_window_ns"] = v
+            else:
+                p[knob] = v
+            if p == best:
+                continue
+            val = measure_sweep(p, path, offs)
+            trials.append((p, val))
+            log("%s=%s: %.0f calls/s" % (knob, v, val))
+            if val > best_v * 1.01:
+                best, best_v = p, val
+    return {"params": best, "calls_per_s": round(best_v, 1), "trials": len(trials),
+            "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def save(workload: str, result: dict, path: str | None = None) -> None:
+    """Merge `result` into the cache (or into `path`, e.g. a copy to ship)."""
+    path = path or CACHE
+    try:
+        with open(CACHE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[host_key(workload)] = result
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    import synth
+    path = synth.random_file(2, 1 << 30, name="c2_1g.bin")
+    offs = synth.sweep_offsets(262144, 262144)
+    res = tune_sweep(path, offs, log=lambda s: print(s, flush=True))
+    save("sweep", res, os.environ.get("GSYS_TUNE_OUT"))
+    print(json.dumps(res))

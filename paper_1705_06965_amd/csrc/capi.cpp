@@ -161,7 +161,7 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
   c->D = cfg.ring_slots;
   c->C = 4 * c->D;
   c->grid_override = (uint32_t)env_u64("GSYS_PERSISTENT_GRID", 0);
-  c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", 64);
+  c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", cfg.sleep_max ? cfg.sleep_max : 64);
   const uint64_t tmo = cfg.device_timeout_ns ? cfg.device_timeout_ns : 30000000000ull;
   c->timeout_ticks = tmo / 10;  // 100 MHz device wall clock
 
