@@ -363,6 +363,22 @@ int gsys_serve_run(gsys_ctx *ctx, uint32_t form, uint64_t jobs_dev, void *jobs_h
                    uint64_t timeout_ns, uint64_t *latency_ns, void *stream);
 
 /*
+ * Visibility canary for producer calls (section 4.1 ordering): work-item i
+ * writes 64 stamp bytes (eight little-endian words
+ * (seed * 0x9E3779B97F4A7C15) ^ ((8i + k + 1) * 0xD1B54A32D192ED03), k =
+ * 0..7, mod 2^64) at buf + 64i, then the buffer is written to `fd` with
+ * pwrite at the granularity / ordering / blocking of `cell`: each work-item
+ * its 64 bytes at file offset 64i, each work-group its range, or the last
+ * work-group of the kernel the whole buffer.  The file must then hold every
+ * stamp.  out_ret (device int64) receives each call's return value: per
+ * work-item, per work-group, or [0] for the kernel call.
+ * buf: registered GSYS_BUF_HOST, n_items * 64 bytes.  wg_size: 64..1024,
+ * multiple of 64.  Errors: -EINVAL (illegal cell, shapes), -EFAULT.
+ */
+int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t seed,
+                uint64_t out_ret, uint32_t cell, uint32_t wg_size, void *stream);
+
+/*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable
  * address: registered host memory or HBM); one kernel computes
