@@ -61,23 +61,27 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp",
-                  "paper_1705_06965_amd/csrc/gsys_device.hpp",
-                  "include/gsys_abi.h")
-PROFILE = "profiles/fnv4k_persistent_pread_sweep_1g.md"
+COMMON_SOURCES = ["paper_1705_06965_amd/csrc/gsys_device.hpp", "include/gsys_abi.h"]
+PROFILES = {
+    "sweep": ("profiles/fnv4k_persistent_pread_sweep_1g.md",
+              ["paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp"]),
+    "wordscan": ("profiles/wordscan_persistent_corpus_2000.md",
+                 ["paper_1705_06965_amd/csrc/k_wordscan.hip"]),
+}
 
 
-def profile_traffic():
-    """HBM + link bytes per launch of the persistent kernel from the committed
-    rocprofv3 counter summary, or None when the kernel sources changed since
-    the counters were taken."""
+def profile_traffic(workload):
+    """HBM + link bytes per launch of the workload's dominant kernel from the
+    committed rocprofv3 counter summary, or None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
+    prof, sources = PROFILES[workload]
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources + COMMON_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     try:
-        with open(os.path.join(ROOT, PROFILE)) as fh:
+        with open(os.path.join(ROOT, prof)) as fh:
             line = [l for l in fh if l.startswith("machine-readable:")][0]
         d = json.loads(line.split(":", 1)[1])
     except (OSError, IndexError, ValueError):
@@ -251,7 +255,7 @@ def main():
         "roofline": {"bound": "host-link", "achieved": round(achieved, 2),
                      "peak": LINK_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / LINK_PEAK_GBPS, 4),
-                     "traffic": profile_traffic() if key == "persistent" else None,
+                     "traffic": profile_traffic("sweep") if key == "persistent" else None,
                      "kernel": "fnv4k_persistent", "kernel_ms": round(kavg_ms, 3),
                      "bytes_per_launch": calls_per_step * ITEM},
         "host": {"calls": st["host_calls"] // steps, "requests": st["requests"] // steps,
@@ -361,8 +365,8 @@ def run_wordscan(args):
         "step_ms_p50": round(1e3 * percentile(wall, 50), 3),
         "step_ms_p99": round(1e3 * percentile(wall, 99), 3),
         "roofline": {"bound": "host-link", "achieved": round(achieved, 2), "peak": LINK_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / LINK_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "wordscan_persistent", "kernel_ms": round(kavg, 3),
+                     "unit": "GB/s", "frac": round(achieved / LINK_PEAK_GBPS, 4),
+                     "traffic": profile_traffic("wordscan"), "kernel": "wordscan_persistent", "kernel_ms": round(kavg, 3),
                      "bytes_per_launch": int(link_bytes)},
     }
     if tw:
