@@ -64,6 +64,9 @@ def lib() -> C.CDLL:
         L.oracle_release_job.restype = C.c_int
         L.oracle_release_job.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.c_uint64,
                                          C.c_void_p]
+        L.oracle_permute.restype = C.c_int
+        L.oracle_permute.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                     C.c_uint32, C.c_uint64, C.c_void_p, C.c_int]
         del u8p
         _lib = L
     return _lib
@@ -175,3 +178,21 @@ def release_job(stamp_fd: int, stamp_off: int, page: int, out_fd: int, out_off: 
     rets = np.zeros(6, dtype=np.int64)
     rc = lib().oracle_release_job(stamp_fd, stamp_off, page, out_fd, out_off, _p(rets))
     return rc, rets
+
+
+def permute(fd: int, data: np.ndarray, sigma: np.ndarray, tau: np.ndarray, iters: int,
+            file_off: int = 0, threads: int = 1) -> np.ndarray:
+    """ret[b] of pwrite(fd, permute^iters(block b), 8192, file_off + 8192 b)."""
+    d = np.ascontiguousarray(data, dtype=np.uint64)
+    if d.size % 1024:
+        raise ValueError("data is not a whole number of 8 KiB blocks")
+    s = np.ascontiguousarray(sigma, dtype=np.uint16)
+    t = np.ascontiguousarray(tau, dtype=np.uint8)
+    if s.size != 1024 or t.size != 64:
+        raise ValueError("sigma needs 1024 entries and tau 64")
+    n = d.size // 1024
+    ret = np.zeros(n, dtype=np.int64)
+    rc = lib().oracle_permute(fd, _p(d), n, _p(s), _p(t), iters, file_off, _p(ret), threads)
+    if rc:
+        raise OSError(-rc, "oracle_permute")
+    return ret

@@ -23,12 +23,15 @@
  *     (0x0a); counts[f][q] is the number of tokens of file f equal to query q;
  *   - key-value GET replies in the style of the UDP server case study
  *     (section 7.3), with a sorted key index and bsearch;
- *   - memory release with madvise(MADV_DONTNEED) in the style of section 7.2.
+ *   - memory release with madvise(MADV_DONTNEED) in the style of section 7.2;
+ *   - the block permutation written out with pwrite of section 6 (Fig. 6).
  *
  * Pins (tests/test_oracle_pins.py): published FNV-1a test vectors; slicing of
  * the file bytes for every (offset, length) pair on tiny files including EOF;
  * Python bytes.split() counting; dictionary lookups; zero pages after
- * MADV_DONTNEED on private anonymous memory (Linux madvise(2)).
+ * MADV_DONTNEED on private anonymous memory (Linux madvise(2)); for the
+ * permutation, numpy's flat bit-index gather, byte swapping, rotations with a
+ * closed form and the order of the permutation.
  *
  * Threads: where a function takes `threads`, items (or files) are split into
  * contiguous ranges, one per POSIX thread, as the paper's CPU wordcount
@@ -349,5 +352,80 @@ int oracle_release_job(int stamp_fd, uint64_t stamp_off, uint32_t page, int out_
     rets[5] = munmap(m, bytes) == 0 ? 0 : -errno;
     for (int i = 0; i < 6; i++)
         if (rets[i] < 0) return (int)rets[i];
+    return 0;
+}
+
+/* --------------------------------------- block permutation, then pwrite */
+/*
+ * The ordering / blocking microbenchmark of section 6 (Fig. 6): an array of
+ * random values is cut into 8 KiB blocks, each block is permuted `iters`
+ * times, and the permuted block is written to a file with pwrite.  The paper
+ * likens the permutation to DES's permutation steps and fixes nothing more;
+ * here one round maps the block x (1024 little-endian 64-bit words) to y with
+ *
+ *     bit j of y[i]  =  bit tau[j] of x[sigma[i]]     (i < 1024, j < 64),
+ *
+ * a shuffle of the words followed by a shuffle of the bits inside each word.
+ * sigma and tau are inputs.  Block b is then written with
+ * pwrite(fd, block, 8192, file_off + 8192 * b); ret[b] gets its result or
+ * -errno.  Blocks are split into contiguous ranges, one per thread.
+ */
+#define PERM_WORDS 1024
+
+struct pm_job {
+    int fd;
+    const uint64_t *in;
+    const uint16_t *sigma;
+    const uint8_t *tau;
+    uint32_t iters;
+    uint64_t file_off;
+    uint64_t lo, hi;
+    int64_t *ret;
+};
+
+static uint64_t bit_shuffle(uint64_t w, const uint8_t *tau)
+{
+    uint64_t y = 0;
+    for (int j = 0; j < 64; j++)
+        y |= ((w >> tau[j]) & 1u) << j;
+    return y;
+}
+
+static void *pm_worker(void *arg)
+{
+    struct pm_job *j = (struct pm_job *)arg;
+    uint64_t x[PERM_WORDS], y[PERM_WORDS];
+    for (uint64_t b = j->lo; b < j->hi; b++) {
+        memcpy(x, j->in + b * PERM_WORDS, sizeof x);
+        for (uint32_t it = 0; it < j->iters; it++) {
+            for (int i = 0; i < PERM_WORDS; i++)
+                y[i] = bit_shuffle(x[j->sigma[i]], j->tau);
+            memcpy(x, y, sizeof x);
+        }
+        ssize_t r = pwrite(j->fd, x, sizeof x, (off_t)(j->file_off + b * sizeof x));
+        j->ret[b] = r < 0 ? -errno : r;
+    }
+    return NULL;
+}
+
+int oracle_permute(int fd, const uint64_t *in, uint64_t n_blocks, const uint16_t *sigma,
+                   const uint8_t *tau, uint32_t iters, uint64_t file_off, int64_t *ret,
+                   int threads)
+{
+    for (int i = 0; i < PERM_WORDS; i++)
+        if (sigma[i] >= PERM_WORDS) return -EINVAL;
+    for (int j = 0; j < 64; j++)
+        if (tau[j] >= 64) return -EINVAL;
+    if (threads < 1) threads = 1;
+    if ((uint64_t)threads > n_blocks) threads = n_blocks ? (int)n_blocks : 1;
+    pthread_t th[256];
+    struct pm_job jobs[256];
+    if (threads > 256) threads = 256;
+    for (int t = 0; t < threads; t++) {
+        jobs[t] = (struct pm_job){fd, in, sigma, tau, iters, file_off,
+                                  n_blocks * t / threads, n_blocks * (t + 1) / threads, ret};
+        if (pthread_create(&th[t], NULL, pm_worker, &jobs[t]) != 0) return -EAGAIN;
+    }
+    for (int t = 0; t < threads; t++) pthread_join(th[t], NULL);
     return 0;
 }

@@ -11,8 +11,9 @@ Files go to a tmpfs directory (``/dev/shm/gsys`` by default, overridable with
 
 The workload shapes follow the paper's evaluation: the pread microbenchmarks
 of section 6 (Fig. 5, files on tmpfs), the wordcount case study of section 7.1
-(64 search strings over many files), the UDP server of section 7.3 and the
-madvise memory-release use of section 7.2.  The paper's own datasets (a Linux
+(64 search strings over many files), the UDP server of section 7.3, the
+madvise memory-release use of section 7.2 and the block-permutation array of
+section 6 (Fig. 6).  The paper's own datasets (a Linux
 source tree on an SSD, miniAMR's input, a NIC) are not available; these
 synthetic inputs stand in for them.
 """
@@ -343,6 +344,31 @@ def job_stream(n_jobs: int = 55_000, rate_per_s: float = 20_000.0,
     content = np.frombuffer(rng(config, 3).bytes(total_w), dtype=np.uint8).copy()
     return JobStream(kind=kind, arrival_ns=arrival, arg_off=arg_off, arg_len=arg_len,
                      content_off=content_off, content=content)
+
+
+# ---------------------------------------------------------------------------
+# block permutation + pwrite (the ordering / blocking microbenchmark)
+# ---------------------------------------------------------------------------
+
+PERM_BLOCK = 8192          # bytes per block: 1024 little-endian 64-bit words
+PERM_WORDS = PERM_BLOCK // 8
+
+
+@dataclass
+class PermuteSet:
+    data: np.ndarray   # uint64[n_blocks * 1024], the pre-loaded random array
+    sigma: np.ndarray  # uint16[1024]: a permutation of the word positions
+    tau: np.ndarray    # uint8[64]: a permutation of the bit positions
+
+
+def permute_set(n_blocks: int = 8192, config: int = 6) -> PermuteSet:
+    """Random array of 8 KiB blocks and the two random shuffles (word order
+    and bit order) that one permutation round applies."""
+    data = rng(config, 0).integers(0, 1 << 64, n_blocks * PERM_WORDS, dtype=np.uint64,
+                                   endpoint=False)
+    sigma = rng(config, 1).permutation(PERM_WORDS).astype(np.uint16)
+    tau = rng(config, 2).permutation(64).astype(np.uint8)
+    return PermuteSet(data=data, sigma=sigma, tau=tau)
 
 
 def digest(*arrays) -> str:

@@ -205,3 +205,95 @@ def test_release_job_stamp_then_zeros(tmpdata):
     finally:
         os.close(sfd)
         os.close(ofd)
+
+
+# --------------------------------------------------------------- permutation
+
+def _bits_round(bits: np.ndarray, sigma: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """One round as a gather over the flat bit index 64*i + j of a block
+    (numpy's unpackbits on little-endian words numbers the bits that way)."""
+    idx = (sigma.astype(np.int64)[:, None] * 64 + tau.astype(np.int64)[None, :]).ravel()
+    return bits.reshape(-1, 65536)[:, idx].ravel()
+
+
+def _permute_file(tmpdata, name, data, sigma, tau, iters, threads=2, file_off=0):
+    p = os.path.join(tmpdata, name)
+    fd = os.open(p, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+    try:
+        ret = oracle.permute(fd, data, sigma, tau, iters, file_off=file_off, threads=threads)
+    finally:
+        os.close(fd)
+    return ret, np.fromfile(p, dtype=np.uint8)[file_off:]
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+def test_permute_vs_flat_bit_gather(tmpdata, iters):
+    ps = synth.permute_set(n_blocks=3)
+    ret, got = _permute_file(tmpdata, "perm_gather.bin", ps.data, ps.sigma, ps.tau, iters)
+    assert ret.tolist() == [8192] * 3
+    bits = np.unpackbits(ps.data.astype("<u8").view(np.uint8), bitorder="little")
+    for _ in range(iters):
+        bits = _bits_round(bits, ps.sigma, ps.tau)
+    want = np.packbits(bits, bitorder="little")
+    assert np.array_equal(got, want)
+    if iters == 0:
+        assert got.tobytes() == ps.data.astype("<u8").tobytes()
+
+
+def test_permute_byte_reversal_is_bswap(tmpdata):
+    data = synth.permute_set(n_blocks=2).data
+    sigma = np.arange(1024, dtype=np.uint16)
+    tau = np.array([8 * (7 - j // 8) + j % 8 for j in range(64)], dtype=np.uint8)
+    _, got = _permute_file(tmpdata, "perm_bswap.bin", data, sigma, tau, 1)
+    assert got.view("<u8").tolist() == data.byteswap().tolist()
+    _, got2 = _permute_file(tmpdata, "perm_bswap2.bin", data, sigma, tau, 2)
+    assert got2.view("<u8").tolist() == data.tolist()
+
+
+@pytest.mark.parametrize("r,k", [(1, 1), (5, 3), (1000, 7)])
+def test_permute_rotation_closed_form(tmpdata, r, k):
+    data = synth.permute_set(n_blocks=2).data
+    sigma = ((np.arange(1024) + r) % 1024).astype(np.uint16)
+    tau = np.arange(64, dtype=np.uint8)
+    _, got = _permute_file(tmpdata, "perm_rot.bin", data, sigma, tau, k)
+    want = np.concatenate([np.roll(blk, -k * r) for blk in data.reshape(2, 1024)])
+    assert got.view("<u8").tolist() == want.tolist()
+
+
+def test_permute_order_returns_identity(tmpdata):
+    # sigma: 3-cycles on words 0..299, 2-cycles on words 300..499, fixed
+    # elsewhere (order 6); tau: 4-cycles on the 64 bits (order 4) -> the
+    # round has order lcm(6, 4) = 12: 12 rounds give back the block, 6 and 4
+    # rounds do not.
+    sigma = np.arange(1024)
+    for a in range(0, 300, 3):
+        sigma[a:a + 3] = [a + 1, a + 2, a]
+    for a in range(300, 500, 2):
+        sigma[a:a + 2] = [a + 1, a]
+    tau = np.arange(64).reshape(16, 4)[:, [1, 2, 3, 0]].ravel()
+    data = synth.permute_set(n_blocks=1).data
+    for iters, same in ((12, True), (24, True), (6, False), (4, False)):
+        _, got = _permute_file(tmpdata, "perm_order.bin", data, sigma.astype(np.uint16),
+                               tau.astype(np.uint8), iters)
+        assert (got.view("<u8").tolist() == data.tolist()) == same, iters
+
+
+def test_permute_keeps_popcounts_and_threads_agree(tmpdata):
+    ps = synth.permute_set(n_blocks=9)
+    _, a = _permute_file(tmpdata, "perm_t1.bin", ps.data, ps.sigma, ps.tau, 5, threads=1)
+    _, b = _permute_file(tmpdata, "perm_t4.bin", ps.data, ps.sigma, ps.tau, 5, threads=4)
+    assert np.array_equal(a, b)
+    pc = lambda w: np.unpackbits(w.astype("<u8").view(np.uint8)).reshape(-1, 64).sum(1)
+    assert sorted(pc(a.view("<u8")).tolist()) == sorted(pc(ps.data).tolist())
+
+
+def test_permute_offset_bad_fd_and_bad_tables(tmpdata):
+    ps = synth.permute_set(n_blocks=2)
+    ret, got = _permute_file(tmpdata, "perm_off.bin", ps.data, ps.sigma, ps.tau, 0,
+                             file_off=4096)
+    assert ret.tolist() == [8192, 8192] and got.tobytes() == ps.data.astype("<u8").tobytes()
+    assert oracle.permute(987654, ps.data, ps.sigma, ps.tau, 1).tolist() == [-errno.EBADF] * 2
+    bad = ps.sigma.copy()
+    bad[3] = 1024
+    with pytest.raises(OSError):
+        oracle.permute(987654, ps.data, bad, ps.tau, 1)
