@@ -379,6 +379,30 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
                 uint64_t out_ret, uint32_t cell, uint32_t wg_size, void *stream);
 
 /*
+ * Block permutation written out with pwrite: the ordering / blocking
+ * microbenchmark of section 6 (Fig. 6).  `in` (device, n_blocks * 8192
+ * bytes, little-endian 64-bit words) is cut into 8 KiB blocks; one
+ * work-group of 1024 work-items per block applies `iters` rounds of
+ *     bit j of y[i] = bit tau[j] of x[sigma[i]]   (i < 1024, j < 64)
+ * and then issues one work-group pwrite(fd, staging + 8192 b, 8192,
+ * file_off + 8192 b) under the ordering / blocking of `cell` (work-group
+ * granularity only).  The result never lands in `in`.
+ *   sigma, tau  host arrays: permutations of 0..1023 and 0..63 (copied into
+ *               the launch; anything else is -EINVAL)
+ *   staging     registered GSYS_BUF_HOST, n_blocks * 8192 bytes; it must not
+ *               be reused before gsys_wait returns
+ *   out_ret     device int64[n_blocks]: blocking cells get pwrite's result;
+ *               non-blocking cells get GSYS_NOT_WAITED (the results are in
+ *               the ledger) unless the call could not be issued
+ * n_blocks == 0 launches nothing.  The launch is asynchronous on `stream`;
+ * non-blocking calls may still be in service when the kernel ends:
+ * gsys_wait drains them.  Errors: -EINVAL (cell, tables, sizes), -EFAULT.
+ */
+int gsys_permute(gsys_ctx *ctx, int fd, uint64_t in, const uint16_t *sigma, const uint8_t *tau,
+                 uint64_t n_blocks, uint32_t iters, uint64_t staging, uint64_t file_off,
+                 uint64_t out_ret, uint32_t cell, void *stream);
+
+/*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable
  * address: registered host memory or HBM); one kernel computes

@@ -34,6 +34,7 @@ CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN = 0x1, 0x2, 0x4
 FD_READ, FD_WRITE, FD_SOCK = 0x1, 0x2, 0x4
 BUF_HOST, BUF_DEVICE = 1, 2
 EMU_BLOCKING, EMU_LIST = 0x1, 0x2
+NOT_WAITED = -115   # a non-blocking call's result slot before anyone waited
 
 
 def cell(gran: int, strong: bool, blocking: bool) -> int:
@@ -123,6 +124,8 @@ _SIGS = {
                                  C.c_uint64, _P, _P]),
     "gsys_canary": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                               C.c_uint32, C.c_uint32, _P]),
+    "gsys_permute": (C.c_int, [_P, C.c_int, C.c_uint64, _P, _P, C.c_uint64, C.c_uint32,
+                               C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P]),
     "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                     C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),
