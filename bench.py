@@ -53,10 +53,13 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=55000, help="serve: jobs in the stream")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="serve: arrivals per second")
     ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
+    ap.add_argument("--serve-sweep", default="",
+                    help="serve: offered loads (jobs/s, comma-separated) to sweep after the "
+                         "main run, about 2.75 s of arrivals each")
     ap.add_argument("--perm-iters", default="1,4,16,64,256,1024,2048,4096",
                     help="permute: permutation rounds per block before the pwrite")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "wordscan", "kv", "serve", "permute"],
+                    choices=["sweep", "tiny", "wordscan", "kv", "serve", "permute"],
                     help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
                          "word search over 2,000 files")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -126,6 +129,8 @@ def main():
         return run_serve(args)
     if args.workload == "permute":
         return run_permute(args)
+    if args.workload == "tiny":
+        return run_tiny(args)
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
@@ -594,6 +599,32 @@ def run_serve(args):
         cpu = {"value": round(5000 / dtc, 1), "unit": "jobs/s", "cores": threads, "kind": "oracle",
                "sample": "the first 5,000 jobs run back to back by the oracle on a pool of %d "
                          "threads (closed loop: capacity, not latency)" % threads}
+    kinds = {}
+    for k, nm in ((0, "scan"), (1, "pwrite"), (2, "release")):
+        lk = lat_s[js.kind[warm:] == k]
+        if len(lk):
+            kinds[nm] = {"jobs": int(len(lk)), "p50": round(float(np.percentile(lk, 50)), 1),
+                         "p99": round(float(np.percentile(lk, 99)), 1)}
+    sweep = []
+    for rate in [float(x) for x in args.serve_sweep.split(",") if x]:
+        n_r = max(2000, int(rate * 2.75))
+        jr = synth.job_stream(n_jobs=n_r, rate_per_s=rate)
+        srr = ServeRun(ctx, jr, in_path, out_path + ".sweep")
+        t1 = time.perf_counter()
+        rr, _, lr = srr.run(g.PERSISTENT, max_inflight=args.serve_inflight,
+                            staging_bytes=(2 << 20) * 256, timeout_ns=300_000_000_000)
+        dtr = time.perf_counter() - t1
+        w_r = n_r // 10
+        lrs = lr[w_r:].astype(np.float64) / 1e3
+        span_r = (float(jr.arrival_ns[-1]) - float(jr.arrival_ns[w_r])) / 1e9 + \
+            float(np.median(lrs)) / 1e6
+        sweep.append({"offered_jobs_per_s": rate, "jobs": n_r,
+                      "jobs_per_s": round((n_r - w_r) / span_r, 1),
+                      "latency_us_p50": round(float(np.percentile(lrs, 50)), 1),
+                      "latency_us_p99": round(float(np.percentile(lrs, 99)), 1),
+                      "session_s": round(dtr, 3)})
+        srr.close()
+        print("sweep %.0f/s done" % rate, file=sys.stderr, flush=True)
     st = ctx.stats()
     res_j = {
         "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
@@ -609,9 +640,12 @@ def run_serve(args):
         "latency_us_p50": round(float(np.percentile(lat_s, 50)), 1),
         "latency_us_p99": round(float(np.percentile(lat_s, 99)), 1),
         "offered_jobs_per_s": args.serve_rate,
+        "latency_us_by_kind": kinds,
         "scan_GBps": round(float(js.arg_len[js.kind == 0].sum()) / dt / 1e9, 3),
         "host_calls": st["host_calls"],
     }
+    if sweep:
+        res_j["offered_load_sweep"] = sweep
     if plain:
         res_j["plain_form"] = plain
     if cpu:
@@ -751,6 +785,91 @@ def run_permute(args):
                      "bytes_per_launch": link_bytes},
         "lds_roofline_at_%d" % hi: {"achieved": round(lds_tbs, 2), "peak": round(lds_peak, 2),
                                      "unit": "TB/s", "frac": round(lds_tbs / lds_peak, 4)},
+    }
+    if cpu:
+        res["cpu_baseline"] = cpu
+    r.close()
+    ctx.shutdown()
+    print(json.dumps(res), flush=True)
+
+
+def run_tiny(args):
+    """Plain form, tiny: one work-group of 64 work-items, each a blocking
+    pread of 4 KiB at 4096 i from a 256 KiB file of random bytes (work-item,
+    strong), FNV-1a per item.  Latency only, no roofline: per launch the
+    end-to-end time (launch until the host pool has drained), the kernel's
+    duration, and per call the time from the launch to the end of its
+    service on the host and the service itself (ledger timestamps, the same
+    CLOCK_MONOTONIC).  value = 64 calls / median end-to-end time."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+    path = synth.random_file(1, 262144, name="c1_256k.bin")
+    offs = synth.tiny_offsets(64)
+    want, _ = oracle.pread_fnv(path, offs, 4096)
+    ctx = g.Context(ring_slots=1 << 10, service_threads=max(0, args.service_threads),
+                    device_timeout_ns=10_000_000_000, flags=g.CFG_LEDGER)
+    r = FnvRunner(ctx, path, offs, 4096, wg_size=64)
+    stream = torch.cuda.current_stream()
+    cell = g.cell_code("WI", "strong", "block")
+    reps = max(20, args.steps)
+    for _ in range(max(1, args.warmup)):
+        r.launch(cell, g.PLAIN, stream)
+        torch.cuda.synchronize()
+        ctx.wait(10_000_000_000)
+    ctx.ledger(reset=True)
+    e2e, kern, to_done, service = [], [], [], []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns()
+        e0.record(stream)
+        r.launch(cell, g.PLAIN, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if ctx.wait(10_000_000_000):
+            raise RuntimeError("drain failed")
+        e2e.append((time.monotonic_ns() - t0) / 1e3)
+        kern.append(e0.elapsed_time(e1) * 1e3)
+        led = ctx.ledger(reset=True)
+        if len(led) != 64:
+            raise RuntimeError("expected 64 serviced calls, got %d" % len(led))
+        t_end = (led[:, 5] >> np.uint64(8)).astype(np.int64)
+        to_done.extend(((t_end - t0) / 1e3).tolist())
+        service.extend(((t_end - led[:, 4].astype(np.int64)) / 1e3).tolist())
+    f, ret = r.result()
+    if not ((ret == 4096).all() and (f == want).all()):
+        raise RuntimeError("GPU checksums differ from the oracle")
+    cpu = None
+    if not args.no_cpu:
+        n_cpu = 2000
+        ts = []
+        for _ in range(n_cpu):
+            t1 = time.perf_counter()
+            oracle.pread_fnv(path, offs, 4096, threads=1)
+            ts.append(time.perf_counter() - t1)
+        cpu = {"value": round(64 / float(np.median(ts)), 1), "unit": "calls/s", "cores": 1,
+               "kind": "oracle", "latency_us_p50": round(1e6 * float(np.median(ts)), 2),
+               "sample": "the same 64 preads + checksums, one thread, median of %d runs "
+                         "(includes opening the file)" % n_cpu}
+    med = float(np.median(e2e))
+    pc = lambda xs, q: round(float(np.percentile(xs, q)), 2)
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(64 / (med * 1e-6), 1), "unit": "calls/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": round(med / 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "tiny plain form: 1 work-group x 64 work-items, blocking 4 KiB "
+                               "pread at 4096 i of a 256 KiB file, work-item / strong",
+                   "form": "plain"},
+        "end_to_end_us": {"p50": pc(e2e, 50), "p99": pc(e2e, 99), "min": round(min(e2e), 2)},
+        "kernel_us": {"p50": pc(kern, 50), "p99": pc(kern, 99)},
+        "per_call_launch_to_serviced_us": {"p50": pc(to_done, 50), "p99": pc(to_done, 99)},
+        "per_call_service_us": {"p50": pc(service, 50), "p99": pc(service, 99)},
     }
     if cpu:
         res["cpu_baseline"] = cpu

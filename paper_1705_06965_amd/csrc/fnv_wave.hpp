@@ -43,13 +43,15 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
 // current step is hashed, so the host-link round trip overlaps the FNV chain.
 // Rows of a wavefront are consecutive items, so row r starts at
 // row0 + r * item_bytes; each row's byte count sits in LDS next to the tile.
+// The loads are global and the tile accesses LDS (not flat) instructions, so
+// the LDS reads of the hashing loop never wait for the loads in flight.
 template <uint32_t CH>
 struct Tile {
   static constexpr uint32_t kLanesPerRow = CH / 16;
   static constexpr uint32_t kRowsPerLoad = 64 / kLanesPerRow;
   static constexpr uint32_t kLoads = 64 / kRowsPerLoad;
   static constexpr uint32_t kRowStride = CH + 16;  // pad: conflict-free 16-byte LDS reads
-  static constexpr uint32_t kBytes = 64 * kRowStride + 64 * 4;
+  static constexpr uint32_t kBytes = 64 * kRowStride + 64 * 4;  // + each row's byte count
 };
 
 // 256-byte rows for work-groups of up to 256 work-items; 128-byte rows for
@@ -61,29 +63,31 @@ template <uint32_t WGMAX>
 constexpr uint32_t chunk_for() { return WGMAX <= 256 ? 256u : 128u; }
 
 // All 64 lanes of the wave call this.  Lane l hashes `nbytes` bytes of item
-// row0 + l * item_bytes.  `tile` is this wave's LDS tile.
+// row0 + l * item_bytes.  `tile` is this wave's LDS tile (Tile<CH>::kBytes).
 template <uint32_t CH>
-__device__ uint64_t wave_fnv_t(uint64_t row0, uint32_t nbytes, uint32_t item_bytes, uint8_t* tile) {
+__device__ __forceinline__ uint64_t wave_fnv_t(uint64_t row0, uint32_t nbytes,
+                                               uint32_t item_bytes, uint8_t* tile_generic) {
   using T = Tile<CH>;
+  lptr_t<uint8_t> tile = lp(tile_generic);
   const uint32_t lane = lane_id();
   const uint32_t col = lane % T::kLanesPerRow;
   const uint32_t rsub = lane / T::kLanesPerRow;
-  uint32_t* rlen = reinterpret_cast<uint32_t*>(tile + 64 * T::kRowStride);
-  rlen[lane] = nbytes;
   uint32_t maxlen = nbytes;
   for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, (uint32_t)__shfl_xor((int)maxlen, o, 64));
   if (maxlen > item_bytes) maxlen = item_bytes;
+  lptr_t<uint32_t> rlen = reinterpret_cast<lptr_t<uint32_t>>(tile + 64 * T::kRowStride);
+  rlen[lane] = nbytes;
   __builtin_amdgcn_wave_barrier();
   uint64_t h = 0xcbf29ce484222325ull;
-  uint4 v[T::kLoads];
+  u32x4 v[T::kLoads];
   auto load = [&](uint32_t off) {
 #pragma unroll
     for (uint32_t k = 0; k < T::kLoads; ++k) {
       const uint32_t r = k * T::kRowsPerLoad + rsub;
-      v[k] = make_uint4(0, 0, 0, 0);
+      v[k] = u32x4{0, 0, 0, 0};
       // a row is read only where it holds bytes, inside its own item slot
       if (off < rlen[r] && off + col * 16 < item_bytes)
-        v[k] = *reinterpret_cast<const uint4*>(row0 + (uint64_t)r * item_bytes + off + col * 16);
+        v[k] = ldg16(row0 + (uint64_t)r * item_bytes + off + col * 16);
     }
   };
   if (maxlen) load(0);
@@ -91,15 +95,15 @@ __device__ uint64_t wave_fnv_t(uint64_t row0, uint32_t nbytes, uint32_t item_byt
 #pragma unroll
     for (uint32_t k = 0; k < T::kLoads; ++k) {
       const uint32_t r = k * T::kRowsPerLoad + rsub;
-      *reinterpret_cast<uint4*>(tile + r * T::kRowStride + col * 16) = v[k];
+      *reinterpret_cast<lptr_t<u32x4>>(tile + r * T::kRowStride + col * 16) = v[k];
     }
     __builtin_amdgcn_wave_barrier();
     if (off + CH < maxlen) load(off + CH);  // prefetch the next step
-    const uint8_t* row = tile + lane * T::kRowStride;
+    lptr_t<const uint8_t> row = tile + lane * T::kRowStride;
     if (off + CH <= nbytes) {
 #pragma unroll 2
       for (uint32_t q = 0; q < CH / 16; ++q) {
-        const uint4 w = *reinterpret_cast<const uint4*>(row + q * 16);
+        const u32x4 w = *reinterpret_cast<lptr_t<const u32x4>>(row + q * 16);
         h = fnv_word4(h, w.x);
         h = fnv_word4(h, w.y);
         h = fnv_word4(h, w.z);
@@ -108,7 +112,7 @@ __device__ uint64_t wave_fnv_t(uint64_t row0, uint32_t nbytes, uint32_t item_byt
     } else if (off < nbytes) {
       const uint32_t left = nbytes - off;
       for (uint32_t q = 0; q < CH / 4 && q * 4 < left; ++q) {
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(row + q * 4);
+        const uint32_t w = *reinterpret_cast<lptr_t<const uint32_t>>(row + q * 4);
         const int nb = (int)min(4u, left - q * 4);
         h = fnv_word(h, w, nb);
       }

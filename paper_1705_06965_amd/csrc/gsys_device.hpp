@@ -65,20 +65,44 @@ struct Ticket {
 };
 
 // ----------------------------------------------------------- memory helpers
+// Address-space views.  Host staging, slots and registered buffers travel as
+// integers or generic pointers, and accesses through those compile to flat
+// instructions.  A flat access counts against the LDS counter as well as the
+// memory counter, so every wait for an LDS result would also wait for each
+// load still in flight over the host link, serialising a wavefront's
+// prefetches.  gp() makes an access global, lp() makes it an LDS access.
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T*;
+template <class T>
+using lptr_t = __attribute__((address_space(3))) T*;
+template <class T>
+__device__ __forceinline__ gptr_t<T> gp(uint64_t a) { return (gptr_t<T>)a; }
+template <class T>
+__device__ __forceinline__ gptr_t<T> gp(T* p) { return (gptr_t<T>)p; }
+template <class T>
+__device__ __forceinline__ lptr_t<T> lp(T* p) { return (lptr_t<T>)p; }
+// 16-byte accesses use a plain vector type: uint4 is a class, and a class
+// object cannot be copied through an address-space-qualified pointer.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 ldg16(uint64_t a) { return *gp<const u32x4>(a); }
+__device__ __forceinline__ void stg16(uint64_t a, u32x4 v) { *gp<u32x4>(a) = v; }
+__device__ __forceinline__ uint4 to_uint4(u32x4 v) { return make_uint4(v.x, v.y, v.z, v.w); }
+__device__ __forceinline__ u32x4 to_u32x4(uint4 v) { return u32x4{v.x, v.y, v.z, v.w}; }
+
 __device__ __forceinline__ uint64_t ld_sys(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ uint64_t ld_sys_acq(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __hip_atomic_load(gp(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ int64_t ld_sys_i64(const int64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void st_sys(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void st_sys_rel(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void fence_release_sys() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, ""); }
 __device__ __forceinline__ void fence_acquire_sys() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
@@ -137,7 +161,7 @@ __device__ __forceinline__ void publish(const gsys_dev_ctx& c, uint64_t t, uint1
                                         uint64_t a0, uint64_t a1, uint64_t a2, uint64_t a3,
                                         uint64_t a4, uint64_t a5) {
   gsys_slot* s = c.ring + (t & c.ring_mask);
-  uint64_t* w = reinterpret_cast<uint64_t*>(s);
+  gptr_t<uint64_t> w = gp(reinterpret_cast<uint64_t*>(s));
   st_sys(&s->ctl, GSYS_CTL(t, GSYS_ST_POPULATING));
   const uint64_t hdr = (uint64_t)nr | ((uint64_t)flags << 16) | ((uint64_t)grp_n << 24) |
                        ((uint64_t)grp_off << 32);
@@ -231,7 +255,7 @@ __device__ inline int64_t call_wi(const gsys_dev_ctx& c, uint16_t nr, const Args
   const uint32_t leader = first_lane(m);
   uint64_t base = 0;
   if (lane_id() == leader)
-    base = __hip_atomic_fetch_add(c.tail, (unsigned long long)n, __ATOMIC_RELAXED,
+    base = __hip_atomic_fetch_add(gp(c.tail), (unsigned long long)n, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   base = bcast64(base, leader);
   Ticket tk{base + rank, rank, n};
@@ -284,7 +308,7 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
   Ticket tk{0, 0, 0};
   int64_t ret = GSYS_NOT_WAITED;
   if (threadIdx.x == 0) {
-    uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t t = __hip_atomic_fetch_add(gp(c.tail), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int err = wait_slot_free(c, t);
     if (err) {
       ret = err;
@@ -315,6 +339,9 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
     __syncthreads();
     ret = s_ret;
     fence_acquire_sys();
+    // thread 0 may write s_ret again in the next call before any barrier of
+    // that call: every work-item takes its copy first
+    __syncthreads();
     if constexpr (b == B::NonBlocking) ret = GSYS_NOT_WAITED;
   } else if constexpr (b == B::Blocking) {
     // weak-block: only the caller's wavefront waits (section 6).
@@ -338,7 +365,9 @@ __device__ inline int64_t wait_wg(const gsys_dev_ctx& c, const Ticket& tk_thread
   }
   __syncthreads();
   fence_acquire_sys();
-  return s_ret;
+  const int64_t r = s_ret;
+  __syncthreads();  // s_ret is rewritten by the next wait before any barrier
+  return r;
 }
 
 // Per-launch state of one kernel-granularity call site; zero it before each
@@ -374,11 +403,11 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
   if (threadIdx.x == 0) {
     int caller;
     if (producer) {
-      caller = __hip_atomic_fetch_add(&ks->arrived, 1u, __ATOMIC_ACQ_REL,
+      caller = __hip_atomic_fetch_add(gp(&ks->arrived), 1u, __ATOMIC_ACQ_REL,
                                       __HIP_MEMORY_SCOPE_AGENT) == nwg - 1;
     } else {
       unsigned int exp = 0;
-      caller = __hip_atomic_compare_exchange_strong(&ks->elect, &exp, 1u, __ATOMIC_ACQ_REL,
+      caller = __hip_atomic_compare_exchange_strong(gp(&ks->elect), &exp, 1u, __ATOMIC_ACQ_REL,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     s_caller = caller;
@@ -393,7 +422,7 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
     __syncthreads();
     if (threadIdx.x == 0) {
       Args6 a = make_args();
-      uint64_t t = __hip_atomic_fetch_add(c.tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t t = __hip_atomic_fetch_add(gp(c.tail), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int err = wait_slot_free(c, t);
       if (err) {
         s_ret = err;
@@ -406,7 +435,7 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
         s_ret = 0;
       }
       if (!producer)
-        __hip_atomic_store(&ks->ticket, s_t1 ? s_t1 : KS_FAILED, __ATOMIC_RELEASE,
+        __hip_atomic_store(gp(&ks->ticket), s_t1 ? s_t1 : KS_FAILED, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -416,7 +445,7 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
       Waiter w(c);
       unsigned long long v;
       for (;;) {
-        v = __hip_atomic_load(&ks->ticket, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        v = __hip_atomic_load(gp(&ks->ticket), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (v) break;
         if (!w.pause()) { v = KS_FAILED; break; }
       }
@@ -479,7 +508,9 @@ __device__ inline int64_t wait_kernel(const gsys_dev_ctx& c, const Ticket& tk) {
   }
   __syncthreads();
   fence_acquire_sys();
-  return s_ret;
+  const int64_t r = s_ret;
+  __syncthreads();  // s_ret is rewritten by the next wait before any barrier
+  return r;
 }
 
 }  // namespace gsys

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(1024) void canary(CnArgs A) {
   const uint64_t item = first + threadIdx.x;
   const bool valid = item < A.n;
   if (valid) {
-    uint64_t* p = reinterpret_cast<uint64_t*>(A.buf + item * 64);
+    gptr_t<uint64_t> p = gp<uint64_t>(A.buf + item * 64);
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) p[k] = stamp_word(A.seed, item, k);
   }

@@ -43,6 +43,7 @@ static_assert(sizeof(Bucket) == 32, "bucket is 32 bytes");
 
 // Per-work-group I/O region in pinned host memory.
 constexpr uint32_t kOffRecvList = 0;
+static_assert(sizeof(gsys_netdesc) == 32, "descriptors are written as two 16-byte vectors");
 constexpr uint32_t kOffSendList = kOffRecvList + kWG * sizeof(gsys_netdesc);
 constexpr uint32_t kOffRecv = kOffSendList + kWG * sizeof(gsys_netdesc);
 constexpr uint32_t kOffSend = kOffRecv + kWG * kReqBuf;
@@ -122,15 +123,14 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
     // barrier before it)
     if (tid < 64)
       for (uint32_t i = tid; i < A.batch; i += 64) {
-        gsys_netdesc d{};
-        d.buf_off = i * kReqBuf;
-        d.len_ret = (int32_t)kReqBuf;
-        rl[i] = d;
+        // {buf_off, len_ret, addr_len, pad}, then an empty address
+        stg16((uint64_t)(rl + i), u32x4{i * kReqBuf, kReqBuf, 0u, 0u});
+        stg16((uint64_t)(rl + i) + 16, u32x4{0u, 0u, 0u, 0u});
       }
     Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)rl, A.batch, rbase, 0, 0}};
     call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra);
     // datagrams arrive as a prefix of the list (the host stops at -EAGAIN)
-    int32_t got = tid < A.batch ? __hip_atomic_load(&rl[tid].len_ret, __ATOMIC_RELAXED,
+    int32_t got = tid < A.batch ? __hip_atomic_load(gp(&rl[tid].len_ret), __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_SYSTEM)
                                 : -1;
     const bool have = got >= 0;
@@ -150,8 +150,8 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
     uint32_t status = 2, vlen = 0;
     if (have) {
       const uint8_t* q = rbuf + tid * kReqBuf;
-      const uint4 w0 = *reinterpret_cast<const uint4*>(q);
-      const uint4 w1 = *reinterpret_cast<const uint4*>(q + 16);
+      const u32x4 w0 = ldg16((uint64_t)q);
+      const u32x4 w1 = ldg16((uint64_t)(q + 16));
       if (got >= 8) id = ((uint64_t)w0.y << 32) | w0.x;
       if (got == 32 && (w0.z & 0xffu) == 1u) {
         const uint64_t k0 = ((uint64_t)w1.y << 32) | w1.x;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
         uint64_t b = __umul64hi(fnv16(k0, k1), A.cap);
         status = 1;
         for (uint64_t p = 0; p < A.cap; ++p) {
-          const Bucket* bk = A.tab + b;
+          const gptr_t<const Bucket> bk = gp<const Bucket>((uint64_t)(A.tab + b));
           if (!bk->used) break;
           if (bk->k0 == k0 && bk->k1 == k1) {
             status = 0;
@@ -170,15 +170,12 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
           b = b + 1 == A.cap ? 0 : b + 1;
         }
       }
-      // reply descriptor: back to the sender recvfrom reported
-      gsys_netdesc d;
-      d.buf_off = tid * kRepBuf;
-      d.len_ret = (int32_t)(16 + vlen);
-      d.addr_len = rl[tid].addr_len;
-      d.pad = 0;
-      const uint4 a = *reinterpret_cast<const uint4*>(rl[tid].addr);
-      *reinterpret_cast<uint4*>(d.addr) = a;
-      sl[tid] = d;
+      // reply descriptor {buf_off, len_ret, addr_len, pad, addr}: back to
+      // the sender recvfrom reported
+      const u32x4 rh = ldg16((uint64_t)(rl + tid));
+      const u32x4 ra = ldg16((uint64_t)(rl + tid) + 16);
+      stg16((uint64_t)(sl + tid), u32x4{tid * kRepBuf, 16u + vlen, rh.z, 0u});
+      stg16((uint64_t)(sl + tid) + 16, ra);
     }
     // replies: one wavefront copies one reply per step, 16 B per lane
     uint64_t m = __ballot(have);
@@ -192,13 +189,13 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
       uint8_t* dst = sbuf + (uint64_t)((tid & ~63u) + j) * kRepBuf;
       const uint32_t chunks = 1 + (jlen + 15) / 16;
       for (uint32_t c = lane; c < chunks; c += 64) {
-        uint4 v;
+        u32x4 v;
         if (c == 0) {
-          v = make_uint4((uint32_t)jid, (uint32_t)(jid >> 32), jst | (jlen << 16), 0u);
+          v = u32x4{(uint32_t)jid, (uint32_t)(jid >> 32), jst | (jlen << 16), 0u};
         } else {
-          v = *reinterpret_cast<const uint4*>(A.heap + jvoff + 16 * (c - 1));
+          v = ldg16((uint64_t)(A.heap + jvoff + 16 * (c - 1)));
         }
-        *reinterpret_cast<uint4*>(dst + 16 * c) = v;
+        stg16((uint64_t)(dst + 16 * c), v);
       }
     }
     // send the replies (producer call: every lane's reply is released before)

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void permute(PmArgs A) {
     cur ^= 1;
   }
   const uint64_t at = A.stage + blk * kBlock;
-  reinterpret_cast<uint64_t*>(at)[t] = buf[cur][t];
+  gp<uint64_t>(at)[t] = buf[cur][t];
   Ticket tk{0, 0, 0};
   const int64_t r = call_wg<o, b>(
       A.c, GSYS_NR_PWRITE64, 0,

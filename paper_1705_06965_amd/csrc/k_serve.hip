@@ -92,10 +92,11 @@ __device__ int64_t pwrite_job(const SvArgs& A, const gsys_job& J, uint64_t stg0)
   const uint64_t n16 = J.len / 16;
   if ((J.src & 15) == 0) {
     for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x)
-      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
-    for (uint64_t i = n16 * 16 + threadIdx.x; i < J.len; i += blockDim.x) dst[i] = src[i];
+      stg16((uint64_t)dst + 16 * i, ldg16((uint64_t)src + 16 * i));
+    for (uint64_t i = n16 * 16 + threadIdx.x; i < J.len; i += blockDim.x)
+      gp(dst)[i] = gp(src)[i];
   } else {
-    for (uint64_t i = threadIdx.x; i < J.len; i += blockDim.x) dst[i] = src[i];
+    for (uint64_t i = threadIdx.x; i < J.len; i += blockDim.x) gp(dst)[i] = gp(src)[i];
   }
   Args6 a{{(uint64_t)(int64_t)J.fd, stg0, J.len, J.off, 0, 0}};
   // producer call: every lane's copy is released before it; only the

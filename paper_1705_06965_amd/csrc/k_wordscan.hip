@@ -135,7 +135,7 @@ __device__ __forceinline__ void load_sub(const uint8_t* stg, uint32_t cbuf, uint
     const uint32_t i = threadIdx.x + k * kWG;
     v[k] = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
     if (i < kCopyVec && sb0 + i * 16 + 16 <= cbuf)
-      v[k] = *reinterpret_cast<const uint4*>(stg + sb0 + i * 16);
+      v[k] = to_uint4(ldg16((uint64_t)(stg + sb0 + i * 16)));
   }
 }
 
