@@ -39,6 +39,8 @@ typedef struct gsys_ctx gsys_ctx;
 #define GSYS_CFG_LEDGER    0x1u  /* record every serviced ticket (exactly-once checks) */
 #define GSYS_CFG_NO_DEVICE 0x2u  /* host memory only, no HIP calls (CPU tests)        */
 #define GSYS_CFG_NO_PIN    0x4u  /* do not pin service threads to cores              */
+#define GSYS_CFG_SHARED_FDS 0x8u /* positional calls use the caller's descriptors
+                                    directly (no per-thread copies, see below)       */
 
 typedef struct gsys_config {
     uint32_t abi_version;        /* must be GSYS_ABI_VERSION                          */
@@ -79,6 +81,15 @@ int gsys_init(const gsys_config *cfg, gsys_ctx **out);
  * Allow GPU calls on `fd` with `perms` (GSYS_FD_*).  The caller keeps
  * ownership of the fd and must keep it open until gsys_wait() returns.
  * perms == 0 revokes the fd (later calls on it complete with -EBADF).
+ *
+ * For a regular file, each service thread runs pread / pwrite through its
+ * own open file description of the same file (opened on first use through
+ * /proc/self/fd with the fd's status flags), because calls from many
+ * threads on one description contend on its reference count in the
+ * kernel.  Positional calls behave the same on either; read / write use the
+ * caller's fd and its file offset.  A thread's copy is re-opened after the
+ * next gsys_allow_fd on that fd number and closed when the pool stops, so a
+ * revoked file stays open until then.  GSYS_CFG_SHARED_FDS turns this off.
  * Errors: -EBADF (fd < 0 or >= 65536).
  */
 int gsys_allow_fd(gsys_ctx *ctx, int fd, uint32_t perms);

@@ -30,7 +30,7 @@ F_BLOCKING, F_LIST, F_PRODUCER, F_STRONG = 0x1, 0x2, 0x4, 0x8
 GRAN_WI, GRAN_WG, GRAN_KERNEL = 0, 1, 2
 CELL_STRONG, CELL_BLOCKING = 0x4, 0x8
 PLAIN, PERSISTENT, GRAPH = 0, 1, 2
-CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN = 0x1, 0x2, 0x4
+CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS = 0x1, 0x2, 0x4, 0x8
 FD_READ, FD_WRITE, FD_SOCK = 0x1, 0x2, 0x4
 BUF_HOST, BUF_DEVICE = 1, 2
 EMU_BLOCKING, EMU_LIST = 0x1, 0x2

@@ -6,6 +6,7 @@
 #include <netinet/in.h>
 #include <pthread.h>
 #include <sched.h>
+#include <stdio.h>
 #include <string.h>
 #include <sys/mman.h>
 #include <sys/socket.h>
@@ -73,7 +74,8 @@ bool loopback_v4(const uint8_t* a, uint64_t len) {
 
 Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* retired_lo,
            const gsys_config& cfg)
-    : ring_(ring), comp_(comp), D_(D), C_(C), retired_lo_(retired_lo), fdperm_(65536) {
+    : ring_(ring), comp_(comp), D_(D), C_(C), retired_lo_(retired_lo), fdperm_(65536),
+      fdgen_(65536) {
   long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
   if (ncpu < 1) ncpu = 1;
   P_ = cfg.service_threads ? (int)cfg.service_threads : (int)std::max(1L, ncpu - 1);
@@ -90,6 +92,9 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
   for (auto& h : st_bhist_) h.store(0);
   for (auto& h : st_ehist_) h.store(0);
   for (auto& p : fdperm_) p.store(0);
+  for (auto& g : fdgen_) g.store(0);
+  copy_fds_ = !(cfg.flags & GSYS_CFG_SHARED_FDS);
+  fdcopies_.resize((size_t)P_);
 }
 
 Pool::~Pool() { stop_and_join(); }
@@ -115,8 +120,45 @@ int Pool::allow_fd(int fd, uint32_t perms) {
     if (fstat(fd, &st) != 0) return -errno;
     if (S_ISREG(st.st_mode)) v |= kRegular;
   }
+  fdgen_[fd].fetch_add(1, std::memory_order_acq_rel);
   fdperm_[fd].store(v, std::memory_order_release);
   return 0;
+}
+
+thread_local Pool::FdCopies* Pool::tls_copies_ = nullptr;
+
+namespace {
+// A new open file description of the file behind `fd`, with its access mode
+// and status flags; -1 if that is not possible.
+int reopen_same(int fd) {
+  const int fl = fcntl(fd, F_GETFL);
+  if (fl < 0) return -1;
+  char path[48];
+  snprintf(path, sizeof path, "/proc/self/fd/%d", fd);
+  const int keep = O_ACCMODE | O_APPEND | O_DIRECT | O_DSYNC | O_SYNC | O_NOATIME | O_NONBLOCK;
+  return open(path, (fl & keep) | O_CLOEXEC);
+}
+}  // namespace
+
+int Pool::fd_for(int64_t fd) {
+  FdCopies* pc = tls_copies_;
+  if (!pc || !copy_fds_ || fd < 0 || fd >= (int64_t)fdperm_.size() ||
+      !(fdperm_[fd].load(std::memory_order_relaxed) & kRegular))
+    return (int)fd;
+  const uint32_t g = fdgen_[fd].load(std::memory_order_acquire);
+  FdCopies::Ent* slot = nullptr;
+  for (FdCopies::Ent& e : pc->e)
+    if (e.src == (int)fd) {
+      if (e.gen == g) return e.fd >= 0 ? e.fd : (int)fd;
+      slot = &e;
+      break;
+    }
+  if (!slot) slot = &pc->e[pc->next++ % FdCopies::kEnts];
+  if (slot->fd >= 0) close(slot->fd);
+  slot->src = (int)fd;
+  slot->gen = g;
+  slot->fd = reopen_same((int)fd);
+  return slot->fd >= 0 ? slot->fd : (int)fd;
 }
 
 bool Pool::fd_ok(int64_t fd, uint32_t need) const {
@@ -214,7 +256,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       if (a[2] > (1ull << 31)) return -EINVAL;
       uint8_t* h = translate(a[1], a[2], true);
       if (!h) return -EFAULT;
-      ssize_t n = s.nr == GSYS_NR_PREAD64 ? pread((int)a[0], h, a[2], (off_t)a[3])
+      ssize_t n = s.nr == GSYS_NR_PREAD64 ? pread(fd_for((int64_t)a[0]), h, a[2], (off_t)a[3])
                                           : read((int)a[0], h, a[2]);
       ++*calls;
       r = n < 0 ? -(int64_t)errno : (int64_t)n;
@@ -227,7 +269,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       if (a[2] > (1ull << 31)) return -EINVAL;
       uint8_t* h = translate(a[1], a[2], false);
       if (!h) return -EFAULT;
-      ssize_t n = s.nr == GSYS_NR_PWRITE64 ? pwrite((int)a[0], h, a[2], (off_t)a[3])
+      ssize_t n = s.nr == GSYS_NR_PWRITE64 ? pwrite(fd_for((int64_t)a[0]), h, a[2], (off_t)a[3])
                                            : write((int)a[0], h, a[2]);
       ++*calls;
       r = n < 0 ? -(int64_t)errno : (int64_t)n;
@@ -329,6 +371,7 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
     gsys_iodesc* d = (gsys_iodesc*)translate(a[1], count * sizeof(gsys_iodesc), true);
     if (!d && count) return -EFAULT;
     const bool mergeable = (fdperm_[fd].load(std::memory_order_relaxed) & kRegular) != 0;
+    const int xfd = fd_for(fd);
     uint64_t i = 0;
     while (i < count) {
       const uint64_t off = d[i].off;
@@ -351,8 +394,8 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       } else if (!h) {
         r = -EFAULT;
       } else {
-        ssize_t n = rd ? pread((int)fd, h, (size_t)len, (off_t)off)
-                       : pwrite((int)fd, h, (size_t)len, (off_t)off);
+        ssize_t n = rd ? pread(xfd, h, (size_t)len, (off_t)off)
+                       : pwrite(xfd, h, (size_t)len, (off_t)off);
         ++*calls;
         r = n < 0 ? -(int64_t)errno : (int64_t)n;
       }
@@ -548,6 +591,7 @@ void Pool::retire_scan() {
 }
 
 void Pool::poller(int idx) {
+  tls_copies_ = &fdcopies_[(size_t)idx];
   if (pin_) {
     long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
     int first = first_cpu_ >= 0 ? first_cpu_ : 1;
@@ -618,6 +662,12 @@ void Pool::poller(int idx) {
       }
     }
   }
+  // the copies are closed by the thread that used them
+  for (FdCopies::Ent& e : fdcopies_[(size_t)idx].e) {
+    if (e.fd >= 0) close(e.fd);
+    e = FdCopies::Ent{};
+  }
+  tls_copies_ = nullptr;
 }
 
 uint64_t Pool::poison_outstanding(uint64_t claimed) {

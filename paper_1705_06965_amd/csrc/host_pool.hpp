@@ -84,6 +84,9 @@ class Pool {
   void complete(uint64_t t, gsys_slot* s, int64_t ret);
   uint8_t* translate(uint64_t dev, uint64_t len, bool need_host_write);
   bool fd_ok(int64_t fd, uint32_t need) const;
+  // The descriptor a positional call on regular file `fd` should use: this
+  // poller's own open file description of it (see FdCopies), or `fd`.
+  int fd_for(int64_t fd);
   void note_errno(int64_t ret);
 
   gsys_slot* ring_;
@@ -104,6 +107,30 @@ class Pool {
   std::atomic_flag retire_busy_ = ATOMIC_FLAG_INIT;
 
   std::vector<std::atomic<uint8_t>> fdperm_;
+  // Bumped by every allow_fd on an fd number: a poller's copy made under an
+  // older generation is re-opened before use.
+  std::vector<std::atomic<uint32_t>> fdgen_;
+  bool copy_fds_ = true;
+
+ public:
+  // A poller's private open file descriptions of allowed regular files.
+  // Many threads calling pread on one description all update its reference
+  // count in the kernel; with one description per thread the host's pread
+  // rate rose from ~10 M/s to ~16 M/s (15 threads, 4 KiB, tmpfs).
+  struct FdCopies {
+    struct Ent {
+      int src = -1;
+      uint32_t gen = 0;
+      int fd = -1;  // -1: re-opening failed, the caller's fd is used
+    };
+    static constexpr int kEnts = 8;
+    Ent e[kEnts];
+    uint32_t next = 0;
+  };
+
+ private:
+  std::vector<FdCopies> fdcopies_;
+  static thread_local FdCopies* tls_copies_;
 
   // buffer table: seqlock-protected fixed array
   static constexpr int kMaxBufs = 512;

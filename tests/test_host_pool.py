@@ -276,3 +276,98 @@ def test_exported_symbols_exist():
     assert "gsys_init" in names and "gsys_fnv4k" in names and "gsys_test_emulate" in names
     for n in names:
         assert hasattr(g.lib, n), n
+
+
+def _links_to(path):
+    """Open descriptors of this process that refer to `path`."""
+    real = os.path.realpath(path)
+    n = 0
+    for name in os.listdir("/proc/self/fd"):
+        try:
+            if os.readlink("/proc/self/fd/" + name) == real:
+                n += 1
+        except OSError:
+            pass
+    return n
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_per_thread_file_copies(datafile, shared):
+    """Positional calls on a regular file run through each service thread's
+    own open file description (unless GSYS_CFG_SHARED_FDS): the results are
+    the same either way, and the copies are closed when the pool stops."""
+    offs = synth.sweep_offsets(1024, (4 << 20) // 4096)
+    want_fnv, want_ret = oracle.pread_fnv(datafile, offs, 4096)
+    fd = os.open(datafile, os.O_RDONLY)
+    base = _links_to(datafile)
+    ctx = _ctx(ring_slots=1024, flags=g.CFG_SHARED_FDS if shared else 0)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf, rets = _run(ctx, fd, offs, 8, 1, g.EMU_BLOCKING)
+        assert (rets == want_ret).all()
+        data = buf.view(np.uint8).reshape(len(offs), 4096)
+        got = np.array([oracle.fnv1a64(data[i]) for i in range(len(offs))], dtype=np.uint64)
+        assert (got == want_fnv).all()
+        copies = _links_to(datafile) - base
+        if shared:
+            assert copies == 0
+        else:
+            assert 1 <= copies <= 4          # at most one per service thread
+    finally:
+        assert ctx.shutdown() == 0
+    assert _links_to(datafile) == base
+    os.close(fd)
+
+
+def test_reused_fd_number_reads_the_new_file(tmpdata):
+    """A thread's copy belongs to the file the fd number named when it was
+    made: after the number is revoked, closed and re-allowed for another
+    file, calls read the new file."""
+    a = os.path.join(tmpdata, "fd_a.bin")
+    b = os.path.join(tmpdata, "fd_b.bin")
+    open(a, "wb").write(b"A" * 8192)
+    open(b, "wb").write(b"B" * 8192)
+    ctx = _ctx(ring_slots=256, service_threads=2)
+    fa = os.open(a, os.O_RDONLY)
+    try:
+        ctx.allow_fd(fa, g.FD_READ)
+        offs = np.zeros(64, dtype=np.uint64)
+        buf, rets = _run(ctx, fa, offs, 4, 1, g.EMU_BLOCKING)
+        assert (rets == 4096).all() and (buf.view(np.uint8)[:64 * 4096] == ord("A")).all()
+        ctx.allow_fd(fa, 0)
+        fb = os.open(b, os.O_RDONLY)
+        os.dup2(fb, fa)                       # the same number now names fd_b.bin
+        os.close(fb)
+        ctx.allow_fd(fa, g.FD_READ)
+        buf2, rets2 = _run(ctx, fa, offs, 4, 1, g.EMU_BLOCKING)
+        assert (rets2 == 4096).all() and (buf2.view(np.uint8)[:64 * 4096] == ord("B")).all()
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fa)
+
+
+def test_copies_keep_append_and_write_modes(tmpdata):
+    """pwrite through a copy writes the caller's file; a write-only fd's copy
+    is write-only (a pread on it is refused by the kernel, as on the
+    original)."""
+    p = os.path.join(tmpdata, "fd_w.bin")
+    fd = os.open(p, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o600)
+    ctx = _ctx(ring_slots=256, service_threads=2)
+    try:
+        ctx.allow_fd(fd, g.FD_READ | g.FD_WRITE)
+        src = ctx.host_alloc(4096)
+        src.array[:4096] = np.arange(4096, dtype=np.uint64).astype(np.uint8)
+        ret = C.c_int64(0)
+        args = (C.c_uint64 * 6)(fd, src.dev, 4096, 8192, 0, 0)
+        assert g.lib.gsys_test_raw_call(ctx.h, g.NR_PWRITE64, g.F_BLOCKING, args, C.byref(ret),
+                                        5_000_000_000) == 0
+        assert ret.value == 4096
+        got = open(p, "rb").read()
+        assert len(got) == 12288 and got[8192:] == src.array[:4096].tobytes()
+        args = (C.c_uint64 * 6)(fd, src.dev, 4096, 0, 0, 0)
+        assert g.lib.gsys_test_raw_call(ctx.h, g.NR_PREAD64, g.F_BLOCKING, args, C.byref(ret),
+                                        5_000_000_000) == 0
+        assert ret.value == -errno.EBADF
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
