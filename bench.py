@@ -159,23 +159,24 @@ def main():
     stream = torch.cuda.current_stream()
     form = g.GRAPH if args.form == "graph" else g.PERSISTENT
 
-    def step(cell, fm, ev=None):
-        runner = r if fm != g.PLAIN else rp
+    def step(cell, fm, ev=None, on=None):
+        runner = on if on is not None else (r if fm != g.PLAIN else rp)
         if ev:
             ev[0].record(stream)
         runner.launch(cell, fm, stream)
         if ev:
             ev[1].record(stream)
         torch.cuda.synchronize()
-        rc = ctx.wait(60_000_000_000)
+        rc = runner.ctx.wait(60_000_000_000)
         if rc:
             raise RuntimeError("drain failed %d" % rc)
 
-    def timed(cell, fm, steps, warmup):
+    def timed(cell, fm, steps, warmup, on=None):
+        c = on.ctx if on is not None else ctx
         for _ in range(warmup):
-            step(cell, fm)
+            step(cell, fm, on=on)
         torch.cuda.synchronize()
-        ctx.stats(reset=True)
+        c.stats(reset=True)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(steps)]
         wall = []
@@ -183,12 +184,12 @@ def main():
         t0 = time.perf_counter()
         for i in range(steps):
             s0 = time.perf_counter()
-            step(cell, fm, evs[i])
+            step(cell, fm, evs[i], on=on)
             wall.append(time.perf_counter() - s0)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         kern_ms = [a.elapsed_time(b) for a, b in evs]
-        st = ctx.stats()
+        st = c.stats()
         return total, wall, kern_ms, st
 
     out = {}
@@ -212,6 +213,18 @@ def main():
               file=sys.stderr, flush=True)
         if "persistent" in out and not ((f2 == f).all() and (ret2 == ret).all()):
             raise RuntimeError("plain and persistent forms disagree")
+        if tp["service_threads"] not in (0, len(os.sched_getaffinity(0)) - 1):
+            # the plain form may prefer a different pool size than the
+            # tuned persistent one: time it on the full pool as well
+            ctx2 = g.Context(ring_slots=tp["ring_slots"], sleep_max=tp["sleep_max"],
+                             device_timeout_ns=60_000_000_000)
+            rp2 = FnvRunner(ctx2, path, offs, ITEM, wg_size=WG)
+            out["plain_full"] = timed(plain_cell, g.PLAIN, psteps, 1, on=rp2)
+            f3, ret3 = rp2.result()
+            if not ((f3 == f2).all() and (ret3 == ret2).all()):
+                raise RuntimeError("plain form differs between pools")
+            rp2.close()
+            ctx2.shutdown()
 
     cpu = None
     if not args.no_cpu:
@@ -255,7 +268,8 @@ def main():
                                "seeded random file on tmpfs + FNV-1a-64 per item",
                    "form": "persistent batched (%s)" % args.form,
                    "calls_per_step": calls_per_step,
-                   "service_threads": int(ctx.cfg.service_threads) or (os.cpu_count() or 2) - 1,
+                   "service_threads": int(ctx.cfg.service_threads) or
+                   len(os.sched_getaffinity(0)) - 1,
                    "staging_bytes": r.staging_bytes,
                    "tuned": {k: v for k, v in tp.items()},
                    "ring_slots": int(ctx.cfg.ring_slots)},
@@ -274,7 +288,7 @@ def main():
                  "service_us_per_call": round(st["service_ns"] / max(1, st["host_calls"]) / 1e3, 3),
                  "pool_busy_frac": round(st["service_ns"] / 1e9 / max(1e-9, total) /
                                          max(1, int(ctx.cfg.service_threads) or
-                                             (os.cpu_count() or 2) - 1), 3)},
+                                             len(os.sched_getaffinity(0)) - 1), 3)},
     }
     if "plain" in out and "persistent" in out:
         pt, pw, pk, _ = out["plain"]
@@ -283,6 +297,13 @@ def main():
                              "ms_per_step": round(1e3 * pt / len(pw), 3),
                              "kernel_ms": round(float(np.mean(pk)), 3)}
         res["persistent_over_plain"] = round(value / pv, 3)
+        if "plain_full" in out:
+            qt, qw, qk, _ = out["plain_full"]
+            qv = calls_per_step * len(qw) / qt
+            res["plain_form_full_pool"] = {"value": round(qv, 1), "unit": "syscalls/s",
+                                           "service_threads": len(os.sched_getaffinity(0)) - 1,
+                                           "ms_per_step": round(1e3 * qt / len(qw), 3)}
+            res["persistent_over_best_plain"] = round(value / max(pv, qv), 3)
     if cpu:
         res["cpu_baseline"] = cpu
     r.close()

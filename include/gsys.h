@@ -46,14 +46,16 @@ typedef struct gsys_config {
     uint32_t abi_version;        /* must be GSYS_ABI_VERSION                          */
     int32_t  device;             /* HIP device ordinal                                */
     uint32_t ring_slots;         /* D, power of two >= 64 (0 = 65536)                 */
-    uint32_t service_threads;    /* P host pollers (0 = online cores - 1, at least 1) */
+    uint32_t service_threads;    /* P host pollers (0 = CPUs in the process's affinity
+                                    mask - 1, at least 1)                            */
     uint32_t coalesce_max;       /* K: max calls per coalesced bundle (0/1 = off)     */
     uint32_t coalesce_window_ns; /* T: how long a poller waits to fill a bundle       */
     uint32_t stripe;             /* tickets per poller stripe (0 = 8)                 */
     uint32_t flags;              /* GSYS_CFG_*                                        */
     uint64_t arena_bytes;        /* reserved address range for GPU mmap (0 = none)    */
     uint64_t device_timeout_ns;  /* GPU watchdog on every wait (0 = 30 s)             */
-    int32_t  first_cpu;          /* pin pollers to cores first_cpu.. (-1 = 1..P)      */
+    int32_t  first_cpu;          /* pin poller i to the (first_cpu + i)-th CPU of the
+                                    affinity mask, wrapping (-1 = from the second)   */
     uint32_t ledger_capacity;    /* ledger records kept (0 = 1<<20)                   */
     uint32_t sleep_max;          /* GPU wait backoff cap, in s_sleep steps of ~256
                                     clocks doubled up to this count (0 = 64)           */

@@ -18,7 +18,7 @@ import time
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 DEFAULTS = {"service_threads": 0, "wg_size": 256, "sleep_max": 64, "ring_slots": 1 << 18,
             "coalesce_max": 1, "coalesce_window_ns": 0}
-SPACE = [("service_threads", [12, 13, 14, 15]),
+SPACE = [("service_threads", [8, 10, 12, 14, 15]),
          ("wg_size", [64, 128, 256]),
          ("sleep_max", [16, 64, 256, 1024]),
          ("ring_slots", [1 << 12, 1 << 16, 1 << 18]),

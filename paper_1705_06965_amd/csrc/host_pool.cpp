@@ -76,9 +76,18 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
            const gsys_config& cfg)
     : ring_(ring), comp_(comp), D_(D), C_(C), retired_lo_(retired_lo), fdperm_(65536),
       fdgen_(65536) {
-  long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
-  if (ncpu < 1) ncpu = 1;
-  P_ = cfg.service_threads ? (int)cfg.service_threads : (int)std::max(1L, ncpu - 1);
+  // the CPUs this process may run on (a container's share, not the machine)
+  cpu_set_t allowed;
+  CPU_ZERO(&allowed);
+  if (sched_getaffinity(0, sizeof allowed, &allowed) == 0)
+    for (int c = 0; c < CPU_SETSIZE; ++c)
+      if (CPU_ISSET(c, &allowed)) cpus_.push_back(c);
+  if (cpus_.empty()) {
+    const long n = sysconf(_SC_NPROCESSORS_ONLN);
+    for (long c = 0; c < std::max(1L, n); ++c) cpus_.push_back((int)c);
+  }
+  const int ncpu = (int)cpus_.size();
+  P_ = cfg.service_threads ? (int)cfg.service_threads : std::max(1, ncpu - 1);
   stripe_ = cfg.stripe ? cfg.stripe : 8;
   K_ = cfg.coalesce_max ? cfg.coalesce_max : 1;
   T_ns_ = cfg.coalesce_window_ns;
@@ -593,11 +602,11 @@ void Pool::retire_scan() {
 void Pool::poller(int idx) {
   tls_copies_ = &fdcopies_[(size_t)idx];
   if (pin_) {
-    long ncpu = sysconf(_SC_NPROCESSORS_ONLN);
-    int first = first_cpu_ >= 0 ? first_cpu_ : 1;
+    // poller i runs on allowed CPU number first + i (mod the allowed count)
+    const size_t first = first_cpu_ >= 0 ? (size_t)first_cpu_ : 1;
     cpu_set_t set;
     CPU_ZERO(&set);
-    CPU_SET((int)((first + idx) % (ncpu > 0 ? ncpu : 1)), &set);
+    CPU_SET(cpus_[(first + (size_t)idx) % cpus_.size()], &set);
     pthread_setaffinity_np(pthread_self(), sizeof set, &set);
   }
   const uint32_t S = stripe_;

@@ -96,6 +96,7 @@ class Pool {
   int P_;
   uint32_t stripe_, K_, T_ns_;
   int first_cpu_;
+  std::vector<int> cpus_;  // CPUs in this process's affinity mask, ascending
   bool pin_;
   bool ledger_on_;
   uint64_t ledger_cap_;
