@@ -183,11 +183,11 @@ int Pool::add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind,
   int n = nbufs_.load();
   if (n >= kMaxBufs) return -ENOSPC;
   for (int i = 0; i < n; ++i) {
-    const Buf& b = bufs_[i];
+    const Buf b = bufs_[i].load();
     if (dev < b.dev + b.bytes && b.dev < dev + bytes) return -EEXIST;
   }
   bufgen_.fetch_add(1, std::memory_order_acq_rel);  // odd: writers active
-  bufs_[n] = Buf{dev, host, bytes, kind, next_id_};
+  bufs_[n].store(Buf{dev, host, bytes, kind, next_id_});
   nbufs_.store(n + 1, std::memory_order_release);
   bufgen_.fetch_add(1, std::memory_order_acq_rel);
   if (id) *id = next_id_;
@@ -199,9 +199,9 @@ int Pool::remove_buffer(uint32_t id) {
   std::lock_guard<std::mutex> g(bufmu_);
   int n = nbufs_.load();
   for (int i = 0; i < n; ++i) {
-    if (bufs_[i].id == id) {
+    if (bufs_[i].id.load(std::memory_order_relaxed) == id) {
       bufgen_.fetch_add(1, std::memory_order_acq_rel);
-      bufs_[i] = bufs_[n - 1];
+      bufs_[i].store(bufs_[n - 1].load());
       nbufs_.store(n - 1, std::memory_order_release);
       bufgen_.fetch_add(1, std::memory_order_acq_rel);
       return 0;
@@ -225,7 +225,7 @@ uint8_t* Pool::translate(uint64_t dev, uint64_t len, bool) {
     uint8_t* r = nullptr;
     int n = nbufs_.load(std::memory_order_acquire);
     for (int i = 0; i < n; ++i) {
-      const Buf& b = bufs_[i];
+      const Buf b = bufs_[i].load();
       if (dev >= b.dev && dev + len <= b.dev + b.bytes) {
         r = b.kind == GSYS_BUF_HOST ? b.host + (dev - b.dev) : nullptr;
         break;

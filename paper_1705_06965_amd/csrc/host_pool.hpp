@@ -40,6 +40,27 @@ struct Buf {
   uint32_t id;
 };
 
+// A registered buffer's slot in the table.  Pollers read it without the
+// table's mutex, under the generation seqlock, so every field is an atomic
+// read and written with relaxed order (the generation orders them).
+struct BufSlot {
+  std::atomic<uint64_t> dev{0}, host{0}, bytes{0};
+  std::atomic<uint32_t> kind{0}, id{0};
+  Buf load() const {
+    return Buf{dev.load(std::memory_order_relaxed),
+               reinterpret_cast<uint8_t*>(host.load(std::memory_order_relaxed)),
+               bytes.load(std::memory_order_relaxed), kind.load(std::memory_order_relaxed),
+               id.load(std::memory_order_relaxed)};
+  }
+  void store(const Buf& b) {
+    dev.store(b.dev, std::memory_order_relaxed);
+    host.store(reinterpret_cast<uint64_t>(b.host), std::memory_order_relaxed);
+    bytes.store(b.bytes, std::memory_order_relaxed);
+    kind.store(b.kind, std::memory_order_relaxed);
+    id.store(b.id, std::memory_order_relaxed);
+  }
+};
+
 struct LedgerRec {
   uint64_t ticket, nr, ret, digest, t_start, t_end_poller;  // t_end << 8 | poller
 };
@@ -135,7 +156,7 @@ class Pool {
 
   // buffer table: seqlock-protected fixed array
   static constexpr int kMaxBufs = 512;
-  Buf bufs_[kMaxBufs];
+  BufSlot bufs_[kMaxBufs];
   std::atomic<int> nbufs_{0};
   std::atomic<uint64_t> bufgen_{0};
   std::mutex bufmu_;

@@ -1,0 +1,161 @@
+// The host service pool under ThreadSanitizer.  Host threads drive the pool
+// through the GPU's slot protocol (gsys_test_emulate: wave-coalesced claims,
+// group completions, descriptor-list calls, blocking and non-blocking),
+// with and without coalescing, while two more threads keep changing the fd
+// table and the registered-buffer table that the pollers read without
+// locks, and a third makes calls into an unregistered range (whose
+// validation scans the whole buffer table).  Every result is checked
+// against the file's bytes.  Exits 0 when
+// all checks pass; ThreadSanitizer turns any data race into a non-zero exit.
+//
+// Build: g++ -fsanitize=thread over this file, capi.cpp and host_pool.cpp
+// (host code only; contexts use GSYS_CFG_NO_DEVICE and make no HIP calls).
+#include <errno.h>
+#include <fcntl.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#include <atomic>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gsys.h"
+#include "gsys_testing.h"
+
+namespace {
+
+constexpr uint64_t kFile = 4u << 20;
+constexpr uint32_t kItem = 4096;
+
+uint8_t pattern(uint64_t i) { return (uint8_t)((i * 2654435761u) >> 13); }
+
+int fail(const char* what, long a = 0, long b = 0) {
+  fprintf(stderr, "FAIL %s (%ld, %ld)\n", what, a, b);
+  return 1;
+}
+
+struct Phase {
+  const char* name;
+  uint32_t threads, group, mode, K, T;
+  bool sequential;  // consecutive offsets, so coalesced bundles merge
+};
+
+int run_phase(const std::string& path, const Phase& ph) {
+  gsys_config cfg;
+  memset(&cfg, 0, sizeof cfg);
+  cfg.abi_version = GSYS_ABI_VERSION;
+  cfg.ring_slots = 4096;  // completion records (4D) outlast slow waiters under a sanitizer
+  cfg.service_threads = 4;
+  cfg.coalesce_max = ph.K;
+  cfg.coalesce_window_ns = ph.T;
+  cfg.flags = GSYS_CFG_NO_DEVICE | GSYS_CFG_NO_PIN | GSYS_CFG_LEDGER;
+  gsys_ctx* ctx = nullptr;
+  if (int e = gsys_init(&cfg, &ctx)) return fail("gsys_init", e);
+  const int fd = open(path.c_str(), O_RDONLY);
+  const int fd2 = open(path.c_str(), O_RDONLY);
+  if (fd < 0 || fd2 < 0) return fail("open");
+  if (gsys_allow_fd(ctx, fd, GSYS_FD_READ)) return fail("allow_fd");
+  // registered first, so that dropping it moves the last live entry into
+  // its slot: the pollers' lock-free lookups see entries move under them
+  const uint64_t churn_base = 1ull << 46;  // a device range no call uses
+  std::vector<uint8_t> dummy(1 << 16);
+  uint32_t churn_id = 0;
+  if (gsys_register_buffer(ctx, churn_base, dummy.data(), dummy.size(), GSYS_BUF_HOST, &churn_id))
+    return fail("register");
+  const uint64_t n = (uint64_t)ph.threads * 256;
+  void* host = nullptr;
+  uint64_t dev = 0;
+  uint32_t id = 0;
+  void* lhost = nullptr;
+  uint64_t ldev = 0;
+  uint32_t lid = 0;
+  if (gsys_host_alloc(ctx, n * kItem, &host, &dev, &id)) return fail("host_alloc");
+  if (gsys_host_alloc(ctx, n * 16, &lhost, &ldev, &lid)) return fail("host_alloc lists");
+  std::vector<uint64_t> offs(n);
+  for (uint64_t k = 0; k < n; ++k)
+    offs[k] = ph.sequential ? (k * kItem) % kFile : ((k * 7919u) % (kFile / kItem)) * kItem;
+  std::vector<int64_t> rets(n, -12345);
+
+  // the tables the pollers read without locks change all the time
+  std::atomic<bool> done{false};
+  std::thread fd_churn([&] {
+    for (uint32_t i = 0; !done.load(); ++i) gsys_allow_fd(ctx, fd2, (i & 1) ? GSYS_FD_READ : 0);
+  });
+  std::thread buf_churn([&] {
+    uint32_t bid = churn_id;
+    while (!done.load()) {
+      gsys_unregister_buffer(ctx, bid);
+      if (gsys_register_buffer(ctx, churn_base, dummy.data(), dummy.size(), GSYS_BUF_HOST, &bid))
+        break;
+    }
+  });
+  // calls into no registered range: their validation scans the whole
+  // table, the slot being rewritten included, and must fail with -EFAULT
+  std::atomic<int> bad{0};
+  std::thread prober([&] {
+    while (!done.load()) {
+      const uint64_t a[6] = {(uint64_t)fd, 1ull << 47, kItem, 0, 0, 0};
+      int64_t r = 0;
+      if (gsys_test_raw_call(ctx, GSYS_NR_PREAD64, GSYS_F_BLOCKING, a, &r, 10000000000ull) ||
+          r != -EFAULT)
+        bad.store(1);
+    }
+  });
+  const int rc = gsys_test_emulate(ctx, ph.threads, 256, ph.group, ph.mode, fd, dev, ldev, kItem,
+                                   offs.data(), rets.data(), 60000000000ull);
+  done.store(true);
+  fd_churn.join();
+  buf_churn.join();
+  prober.join();
+  if (rc) return fail(ph.name, rc);
+  if (bad.load()) return fail("unregistered range not refused");
+  if (gsys_wait(ctx, 10000000000ull)) return fail("gsys_wait");
+  const uint8_t* h = (const uint8_t*)host;
+  for (uint64_t k = 0; k < n; ++k) {
+    if (rets[k] != kItem) return fail("ret", (long)k, (long)rets[k]);
+    for (uint32_t b = 0; b < kItem; ++b)
+      if (h[k * kItem + b] != pattern(offs[k] + b)) return fail("byte", (long)k, (long)b);
+  }
+  gsys_stats st;
+  if (gsys_stats_get(ctx, &st, 0)) return fail("stats");
+  std::vector<uint64_t> led(6 * (st.claimed + 1));
+  const int64_t m = gsys_ledger(ctx, led.data(), st.claimed + 1, 0);
+  if ((uint64_t)m != st.claimed) return fail("ledger", (long)m, (long)st.claimed);
+  for (int64_t i = 0; i < m; ++i)
+    if (led[6 * i] != (uint64_t)i) return fail("ledger order", (long)i, (long)led[6 * i]);
+  if (gsys_shutdown(ctx, 5000000000ull)) return fail("shutdown");
+  close(fd);
+  close(fd2);
+  printf("%s ok: %lu calls, %lu tickets\n", ph.name, (unsigned long)n,
+         (unsigned long)st.claimed);
+  return 0;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 2) return fail("usage: pool_tsan_driver <tmp dir>");
+  const std::string path = std::string(argv[1]) + "/pool_tsan.bin";
+  {
+    std::vector<uint8_t> data(kFile);
+    for (uint64_t i = 0; i < kFile; ++i) data[i] = pattern(i);
+    FILE* f = fopen(path.c_str(), "wb");
+    if (!f || fwrite(data.data(), 1, kFile, f) != kFile) return fail("write file");
+    fclose(f);
+  }
+  const Phase phases[] = {
+      {"wavefront groups, blocking", 6, 64, GSYS_EMU_BLOCKING, 1, 0, false},
+      {"small groups, non-blocking", 6, 8, 0, 1, 0, false},
+      {"list calls, blocking", 4, 16, GSYS_EMU_LIST | GSYS_EMU_BLOCKING, 1, 0, false},
+      {"list calls, non-blocking", 4, 32, GSYS_EMU_LIST, 1, 0, true},
+      {"coalesced bundles", 6, 64, GSYS_EMU_BLOCKING, 8, 2000, true},
+  };
+  for (const Phase& ph : phases)
+    if (int e = run_phase(path, ph)) return e;
+  unlink(path.c_str());
+  return 0;
+}
