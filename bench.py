@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--perm-iters", default="1,4,16,64,256,1024,2048,4096",
                     help="permute: permutation rounds per block before the pwrite")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "tiny", "wordscan", "kv", "serve", "permute"],
+                    choices=["sweep", "tiny", "wordscan", "kv", "serve", "permute",
+                             "granularity", "coalesce"],
                     help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
                          "word search over 2,000 files")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -131,6 +132,10 @@ def main():
         return run_permute(args)
     if args.workload == "tiny":
         return run_tiny(args)
+    if args.workload == "granularity":
+        return run_granularity(args)
+    if args.workload == "coalesce":
+        return run_coalesce(args)
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
@@ -896,6 +901,160 @@ def run_tiny(args):
         res["cpu_baseline"] = cpu
     r.close()
     ctx.shutdown()
+    print(json.dumps(res), flush=True)
+
+
+def _spot_check(path, offs, item, f, ret, k=64):
+    """Recompute k evenly spaced items with the oracle."""
+    import numpy as np
+    import oracle
+    pick = np.unique(np.linspace(0, len(offs) - 1, k).astype(np.int64))
+    want_f, want_r = oracle.pread_fnv(path, offs[pick], item)
+    if not ((f[pick] == want_f).all() and (ret[pick] == want_r).all()):
+        raise RuntimeError("GPU checksums differ from the oracle")
+
+
+def _time_runs(runner, ctx, cell, form, steps, warmup):
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        runner.launch(cell, form)
+        torch.cuda.synchronize()
+        if ctx.wait(120_000_000_000):
+            raise RuntimeError("drain failed")
+    ts = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runner.launch(cell, form)
+        torch.cuda.synchronize()
+        if ctx.wait(120_000_000_000):
+            raise RuntimeError("drain failed")
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def run_granularity(args):
+    """Invocation granularity (section 6, Fig. 5).  Left: the time to read
+    the first S bytes of the file in 4 KiB preads (one per work-item, items
+    in file order, 64-wide work-groups, one plain launch), for every legal
+    granularity x ordering x blocking cell.  Right: work-group granularity
+    (relaxed, blocking) as the work-group grows from 64 to 1024 work-items.
+    Adjacent reads of a group's descriptor list merge into one host pread,
+    so a work-group call reads its whole range at once and a kernel call
+    reads the file as one pread on one host thread.  value = calls/s of the
+    fastest cell at the largest size."""
+    import numpy as np
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+    path = synth.random_file(2, FILE_BYTES, name="c2_1g.bin")
+    with open(path, "rb") as fh:
+        while fh.read(64 << 20):
+            pass
+    sizes = [4 << 20, 64 << 20, 1 << 30]
+    ctx = g.Context(ring_slots=1 << 18, service_threads=max(0, args.service_threads),
+                    device_timeout_ns=120_000_000_000)
+    steps = max(1, min(args.steps, 3))
+    left = {}
+    best = (0.0, None)
+    for S in sizes:
+        n = S // ITEM
+        offs = (np.arange(n, dtype=np.uint64) * ITEM)
+        r = FnvRunner(ctx, path, offs, ITEM, wg_size=64)
+        left[S] = {}
+        for cell in g.LEGAL_CELLS:
+            code = g.cell_code(*cell)
+            t = _time_runs(r, ctx, code, g.PLAIN, steps, 1)
+            f, ret = r.result()
+            _spot_check(path, offs, ITEM, f, ret)
+            name = "/".join(cell)
+            left[S][name] = round(1e3 * t, 3)
+            if S == sizes[-1] and n / t > best[0]:
+                best = (n / t, name)
+        r.close()
+        print("size %d MiB done" % (S >> 20), file=sys.stderr, flush=True)
+    S = sizes[-1]
+    n = S // ITEM
+    offs = (np.arange(n, dtype=np.uint64) * ITEM)
+    right = {}
+    for wg in (64, 128, 256, 512, 1024):
+        r = FnvRunner(ctx, path, offs, ITEM, wg_size=wg)
+        t = _time_runs(r, ctx, g.cell_code("WG", "relaxed", "block"), g.PLAIN, steps, 1)
+        f, ret = r.result()
+        _spot_check(path, offs, ITEM, f, ret)
+        st = ctx.stats()
+        right[wg] = round(1e3 * t, 3)
+        r.close()
+    ctx.shutdown()
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(best[0], 1), "unit": "syscalls/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": round(1e3 * n / best[0], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "invocation granularity: read the first S bytes of a 1 GiB "
+                               "random file in 4 KiB preads, plain launch",
+                   "sizes": sizes, "best_cell_at_1g": best[1]},
+        "read_ms_by_size_and_cell": {str(k): v for k, v in left.items()},
+        "read_ms_1g_by_wg_size": {str(k): v for k, v in right.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
+def run_coalesce(args):
+    """Coalescing (section 6, Fig. 7): 16,384 work-items (64 work-groups of
+    256) each pread one contiguous piece of the file, so the piece size is
+    the file size / 16,384; work-item granularity, strong, blocking, one
+    plain launch.  Host pool without coalescing (K = 1) and with bundles of
+    up to K = 8 calls gathered for up to T = 10 us; a bundle's calls that
+    continue each other in the file and in memory become one pread.
+    Reported: time per requested byte.  value = calls/s of the best setting
+    at the smallest piece."""
+    import numpy as np
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+    path = synth.random_file(2, FILE_BYTES, name="c2_1g.bin")
+    with open(path, "rb") as fh:
+        while fh.read(64 << 20):
+            pass
+    n = 16384
+    pieces = [64, 256, 1024, 4096, 16384, 65536]
+    steps = max(1, min(args.steps, 5))
+    cell = g.cell_code("WI", "strong", "block")
+    out = {}
+    best = (0.0, None)
+    for K, T in ((1, 0), (8, 10_000)):
+        ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
+                        coalesce_max=K, coalesce_window_ns=T, device_timeout_ns=60_000_000_000)
+        key = "K%d" % K
+        out[key] = {}
+        for piece in pieces:
+            offs = np.arange(n, dtype=np.uint64) * np.uint64(piece)
+            r = FnvRunner(ctx, path, offs, piece, wg_size=256)
+            t = _time_runs(r, ctx, cell, g.PLAIN, steps, 1)
+            f, ret = r.result()
+            _spot_check(path, offs, piece, f, ret)
+            st = ctx.stats(reset=True)
+            out[key][piece] = {"ms": round(1e3 * t, 3),
+                               "ns_per_byte": round(1e9 * t / (n * piece), 4),
+                               "merged_per_launch": st["merged"] // (steps + 1)}
+            if piece == pieces[0] and n / t > best[0]:
+                best = (n / t, key)
+            r.close()
+        ctx.shutdown()
+        print("coalescing %s done" % key, file=sys.stderr, flush=True)
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(best[0], 1), "unit": "syscalls/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": round(1e3 * n / best[0], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "coalescing: 16,384 work-items each pread one contiguous piece "
+                               "of a 1 GiB random file, work-item / strong / blocking",
+                   "pieces": pieces, "coalescing": {"K1": "off", "K8": "K = 8, T = 10 us"},
+                   "best_at_64B": best[1]},
+        "by_setting_and_piece": {k: {str(p): v for p, v in d.items()} for k, d in out.items()},
+    }
     print(json.dumps(res), flush=True)
 
 

@@ -55,5 +55,8 @@ class FnvRunner:
         return f, r
 
     def close(self):
+        """Revoke and close the file, free the staging and list buffers."""
         self.ctx.allow_fd(self.fd, 0)
         os.close(self.fd)
+        self.staging.free()
+        self.lists.free()
