@@ -78,11 +78,25 @@ int gsys_init(const gsys_config *cfg, gsys_ctx **out);
 #define GSYS_FD_READ  0x1u
 #define GSYS_FD_WRITE 0x2u
 #define GSYS_FD_SOCK  0x4u
+#define GSYS_FD_DIR   0x8u  /* a directory that GPU openat calls resolve beneath */
 
 /*
  * Allow GPU calls on `fd` with `perms` (GSYS_FD_*).  The caller keeps
  * ownership of the fd and must keep it open until gsys_wait() returns.
  * perms == 0 revokes the fd (later calls on it complete with -EBADF).
+ *
+ * GSYS_FD_DIR (fd must be a directory, else -ENOTDIR) lets the GPU open
+ * files beneath it: openat(dirfd, path, flags, mode) with `path` in a
+ * registered host buffer (NUL within GSYS_PATH_MAX bytes, else
+ * -ENAMETOOLONG), flags from O_RDONLY / O_WRONLY / O_RDWR / O_CREAT /
+ * O_TRUNC / O_APPEND (others -EINVAL; writing needs GSYS_FD_WRITE on the
+ * directory, creating needs it too, else -EPERM; mode & 0666).  The path is
+ * resolved with openat2(RESOLVE_BENEATH | RESOLVE_NO_MAGICLINKS): absolute
+ * paths, ".." and symlinks that leave the directory fail (-EXDEV).  The new
+ * fd is allowed for the access the flags give and belongs to the pool: the
+ * GPU closes it with close(fd) (-EBADF for any fd it did not open), and
+ * gsys_shutdown closes the ones still open.  A GPU-opened fd must not be
+ * closed while calls on it are in flight (as with POSIX close).
  *
  * For a regular file, each service thread runs pread / pwrite through its
  * own open file description of the same file (opened on first use through

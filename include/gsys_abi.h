@@ -38,6 +38,7 @@
 /* ---- call numbers: the host's x86_64 system-call numbers ---- */
 #define GSYS_NR_READ      0
 #define GSYS_NR_WRITE     1
+#define GSYS_NR_CLOSE     3
 #define GSYS_NR_MMAP      9
 #define GSYS_NR_MUNMAP   11
 #define GSYS_NR_PREAD64  17
@@ -45,6 +46,10 @@
 #define GSYS_NR_MADVISE  28
 #define GSYS_NR_SENDTO   44
 #define GSYS_NR_RECVFROM 45
+#define GSYS_NR_OPENAT  257
+
+/* openat paths: the NUL must lie in the first GSYS_PATH_MAX bytes */
+#define GSYS_PATH_MAX   256
 
 /* ---- slot flags ---- */
 #define GSYS_F_BLOCKING  0x01u  /* the paper's blocking bit */

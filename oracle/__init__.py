@@ -64,6 +64,10 @@ def lib() -> C.CDLL:
         L.oracle_release_job.restype = C.c_int
         L.oracle_release_job.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.c_uint64,
                                          C.c_void_p]
+        L.oracle_wordcount_open.restype = C.c_int
+        L.oracle_wordcount_open.argtypes = [C.c_int, C.c_void_p, C.c_uint32, C.c_uint32,
+                                            C.c_uint32, C.c_void_p, C.c_void_p, C.c_uint32,
+                                            C.c_uint32, C.c_void_p, C.c_void_p, C.c_int]
         L.oracle_permute.restype = C.c_int
         L.oracle_permute.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                      C.c_uint32, C.c_uint64, C.c_void_p, C.c_int]
@@ -124,6 +128,36 @@ def wordcount(paths, queries, threads: int = 1) -> np.ndarray:
     if rc:
         raise OSError(-rc, "oracle_wordcount")
     return counts
+
+
+def pack_paths(names, stride: int = 256) -> np.ndarray:
+    """NUL-terminated byte strings `stride` bytes apart."""
+    out = np.zeros((len(names), stride), dtype=np.uint8)
+    for i, n in enumerate(names):
+        b = n.encode() if isinstance(n, str) else bytes(n)
+        if len(b) >= stride:
+            raise ValueError("path longer than stride - 1")
+        out[i, :len(b)] = np.frombuffer(b, dtype=np.uint8)
+    return out
+
+
+def wordcount_open(directory: str, names, queries, chunk: int = 1 << 20, threads: int = 1):
+    """(counts[f, q], rets[f]): each file opened beneath `directory` by name,
+    read with read() in `chunk`-byte pieces, closed, and its tokens counted."""
+    q, ql = pack_queries(queries)
+    paths = pack_paths(names)
+    counts = np.zeros((len(names), len(queries)), dtype=np.uint32)
+    rets = np.zeros(len(names), dtype=np.int64)
+    dfd = os.open(directory, os.O_RDONLY | os.O_DIRECTORY)
+    try:
+        rc = lib().oracle_wordcount_open(dfd, _p(paths), len(names), paths.shape[1], chunk, _p(q),
+                                         _p(ql), len(queries), q.shape[1], _p(counts), _p(rets),
+                                         threads)
+    finally:
+        os.close(dfd)
+    if rc:
+        raise OSError(-rc, "oracle_wordcount_open")
+    return counts, rets
 
 
 class KVIndex:

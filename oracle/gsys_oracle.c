@@ -20,7 +20,8 @@
  *     0xcbf29ce484222325, prime 0x100000001b3, xor then multiply, per byte);
  *   - word counts in the style of the wordcount case study (section 7.1):
  *     a token is a maximal run of bytes other than space (0x20) and newline
- *     (0x0a); counts[f][q] is the number of tokens of file f equal to query q;
+ *     (0x0a); counts[f][q] is the number of tokens of file f equal to query q
+ *     (files read with pread, or opened by name and read with read());
  *   - key-value GET replies in the style of the UDP server case study
  *     (section 7.3), with a sorted key index and bsearch;
  *   - memory release with madvise(MADV_DONTNEED) in the style of section 7.2;
@@ -39,6 +40,7 @@
  */
 #define _GNU_SOURCE
 #include <errno.h>
+#include <fcntl.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -138,6 +140,24 @@ struct wc_job {
 
 static int is_delim(uint8_t c) { return c == 0x20 || c == 0x0a; }
 
+/* cnt[q] = number of tokens of buf[0..n) equal to query q */
+static void count_tokens(const uint8_t *buf, uint64_t n, const uint8_t *qbytes,
+                         const uint32_t *qlen, uint32_t nq, uint32_t qstride, uint32_t *cnt)
+{
+    for (uint32_t q = 0; q < nq; q++) cnt[q] = 0;
+    uint64_t p = 0;
+    while (p < n) {
+        if (is_delim(buf[p])) { p++; continue; }
+        uint64_t s = p;
+        while (p < n && !is_delim(buf[p])) p++;
+        uint64_t tl = p - s;
+        for (uint32_t q = 0; q < nq; q++) {
+            if (qlen[q] == tl && memcmp(buf + s, qbytes + (uint64_t)q * qstride, tl) == 0)
+                cnt[q]++;
+        }
+    }
+}
+
 static void *wc_worker(void *arg)
 {
     struct wc_job *j = (struct wc_job *)arg;
@@ -152,20 +172,8 @@ static void *wc_worker(void *arg)
             if (r == 0) break;
             got += (uint64_t)r;
         }
-        uint32_t *cnt = j->counts + (uint64_t)f * j->nq;
-        for (uint32_t q = 0; q < j->nq; q++) cnt[q] = 0;
-        uint64_t p = 0;
-        while (p < got) {
-            if (is_delim(buf[p])) { p++; continue; }
-            uint64_t s = p;
-            while (p < got && !is_delim(buf[p])) p++;
-            uint64_t tl = p - s;
-            for (uint32_t q = 0; q < j->nq; q++) {
-                if (j->qlen[q] == tl &&
-                    memcmp(buf + s, j->qbytes + (uint64_t)q * j->qstride, tl) == 0)
-                    cnt[q]++;
-            }
-        }
+        count_tokens(buf, got, j->qbytes, j->qlen, j->nq, j->qstride,
+                     j->counts + (uint64_t)f * j->nq);
         free(buf);
     }
     return NULL;
@@ -195,6 +203,77 @@ int oracle_wordcount(const int *fds, const uint64_t *sizes, uint32_t nfiles,
     }
     free(jobs); free(tid);
     return err;
+}
+
+/*
+ * The wordcount as the case study of section 7.1 issues it: every file is
+ * opened by name (openat beneath dirfd), read front to back with read() in
+ * pieces of `chunk` bytes until it returns 0, closed, and its tokens are
+ * counted as above.  Paths are NUL-terminated strings `stride` bytes apart.
+ * rets[f] = bytes read, or -errno of the failing open or read (counts 0).
+ */
+struct wo_job {
+    int dirfd;
+    const char *paths;
+    uint32_t stride, chunk, lo, hi, nq, qstride;
+    const uint8_t *qbytes;
+    const uint32_t *qlen;
+    uint32_t *counts;
+    int64_t *rets;
+};
+
+static void *wo_worker(void *arg)
+{
+    struct wo_job *j = (struct wo_job *)arg;
+    for (uint32_t f = j->lo; f < j->hi; f++) {
+        uint32_t *cnt = j->counts + (uint64_t)f * j->nq;
+        for (uint32_t q = 0; q < j->nq; q++) cnt[q] = 0;
+        int fd = openat(j->dirfd, j->paths + (uint64_t)f * j->stride, O_RDONLY | O_CLOEXEC);
+        if (fd < 0) { j->rets[f] = -errno; continue; }
+        uint64_t cap = j->chunk, got = 0;
+        uint8_t *buf = (uint8_t *)malloc(cap);
+        int64_t err = 0;
+        for (;;) {
+            if (got + j->chunk > cap) {
+                cap = 2 * cap + j->chunk;
+                uint8_t *nb = (uint8_t *)realloc(buf, cap);
+                if (!nb) { err = -ENOMEM; break; }
+                buf = nb;
+            }
+            ssize_t r = read(fd, buf + got, j->chunk);
+            if (r < 0) { err = -errno; break; }
+            if (r == 0) break;
+            got += (uint64_t)r;
+        }
+        close(fd);
+        if (err) { j->rets[f] = err; free(buf); continue; }
+        count_tokens(buf, got, j->qbytes, j->qlen, j->nq, j->qstride, cnt);
+        j->rets[f] = (int64_t)got;
+        free(buf);
+    }
+    return NULL;
+}
+
+int oracle_wordcount_open(int dirfd, const char *paths, uint32_t nfiles, uint32_t stride,
+                          uint32_t chunk, const uint8_t *qbytes, const uint32_t *qlen,
+                          uint32_t nq, uint32_t qstride, uint32_t *counts, int64_t *rets,
+                          int threads)
+{
+    if (!chunk) return -EINVAL;
+    if (threads < 1) threads = 1;
+    if ((uint32_t)threads > nfiles) threads = nfiles ? (int)nfiles : 1;
+    pthread_t tid[256];
+    struct wo_job jobs[256];
+    if (threads > 256) threads = 256;
+    for (int t = 0; t < threads; t++) {
+        jobs[t] = (struct wo_job){dirfd, paths, stride, chunk,
+                                  (uint32_t)((uint64_t)nfiles * t / threads),
+                                  (uint32_t)((uint64_t)nfiles * (t + 1) / threads),
+                                  nq, qstride, qbytes, qlen, counts, rets};
+        if (pthread_create(&tid[t], NULL, wo_worker, &jobs[t]) != 0) return -EAGAIN;
+    }
+    for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    return 0;
 }
 
 /* ----------------------------------------------------------- key-value GET */

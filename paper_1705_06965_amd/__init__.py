@@ -24,14 +24,15 @@ ABI_VERSION = 1
 
 # slot flags / states / call numbers (mirror include/gsys_abi.h)
 ST_FREE, ST_POPULATING, ST_READY, ST_PROCESSING, ST_FINISHED = 0, 1, 2, 3, 4
-NR_READ, NR_WRITE, NR_MMAP, NR_MUNMAP = 0, 1, 9, 11
-NR_PREAD64, NR_PWRITE64, NR_MADVISE, NR_SENDTO, NR_RECVFROM = 17, 18, 28, 44, 45
+NR_READ, NR_WRITE, NR_CLOSE, NR_MMAP, NR_MUNMAP = 0, 1, 3, 9, 11
+NR_PREAD64, NR_PWRITE64, NR_MADVISE, NR_SENDTO, NR_RECVFROM, NR_OPENAT = 17, 18, 28, 44, 45, 257
+PATH_MAX = 256
 F_BLOCKING, F_LIST, F_PRODUCER, F_STRONG = 0x1, 0x2, 0x4, 0x8
 GRAN_WI, GRAN_WG, GRAN_KERNEL = 0, 1, 2
 CELL_STRONG, CELL_BLOCKING = 0x4, 0x8
 PLAIN, PERSISTENT, GRAPH = 0, 1, 2
 CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS = 0x1, 0x2, 0x4, 0x8
-FD_READ, FD_WRITE, FD_SOCK = 0x1, 0x2, 0x4
+FD_READ, FD_WRITE, FD_SOCK, FD_DIR = 0x1, 0x2, 0x4, 0x8
 BUF_HOST, BUF_DEVICE = 1, 2
 EMU_BLOCKING, EMU_LIST = 0x1, 0x2
 NOT_WAITED = -115   # a non-blocking call's result slot before anyone waited

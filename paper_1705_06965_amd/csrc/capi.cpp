@@ -110,6 +110,7 @@ void destroy(gsys_ctx* c) {
   if (!c) return;
   if (c->pool) {
     c->pool->stop_and_join();
+    c->pool->close_owned();
     delete c->pool;
     c->pool = nullptr;
   }

@@ -36,12 +36,13 @@ enum class Role { Producer, Consumer };
 
 // Role of each whitelisted call under relaxed ordering: data flows out of the
 // GPU program for write/send (producers) and into it for read/recv
-// (section 4.1).  mmap hands back an address, so it is a consumer; munmap and
-// madvise act on memory the program is done with, so they are producers (the
-// paper issues madvise non-blocking and relaxed, section 7.2).
+// (section 4.1).  mmap and openat hand back an address or a descriptor, so
+// they are consumers; munmap, madvise and close act on memory or a file the
+// program is done with, so they are producers (the paper issues madvise
+// non-blocking and relaxed, section 7.2).
 __host__ __device__ constexpr Role role_of(int nr) {
   return (nr == GSYS_NR_WRITE || nr == GSYS_NR_PWRITE64 || nr == GSYS_NR_SENDTO ||
-          nr == GSYS_NR_MUNMAP || nr == GSYS_NR_MADVISE)
+          nr == GSYS_NR_MUNMAP || nr == GSYS_NR_MADVISE || nr == GSYS_NR_CLOSE)
              ? Role::Producer
              : Role::Consumer;
 }

@@ -12,6 +12,7 @@
 #include <sys/socket.h>
 #include <sys/stat.h>
 #include <sys/syscall.h>
+#include <linux/openat2.h>
 #include <time.h>
 #include <unistd.h>
 #include <immintrin.h>
@@ -26,14 +27,16 @@ static_assert(GSYS_NR_READ == SYS_read && GSYS_NR_WRITE == SYS_write &&
                   GSYS_NR_MMAP == SYS_mmap && GSYS_NR_MUNMAP == SYS_munmap &&
                   GSYS_NR_PREAD64 == SYS_pread64 && GSYS_NR_PWRITE64 == SYS_pwrite64 &&
                   GSYS_NR_MADVISE == SYS_madvise && GSYS_NR_SENDTO == SYS_sendto &&
-                  GSYS_NR_RECVFROM == SYS_recvfrom,
+                  GSYS_NR_RECVFROM == SYS_recvfrom && GSYS_NR_CLOSE == SYS_close &&
+                  GSYS_NR_OPENAT == SYS_openat,
               "call numbers are the host's system-call numbers");
 
 namespace gsys_host {
 
 namespace {
 
-constexpr uint8_t kPermMask = 0x7;
+constexpr uint8_t kPermMask = 0xF;  // GSYS_FD_READ | WRITE | SOCK | DIR
+constexpr uint8_t kOwned = 0x40;    // opened by a GPU openat: the pool closes it
 constexpr uint8_t kRegular = 0x80;  // fd refers to a regular file (transfers may merge)
 
 inline uint64_t now_ns() {
@@ -127,6 +130,7 @@ int Pool::allow_fd(int fd, uint32_t perms) {
   if (v) {
     struct stat st;
     if (fstat(fd, &st) != 0) return -errno;
+    if ((v & GSYS_FD_DIR) && !S_ISDIR(st.st_mode)) return -ENOTDIR;
     if (S_ISREG(st.st_mode)) v |= kRegular;
   }
   fdgen_[fd].fetch_add(1, std::memory_order_acq_rel);
@@ -357,9 +361,65 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       ++*calls;
       return rc ? -(int64_t)errno : 0;
     }
+    case GSYS_NR_OPENAT: {
+      // a file beneath an allowed directory; the new fd belongs to the pool
+      const int64_t dfd = (int64_t)a[0];
+      if (!fd_ok(dfd, GSYS_FD_DIR)) return -EBADF;
+      const uint8_t dperm = fdperm_[dfd].load(std::memory_order_acquire);
+      const uint8_t* path = translate(a[1], GSYS_PATH_MAX, false);
+      if (!path) return -EFAULT;
+      if (!memchr(path, 0, GSYS_PATH_MAX)) return -ENAMETOOLONG;
+      const uint64_t fl = a[2];
+      const uint64_t ok_fl = O_ACCMODE | O_CREAT | O_TRUNC | O_APPEND;
+      if ((fl & ~ok_fl) || (fl & O_ACCMODE) == O_ACCMODE) return -EINVAL;
+      const bool writes = (fl & O_ACCMODE) != O_RDONLY || (fl & (O_CREAT | O_TRUNC));
+      if (writes && !(dperm & GSYS_FD_WRITE)) return -EPERM;
+      if (!writes && !(dperm & GSYS_FD_READ)) return -EPERM;
+      struct open_how how;
+      memset(&how, 0, sizeof how);
+      how.flags = fl | O_CLOEXEC;
+      how.mode = (fl & O_CREAT) ? (a[3] & 0666) : 0;
+      how.resolve = RESOLVE_BENEATH | RESOLVE_NO_MAGICLINKS;
+      const long nfd = syscall(SYS_openat2, (int)dfd, (const char*)path, &how, sizeof how);
+      ++*calls;
+      if (nfd < 0) return -(int64_t)errno;
+      if (nfd >= (long)fdperm_.size()) {
+        close((int)nfd);
+        return -EMFILE;
+      }
+      uint8_t v = kOwned;
+      if ((fl & O_ACCMODE) != O_WRONLY) v |= GSYS_FD_READ;
+      if ((fl & O_ACCMODE) != O_RDONLY) v |= GSYS_FD_WRITE;
+      struct stat st;
+      if (fstat((int)nfd, &st) == 0 && S_ISREG(st.st_mode)) v |= kRegular;
+      fdgen_[nfd].fetch_add(1, std::memory_order_acq_rel);
+      fdperm_[nfd].store(v, std::memory_order_release);
+      return (int64_t)nfd;
+    }
+    case GSYS_NR_CLOSE: {
+      // only what a GPU openat opened; the fd is revoked before it is closed
+      const int64_t fd = (int64_t)a[0];
+      if (fd < 0 || fd >= (int64_t)fdperm_.size()) return -EBADF;
+      uint8_t p = fdperm_[fd].load(std::memory_order_acquire);
+      if (!(p & kOwned) || !fdperm_[fd].compare_exchange_strong(p, 0, std::memory_order_acq_rel))
+        return -EBADF;
+      fdgen_[fd].fetch_add(1, std::memory_order_acq_rel);
+      ++*calls;
+      return close((int)fd) ? -(int64_t)errno : 0;
+    }
     default:
       st_rej_.fetch_add(1, std::memory_order_relaxed);
       return -EPERM;
+  }
+}
+
+void Pool::close_owned() {
+  for (size_t fd = 0; fd < fdperm_.size(); ++fd) {
+    uint8_t p = fdperm_[fd].load(std::memory_order_acquire);
+    if ((p & kOwned) && fdperm_[fd].compare_exchange_strong(p, 0, std::memory_order_acq_rel)) {
+      fdgen_[fd].fetch_add(1, std::memory_order_acq_rel);
+      close((int)fd);
+    }
   }
 }
 

@@ -76,6 +76,9 @@ class Pool {
 
   // whitelist
   int allow_fd(int fd, uint32_t perms);
+  // Close every fd a GPU openat opened and is still open (after the pollers
+  // stopped).
+  void close_owned();
   int add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id);
   int remove_buffer(uint32_t id);
   void set_arena(uint8_t* base, uint64_t bytes) { arena_ = base; arena_bytes_ = bytes; }

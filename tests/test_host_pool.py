@@ -164,8 +164,11 @@ def test_whitelist_rejects(datafile):
         assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev + 8000, 4096, 0]) == -errno.EFAULT
         assert _raw(ctx, g.NR_PREAD64, [fd, 0x1000, 16, 0]) == -errno.EFAULT
         # calls outside the whitelist
-        for nr in (2, 3, 57, 59, 62):  # open, close, fork, execve, kill
+        for nr in (2, 57, 59, 62, 85):  # open, fork, execve, kill, creat
             assert _raw(ctx, nr, [0, 0, 0]) == -errno.EPERM
+        # close: only descriptors a GPU openat opened (never the caller's)
+        assert _raw(ctx, g.NR_CLOSE, [0]) == -errno.EBADF
+        assert _raw(ctx, g.NR_CLOSE, [fd]) == -errno.EBADF
         # madvise: only MADV_DONTNEED, only inside the arena
         assert _raw(ctx, g.NR_MADVISE, [buf.dev & ~4095, 4096, 8]) == -errno.EINVAL  # MADV_FREE
         assert _raw(ctx, g.NR_MADVISE, [buf.dev & ~4095, 4096, 4]) == -errno.EFAULT  # not arena
@@ -371,3 +374,84 @@ def test_copies_keep_append_and_write_modes(tmpdata):
     finally:
         assert ctx.shutdown() == 0
         os.close(fd)
+
+
+def _path(ctx, name: bytes):
+    b = ctx.host_alloc(g.PATH_MAX)
+    b.array[:g.PATH_MAX] = 0
+    b.array[:len(name)] = np.frombuffer(name, dtype=np.uint8)
+    return b
+
+
+def test_openat_read_close_beneath_an_allowed_directory(tmpdata):
+    """openat resolves beneath a GSYS_FD_DIR directory, the new fd reads
+    sequentially (the file offset advances), close gives it back; escapes,
+    unknown flags, writes into a read-only directory and foreign closes are
+    refused."""
+    d = os.path.join(tmpdata, "opendir")
+    os.makedirs(os.path.join(d, "sub"), exist_ok=True)
+    body = bytes(range(256)) * 64
+    open(os.path.join(d, "sub", "f.bin"), "wb").write(body)
+    open(os.path.join(tmpdata, "outside.bin"), "wb").write(b"secret")
+    link = os.path.join(d, "escape")
+    if not os.path.lexists(link):
+        os.symlink(os.path.join(tmpdata, "outside.bin"), link)
+    dfd = os.open(d, os.O_RDONLY | os.O_DIRECTORY)
+    ctx = _ctx(ring_slots=256, service_threads=2)
+    try:
+        buf = ctx.host_alloc(1 << 16)
+        good = _path(ctx, b"sub/f.bin")
+        # the directory must be allowed, and as a directory
+        assert _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_RDONLY, 0]) == -errno.EBADF
+        ffd = os.open(os.path.join(d, "sub", "f.bin"), os.O_RDONLY)
+        with pytest.raises(g.GsysError) as ei:
+            ctx.allow_fd(ffd, g.FD_READ | g.FD_DIR)
+        assert ei.value.errno == errno.ENOTDIR
+        os.close(ffd)
+        ctx.allow_fd(dfd, g.FD_READ | g.FD_DIR)
+        fd = _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_RDONLY, 0])
+        assert fd >= 0
+        # read() advances the file offset: two reads return consecutive bytes
+        assert _raw(ctx, g.NR_READ, [fd, buf.dev, 4000]) == 4000
+        assert _raw(ctx, g.NR_READ, [fd, buf.dev + 4000, 1 << 14]) == len(body) - 4000
+        assert _raw(ctx, g.NR_READ, [fd, buf.dev, 16]) == 0          # end of file
+        assert buf.array[:len(body)].tobytes() == body
+        # a read-only open cannot write
+        assert _raw(ctx, g.NR_WRITE, [fd, buf.dev, 16]) == -errno.EBADF
+        assert _raw(ctx, g.NR_CLOSE, [fd]) == 0
+        assert _raw(ctx, g.NR_CLOSE, [fd]) == -errno.EBADF        # already closed
+        assert _raw(ctx, g.NR_READ, [fd, buf.dev, 16]) == -errno.EBADF
+        # escapes: absolute path, "..", a symlink out of the directory
+        for bad in (b"/etc/hostname", b"../outside.bin", b"sub/../../outside.bin", b"escape"):
+            p = _path(ctx, bad)
+            r = _raw(ctx, g.NR_OPENAT, [dfd, p.dev, os.O_RDONLY, 0])
+            assert r in (-errno.EXDEV, -errno.ELOOP), (bad, r)
+        # flags outside the whitelist; writing into a read-only directory
+        assert _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_RDONLY | os.O_DIRECTORY, 0]) == -errno.EINVAL
+        assert _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_RDONLY | 0o10000000, 0]) == -errno.EINVAL
+        assert _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_WRONLY, 0]) == -errno.EPERM
+        new = _path(ctx, b"made.bin")
+        assert _raw(ctx, g.NR_OPENAT, [dfd, new.dev, os.O_WRONLY | os.O_CREAT, 0o644]) == -errno.EPERM
+        # a path without a NUL in GSYS_PATH_MAX bytes, a path outside any buffer
+        long = ctx.host_alloc(g.PATH_MAX)
+        long.array[:g.PATH_MAX] = ord("a")
+        assert _raw(ctx, g.NR_OPENAT, [dfd, long.dev, os.O_RDONLY, 0]) == -errno.ENAMETOOLONG
+        assert _raw(ctx, g.NR_OPENAT, [dfd, 0x1000, os.O_RDONLY, 0]) == -errno.EFAULT
+        # a writable directory: create, write, read back through the caller
+        ctx.allow_fd(dfd, g.FD_READ | g.FD_WRITE | g.FD_DIR)
+        wfd = _raw(ctx, g.NR_OPENAT, [dfd, new.dev, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o600])
+        assert wfd >= 0
+        assert _raw(ctx, g.NR_WRITE, [wfd, buf.dev, 100]) == 100
+        assert _raw(ctx, g.NR_WRITE, [wfd, buf.dev + 100, 28]) == 28
+        assert _raw(ctx, g.NR_READ, [wfd, buf.dev, 16]) == -errno.EBADF   # write-only
+        assert _raw(ctx, g.NR_CLOSE, [wfd]) == 0
+        assert open(os.path.join(d, "made.bin"), "rb").read() == body[:128]
+        assert (os.stat(os.path.join(d, "made.bin")).st_mode & 0o777) == 0o600
+        # an fd left open is closed by the pool at shutdown
+        left = _raw(ctx, g.NR_OPENAT, [dfd, good.dev, os.O_RDONLY, 0])
+        assert left >= 0 and os.readlink("/proc/self/fd/%d" % left).endswith("sub/f.bin")
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(dfd)
+    assert not os.path.exists("/proc/self/fd/%d" % left) or \
+        not os.readlink("/proc/self/fd/%d" % left).endswith("sub/f.bin")

@@ -297,3 +297,30 @@ def test_permute_offset_bad_fd_and_bad_tables(tmpdata):
     bad[3] = 1024
     with pytest.raises(OSError):
         oracle.permute(987654, ps.data, bad, ps.tau, 1)
+
+
+# ------------------------------------------- wordcount with open/read/close
+
+@pytest.mark.parametrize("chunk", [1, 7, 4096, 1 << 20])
+def test_wordcount_open_vs_bytes_split(tmpdata, chunk):
+    """Files opened by name and read with read() in pieces of any size give
+    the bytes.split() counts and their sizes as byte counts."""
+    os.environ["GSYS_DATA_DIR"] = tmpdata
+    c = synth.wordcount_corpus(n_files=6, median_bytes=6000, n_vocab=200, tag="pinopen")
+    d = os.path.dirname(c.paths[0])
+    names = [os.path.basename(p) for p in c.paths]
+    counts, rets = oracle.wordcount_open(d, names, c.queries, chunk=chunk, threads=3)
+    for f, p in enumerate(c.paths):
+        data = open(p, "rb").read()
+        assert rets[f] == len(data)
+        cnt = collections.Counter(data.split())
+        assert counts[f].tolist() == [cnt.get(q, 0) for q in c.queries]
+
+
+def test_wordcount_open_missing_file_and_subdirectory(tmpdata):
+    d = os.path.join(tmpdata, "open_pin")
+    os.makedirs(os.path.join(d, "s"), exist_ok=True)
+    open(os.path.join(d, "s", "a.txt"), "wb").write(b"x y\nx")
+    counts, rets = oracle.wordcount_open(d, ["s/a.txt", "nope.txt"], [b"x", b"y"])
+    assert rets.tolist() == [5, -errno.ENOENT]
+    assert counts.tolist() == [[2, 1], [0, 0]]
