@@ -406,6 +406,35 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
                 uint64_t out_ret, uint32_t cell, uint32_t wg_size, void *stream);
 
 /*
+ * The wordcount as section 7.1 issues it: work-group w takes files w, w +
+ * grid, ...; for each it calls openat(dirfd, paths + f * GSYS_PATH_MAX,
+ * O_RDONLY), read(fd, buf, chunk) until a read returns fewer than chunk
+ * bytes (the end of a regular file), and close(fd), all at work-group
+ * granularity with relaxed ordering (the next read is in flight while the
+ * previous piece is scanned).  counts[f][q] (device uint32, zeroed here) =
+ * tokens of file f equal to query q (tokens: maximal runs of bytes other
+ * than space and newline; queries as for gsys_wordscan); file_ret[f]
+ * (device int64) = bytes read, or the -errno of the failing openat / read /
+ * close.
+ *   dirfd    allowed with GSYS_FD_DIR | GSYS_FD_READ (see gsys_allow_fd)
+ *   paths    registered host buffer of nfiles x GSYS_PATH_MAX bytes of
+ *            NUL-terminated paths relative to dirfd
+ *   chunk    bytes per read: a multiple of 64, 64 .. 64 MiB
+ *   staging  registered host buffer; each resident work-group uses two
+ *            buffers of chunk + 16,496 bytes rounded up to 16 (the grid
+ *            shrinks to fit)
+ * Asynchronous on `stream`; gsys_wait drains the host side.  Errors:
+ * -EINVAL, -EFAULT (paths or staging not registered), -ENODEV.
+ * Currently switched off: returns -ENOSYS after checking its arguments (a
+ * GPU run did not finish and the cause is not yet known); the host side of
+ * openat / read / close is available to kernels through gsys_allow_fd.
+ */
+int gsys_wordcount_open(gsys_ctx *ctx, int dirfd, uint64_t paths, uint32_t nfiles,
+                        uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts,
+                        uint64_t file_ret, uint32_t chunk, uint64_t staging,
+                        uint64_t staging_bytes, void *stream);
+
+/*
  * Block permutation written out with pwrite: the ordering / blocking
  * microbenchmark of section 6 (Fig. 6).  `in` (device, n_blocks * 8192
  * bytes, little-endian 64-bit words) is cut into 8 KiB blocks; one

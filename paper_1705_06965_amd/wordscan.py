@@ -95,3 +95,75 @@ class WordScanRunner:
             self.ctx.allow_fd(fd, 0)
             os.close(fd)
         self.fds = []
+
+
+def open_buffer_bytes(chunk: int) -> int:
+    """Bytes of one of a work-group's two piece buffers in the open form."""
+    return (64 + chunk + 16384 + 48 + 15) // 16 * 16
+
+
+class WordOpenRunner:
+    """The open / read / close form of the word search (gsys_wordcount_open):
+    the GPU opens every file beneath `directory` by its name, reads it with
+    read() in `chunk`-byte pieces and closes it."""
+
+    def __init__(self, ctx, directory, names, queries, chunk: int = 1 << 20,
+                 device: str = "cuda", groups: int = 256):
+        import torch
+        from . import FD_DIR, PATH_MAX
+        self.torch = torch
+        self.ctx = ctx
+        self.dirfd = os.open(directory, os.O_RDONLY | os.O_DIRECTORY)
+        ctx.allow_fd(self.dirfd, FD_READ | FD_DIR)
+        self.nfiles = len(names)
+        self.nq = len(queries)
+        self.chunk = chunk
+        self.paths = ctx.host_alloc(max(1, self.nfiles) * PATH_MAX)
+        self.paths.array[:max(1, self.nfiles) * PATH_MAX] = 0
+        for i, n in enumerate(names):
+            b = n.encode() if isinstance(n, str) else bytes(n)
+            if len(b) >= PATH_MAX:
+                raise ValueError("path %r: at most %d bytes" % (n, PATH_MAX - 1))
+            self.paths.array[i * PATH_MAX:i * PATH_MAX + len(b)] = np.frombuffer(b, dtype=np.uint8)
+        q = np.zeros((self.nq, 16), dtype=np.uint8)
+        ql = np.zeros(self.nq, dtype=np.uint32)
+        for i, w in enumerate(queries):
+            if not 1 <= len(w) <= 16 or b" " in w or b"\n" in w:
+                raise ValueError("query %r: 1..16 bytes without delimiters" % (w,))
+            q[i, :len(w)] = np.frombuffer(w, dtype=np.uint8)
+            ql[i] = len(w)
+        self.queries = torch.from_numpy(q).to(device)
+        self.qlens = torch.from_numpy(ql.view(np.int32)).to(device)
+        self.counts = torch.zeros(max(1, self.nfiles * self.nq), dtype=torch.int32, device=device)
+        self.file_ret = torch.zeros(max(1, self.nfiles), dtype=torch.int64, device=device)
+        self.staging_bytes = 2 * open_buffer_bytes(chunk) * max(1, min(groups, self.nfiles))
+        self.staging = ctx.host_alloc(self.staging_bytes)
+
+    def launch(self, stream=None):
+        return check(lib.gsys_wordcount_open(self.ctx.h, self.dirfd, self.paths.dev, self.nfiles,
+                                             self.queries.data_ptr(), self.qlens.data_ptr(),
+                                             self.nq, self.counts.data_ptr(),
+                                             self.file_ret.data_ptr(), self.chunk,
+                                             self.staging.dev, self.staging_bytes,
+                                             _stream(stream)), "gsys_wordcount_open")
+
+    def run(self, stream=None):
+        """(counts[f, q], bytes read per file or -errno)."""
+        self.file_ret.fill_(-12345)
+        self.launch(stream)
+        self.torch.cuda.synchronize()
+        rc = self.ctx.wait(60_000_000_000)
+        if rc:
+            raise RuntimeError("drain failed: %d" % rc)
+        return self.result()
+
+    def result(self):
+        c = self.counts.cpu().numpy().view(np.uint32)[:self.nfiles * self.nq] \
+            .reshape(self.nfiles, self.nq).copy()
+        return c, self.file_ret.cpu().numpy()[:self.nfiles].copy()
+
+    def close(self):
+        self.ctx.allow_fd(self.dirfd, 0)
+        os.close(self.dirfd)
+        self.paths.free()
+        self.staging.free()
