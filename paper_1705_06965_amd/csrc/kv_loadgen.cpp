@@ -5,6 +5,8 @@
 // match replies to requests by id (request k carries id k + 1), and
 // retransmit a request whose reply has not come within rto_ns (UDP may drop
 // datagrams; a GET is idempotent, so a duplicate reply is identical).
+// Requests go out and replies come in up to kBatch datagrams per kernel call
+// (sendmmsg / recvmmsg), so that the generator is not what bounds a server.
 #include <arpa/inet.h>
 #include <errno.h>
 #include <netinet/in.h>
@@ -22,6 +24,8 @@
 #include "gsys.h"
 
 namespace {
+
+constexpr uint32_t kBatch = 64;
 
 uint64_t now_ns() {
   timespec ts;
@@ -63,7 +67,10 @@ void client(uint32_t port, const uint8_t* reqs, uint32_t req_len, Slice* sl, uin
   std::vector<uint8_t> state(n, 0);        // 0 unsent, 1 outstanding, 2 done
   std::vector<uint64_t> t_first(n, 0), t_last(n, 0);
   uint64_t next = 0, oldest = 0, outstanding = 0, done = 0;
-  std::vector<uint8_t> rbuf(std::max<uint32_t>(stride, 2048));
+  const uint32_t rsz = std::max<uint32_t>(stride, 2048);
+  std::vector<uint8_t> rbuf((size_t)rsz * kBatch);
+  mmsghdr mm[kBatch];
+  iovec iov[kBatch];
   while (done < n) {
     const uint64_t t = now_ns();
     if (t > deadline) {
@@ -72,39 +79,67 @@ void client(uint32_t port, const uint8_t* reqs, uint32_t req_len, Slice* sl, uin
     }
     // new requests
     while (outstanding < window && next < n) {
-      const uint64_t k = sl->lo + next;
-      if (sendto(fd, reqs + k * req_len, req_len, 0, (sockaddr*)&srv, sizeof srv) < 0) {
+      const uint32_t m = (uint32_t)std::min<uint64_t>({kBatch, window - outstanding, n - next});
+      for (uint32_t j = 0; j < m; ++j) {
+        const uint64_t k = sl->lo + next + j;
+        iov[j].iov_base = const_cast<uint8_t*>(reqs + k * req_len);
+        iov[j].iov_len = req_len;
+        memset(&mm[j], 0, sizeof mm[j]);
+        mm[j].msg_hdr.msg_name = &srv;
+        mm[j].msg_hdr.msg_namelen = sizeof srv;
+        mm[j].msg_hdr.msg_iov = &iov[j];
+        mm[j].msg_hdr.msg_iovlen = 1;
+      }
+      const int sent = sendmmsg(fd, mm, m, 0);
+      if (sent < 0) {
         if (errno == EAGAIN || errno == ENOBUFS) break;
         sl->err = -errno;
         close(fd);
         return;
       }
-      state[next] = 1;
-      t_first[next] = t_last[next] = now_ns();
-      ++next;
-      ++outstanding;
+      const uint64_t t1 = now_ns();
+      for (int j = 0; j < sent; ++j) {
+        state[next] = 1;
+        t_first[next] = t_last[next] = t1;
+        ++next;
+        ++outstanding;
+      }
+      if ((uint32_t)sent < m) break;
     }
     // replies
     bool any = false;
     for (;;) {
-      ssize_t r = recv(fd, rbuf.data(), rbuf.size(), MSG_DONTWAIT);
-      if (r < 0) break;
+      for (uint32_t j = 0; j < kBatch; ++j) {
+        iov[j].iov_base = rbuf.data() + (size_t)j * rsz;
+        iov[j].iov_len = rsz;
+        memset(&mm[j], 0, sizeof mm[j]);
+        mm[j].msg_hdr.msg_iov = &iov[j];
+        mm[j].msg_hdr.msg_iovlen = 1;
+      }
+      const int got = recvmmsg(fd, mm, kBatch, MSG_DONTWAIT, nullptr);
+      if (got <= 0) break;
       any = true;
-      if (r < 16) continue;
-      uint64_t id;
-      memcpy(&id, rbuf.data(), 8);
-      if (id == 0) continue;
-      const uint64_t k = id - 1;
-      if (k < sl->lo || k >= sl->hi) continue;
-      const uint64_t i = k - sl->lo;
-      if (state[i] != 1) continue;  // duplicate
-      state[i] = 2;
-      const uint32_t len = (uint32_t)std::min<ssize_t>(r, stride);
-      memcpy(replies + k * (uint64_t)stride, rbuf.data(), len);
-      reply_len[k] = (uint32_t)r;
-      if (lat_ns) lat_ns[k] = now_ns() - t_first[i];
-      --outstanding;
-      ++done;
+      const uint64_t t1 = now_ns();
+      for (int j = 0; j < got; ++j) {
+        const uint8_t* rb = rbuf.data() + (size_t)j * rsz;
+        const uint32_t r = mm[j].msg_len;
+        if (r < 16) continue;
+        uint64_t id;
+        memcpy(&id, rb, 8);
+        if (id == 0) continue;
+        const uint64_t k = id - 1;
+        if (k < sl->lo || k >= sl->hi) continue;
+        const uint64_t i = k - sl->lo;
+        if (state[i] != 1) continue;  // duplicate
+        state[i] = 2;
+        const uint32_t len = std::min<uint32_t>(r, stride);
+        memcpy(replies + k * (uint64_t)stride, rb, len);
+        reply_len[k] = r;
+        if (lat_ns) lat_ns[k] = t1 - t_first[i];
+        --outstanding;
+        ++done;
+      }
+      if ((uint32_t)got < kBatch) break;
     }
     while (oldest < next && state[oldest] == 2) ++oldest;
     if (!any) {

@@ -455,3 +455,76 @@ def test_openat_read_close_beneath_an_allowed_directory(tmpdata):
         os.close(dfd)
     assert not os.path.exists("/proc/self/fd/%d" % left) or \
         not os.readlink("/proc/self/fd/%d" % left).endswith("sub/f.bin")
+
+
+NETDESC = np.dtype([("buf_off", "<u4"), ("len_ret", "<i4"), ("addr_len", "<u4"), ("pad", "<u4"),
+                    ("addr", "u1", 16)])
+
+
+def test_socket_lists_keep_per_datagram_semantics():
+    """Receive and send lists run as batched kernel calls but keep the
+    one-call-per-descriptor results: datagrams in order, truncation to the
+    buffer, -EINVAL / -EFAULT for bad descriptors without ending the list,
+    -EAGAIN for every receive after the socket is drained, -EINVAL for a
+    non-loopback destination, more than one batch per list."""
+    import time
+    srv = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
+    srv.setsockopt(socket.SOL_SOCKET, socket.SO_RCVBUF, 1 << 22)
+    srv.bind(("127.0.0.1", 0))
+    cli = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
+    cli.bind(("127.0.0.1", 0))
+    ctx = _ctx()
+    try:
+        ctx.allow_fd(srv.fileno(), g.FD_SOCK)
+        n_dgram, n_desc = 150, 200
+        payload = [bytes([i % 251]) * (1 + (i * 37) % 300) for i in range(n_dgram)]
+        for p in payload:
+            cli.sendto(p, srv.getsockname())
+        time.sleep(0.1)
+        bufs = ctx.host_alloc(n_desc * 512)
+        lst = ctx.host_alloc(n_desc * NETDESC.itemsize)
+        d = np.zeros(n_desc, dtype=NETDESC)
+        d["buf_off"] = np.arange(n_desc) * 512
+        d["len_ret"] = 512
+        d["len_ret"][10] = -1                       # invalid length
+        d["buf_off"][20] = 1 << 30                  # outside any registered buffer
+        d["len_ret"][30] = 8                        # shorter than its datagram
+        lst.array[:d.nbytes] = d.view(np.uint8)
+        r = _raw(ctx, g.NR_RECVFROM, [srv.fileno(), lst.dev, n_desc, bufs.dev, 0],
+                 flags=g.F_BLOCKING | g.F_LIST)
+        assert r == -errno.EINVAL                   # the first error of the list
+        out = lst.array[:d.nbytes].view(NETDESC)
+        got = out["len_ret"]
+        assert got[10] == -errno.EINVAL and got[20] == -errno.EFAULT
+        valid = [i for i in range(n_desc) if i not in (10, 20)]
+        for k, i in enumerate(valid):
+            if k < n_dgram:
+                want = min(len(payload[k]), 8 if i == 30 else 512)
+                assert got[i] == want, (i, k)
+                assert bufs.array[i * 512:i * 512 + want].tobytes() == payload[k][:want]
+            else:
+                assert got[i] == -errno.EAGAIN, i
+        # send back to the recorded senders; one destination is not loopback
+        s = np.zeros(n_dgram, dtype=NETDESC)
+        s["buf_off"] = np.array(valid[:n_dgram]) * 512
+        s["len_ret"] = [min(len(payload[k]), 8 if valid[k] == 30 else 512) for k in range(n_dgram)]
+        s["addr_len"] = out["addr_len"][valid[:n_dgram]]
+        s["addr"] = out["addr"][valid[:n_dgram]]
+        s["addr"][5, 4:8] = [8, 8, 8, 8]
+        lst.array[:s.nbytes] = s.view(np.uint8)
+        r = _raw(ctx, g.NR_SENDTO, [srv.fileno(), lst.dev, n_dgram, bufs.dev, 0],
+                 flags=g.F_BLOCKING | g.F_LIST)
+        assert r == -errno.EINVAL
+        sent = lst.array[:s.nbytes].view(NETDESC)["len_ret"]
+        assert sent[5] == -errno.EINVAL
+        assert (np.delete(sent, 5) == np.delete(s["len_ret"], 5)).all()
+        cli.settimeout(2.0)
+        echoed = [cli.recvfrom(1024)[0] for _ in range(n_dgram - 1)]
+        want = [payload[k][:s["len_ret"][k]] for k in range(n_dgram) if k != 5]
+        assert echoed == want
+        st = ctx.stats()
+        assert st["merged"] > 0                      # datagrams shared kernel calls
+    finally:
+        ctx.shutdown()
+        srv.close()
+        cli.close()
