@@ -62,9 +62,13 @@ def parse():
                     help="permute: permutation rounds per block before the pwrite")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "tiny", "wordscan", "kv", "serve", "permute",
-                             "granularity", "coalesce", "wordopen"],
+                             "granularity", "coalesce", "wordopen", "doorbell"],
                     help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
                          "word search over 2,000 files")
+    ap.add_argument("--db-gap-us", type=int, default=2000,
+                    help="doorbell: GPU idle time before each tiny launch")
+    ap.add_argument("--db-serve-rate", type=float, default=2000.0,
+                    help="doorbell: offered load of the low-load serving run (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -138,6 +142,8 @@ def main():
         return run_wordopen(args)
     if args.workload == "granularity":
         return run_granularity(args)
+    if args.workload == "doorbell":
+        return run_doorbell(args)
     if args.workload == "coalesce":
         return run_coalesce(args)
     import synth
@@ -1180,6 +1186,109 @@ def run_wordopen(args):
     ctx.shutdown()
     print(json.dumps(res), flush=True)
 
+
+
+def _cpu_s():
+    import resource
+    ru = resource.getrusage(resource.RUSAGE_SELF)
+    return ru.ru_utime + ru.ru_stime
+
+
+def run_doorbell(args):
+    """Host cost of waiting for a quiet GPU: spinning pollers against the
+    doorbell (idle pollers block on an HSA interrupt signal the kernels
+    raise).  Per mode: the host CPU time the whole process burns per second
+    of wall time while the GPU is idle, and the tiny case (one work-group x
+    64 blocking 4 KiB preads) launched after `--db-gap-us` of idleness each
+    time, end-to-end latency and CPU per second; then the serving mix at a
+    low offered load (`--db-serve-rate`), latency and CPU per second.
+    value = 64 calls / median tiny latency with the doorbell."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fnv import FnvRunner
+    from paper_1705_06965_amd.serve import ServeRun
+    path = synth.random_file(1, 262144, name="c1_256k.bin")
+    offs = synth.tiny_offsets(64)
+    want, _ = oracle.pread_fnv(path, offs, 4096)
+    reps = max(50, args.steps)
+    cell = g.cell_code("WI", "strong", "block")
+    stream = torch.cuda.current_stream()
+    modes = {}
+    js = None
+    if args.db_serve_rate > 0:
+        in_path = synth.random_file(2, FILE_BYTES, name="c2_1g.bin")
+        out_path = os.path.join(synth.data_dir(), "serve_out_db.bin")
+        n_jobs = max(2000, int(args.db_serve_rate * 3))
+        js = synth.job_stream(n_jobs=n_jobs, rate_per_s=args.db_serve_rate)
+    for mode, flags in (("spin", 0), ("doorbell", g.CFG_DOORBELL)):
+        ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
+                        device_timeout_ns=60_000_000_000, flags=flags,
+                        arena_bytes=(16 << 30) if js is not None else 0)
+        r = FnvRunner(ctx, path, offs, 4096, wg_size=64)
+        for _ in range(max(1, args.warmup)):
+            r.launch(cell, g.PLAIN, stream)
+            torch.cuda.synchronize()
+            ctx.wait(10_000_000_000)
+        # idle: nothing launched for one second
+        c0, w0 = _cpu_s(), time.perf_counter()
+        time.sleep(1.0)
+        idle_cores = (_cpu_s() - c0) / (time.perf_counter() - w0)
+        s0 = ctx.stats()["doorbell_sleeps"]
+        e2e = []
+        c0, w0 = _cpu_s(), time.perf_counter()
+        for _ in range(reps):
+            time.sleep(args.db_gap_us * 1e-6)
+            t0 = time.perf_counter()
+            r.launch(cell, g.PLAIN, stream)
+            torch.cuda.synchronize()
+            if ctx.wait(10_000_000_000):
+                raise RuntimeError("drain failed")
+            e2e.append((time.perf_counter() - t0) * 1e6)
+        tiny_cores = (_cpu_s() - c0) / (time.perf_counter() - w0)
+        f, ret = r.result()
+        if not ((ret == 4096).all() and (f == want).all()):
+            raise RuntimeError("GPU checksums differ from the oracle (%s)" % mode)
+        m = {"idle_host_cores_busy": round(idle_cores, 3),
+             "tiny_after_gap": {"gap_us": args.db_gap_us, "runs": reps,
+                                "latency_us_p50": round(float(np.percentile(e2e, 50)), 1),
+                                "latency_us_p99": round(float(np.percentile(e2e, 99)), 1),
+                                "host_cores_busy": round(tiny_cores, 3)},
+             "pollers_blocked": ctx.stats()["doorbell_sleeps"] - s0}
+        r.close()
+        if js is not None:
+            sr = ServeRun(ctx, js, in_path, out_path)
+            c0, w0 = _cpu_s(), time.perf_counter()
+            res, _, lat = sr.run(g.PERSISTENT, max_inflight=args.serve_inflight,
+                                 staging_bytes=(2 << 20) * 256, timeout_ns=300_000_000_000)
+            cores = (_cpu_s() - c0) / (time.perf_counter() - w0)
+            w = len(js.kind) // 10
+            ls = lat[w:].astype(np.float64) / 1e3
+            if (res < 0).any():
+                raise RuntimeError("serving job failed (%s)" % mode)
+            m["serve_low_load"] = {"offered_jobs_per_s": args.db_serve_rate, "jobs": len(js.kind),
+                                   "latency_us_p50": round(float(np.percentile(ls, 50)), 1),
+                                   "latency_us_p99": round(float(np.percentile(ls, 99)), 1),
+                                   "host_cores_busy": round(cores, 3)}
+            sr.close()
+        modes[mode] = m
+        ctx.shutdown()
+        print("doorbell bench: %s done" % mode, file=sys.stderr, flush=True)
+    med = modes["doorbell"]["tiny_after_gap"]["latency_us_p50"]
+    res_j = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(64 / (med * 1e-6), 1), "unit": "calls/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": round(med / 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "doorbell against spinning pollers: tiny plain form (1 x 64 "
+                               "blocking 4 KiB preads) after %d us of GPU idleness, and the "
+                               "serving mix at %.0f jobs/s" % (args.db_gap_us, args.db_serve_rate),
+                   "form": "plain (tiny), persistent (serving)"},
+        "modes": modes,
+    }
+    print(json.dumps(res_j), flush=True)
 
 if __name__ == "__main__":
     main()

@@ -41,6 +41,9 @@ typedef struct gsys_ctx gsys_ctx;
 #define GSYS_CFG_NO_PIN    0x4u  /* do not pin service threads to cores              */
 #define GSYS_CFG_SHARED_FDS 0x8u /* positional calls use the caller's descriptors
                                     directly (no per-thread copies, see below)       */
+#define GSYS_CFG_DOORBELL  0x10u /* idle pollers block on an interrupt signal that
+                                    the GPU raises after publishing, instead of
+                                    spinning (see gsys_init)                          */
 
 typedef struct gsys_config {
     uint32_t abi_version;        /* must be GSYS_ABI_VERSION                          */
@@ -59,7 +62,9 @@ typedef struct gsys_config {
     uint32_t ledger_capacity;    /* ledger records kept (0 = 1<<20)                   */
     uint32_t sleep_max;          /* GPU wait backoff cap, in s_sleep steps of ~256
                                     clocks doubled up to this count (0 = 64)           */
-    uint32_t reserved[3];
+    uint32_t doorbell_idle_us;   /* GSYS_CFG_DOORBELL: how long a poller finds nothing
+                                    before it blocks (0 = 200)                        */
+    uint32_t reserved[2];
 } gsys_config;
 
 /*
@@ -69,8 +74,20 @@ typedef struct gsys_config {
  * The ring replaces the paper's syscall area (section 5); the polling pool
  * replaces its interrupt + work-queue dispatch (section 3 notes that the
  * design is orthogonal to interrupts versus polling).
+ * GSYS_CFG_DOORBELL: the context also creates an HSA interrupt signal.  A
+ * poller that has found nothing for a while counts itself in a host-coherent
+ * sleeper word, scans once more and blocks on the signal (1 ms at most); a
+ * GPU caller that has published a request and sees a non-zero sleeper count
+ * adds 1 to the signal, which raises an interrupt and wakes the blocked
+ * pollers.  Fences on both sides order the READY store / sleeper load
+ * against the sleeper store / last scan, so a request is never left with
+ * every poller asleep.  Pollers then cost no CPU while the GPU is quiet, at
+ * the price of the interrupt's latency on the first request after a pause.
+ * In a GSYS_CFG_NO_DEVICE context the doorbell is a condition variable that
+ * the emulated callers (gsys_testing.h) raise the same way.
  * cfg == NULL uses all defaults.  *out receives the context.
- * Errors: -EINVAL (bad D / version), -ENOMEM, -ENODEV (HIP failure).
+ * Errors: -EINVAL (bad D / version), -ENOMEM, -ENODEV (HIP failure),
+ * -ENOTSUP (GSYS_CFG_DOORBELL, but no interrupt signal mapped for the GPU).
  */
 int gsys_init(const gsys_config *cfg, gsys_ctx **out);
 
@@ -190,6 +207,7 @@ typedef struct gsys_stats {
     uint64_t service_ns;        /* host time spent executing calls               */
     uint64_t bundle_hist[8];    /* bundle sizes 1, 2, 3-4, 5-8, 9-16, 17-32, 33-64, 65+ */
     uint64_t errno_hist[8];     /* EPERM, EBADF, EFAULT, EINVAL, EAGAIN, ESHUTDOWN, ETIMEDOUT, other */
+    uint64_t doorbell_sleeps;   /* times a poller blocked on the doorbell        */
 } gsys_stats;
 
 /* Snapshot (and optionally reset) the counters. */

@@ -126,6 +126,8 @@ typedef struct gsys_dev_ctx {
     uint32_t flags;
     uint64_t arena;                  /* reserved range for GPU mmap (0 = none)   */
     uint64_t arena_bytes;
+    uint64_t doorbell;               /* interrupt signal handle (0 = pollers spin) */
+    const uint64_t *sleepers;        /* host-coherent: pollers blocked on it      */
 } gsys_dev_ctx;
 
 #define GSYS_ETIMEDOUT_RET (-110)    /* -ETIMEDOUT */

@@ -31,7 +31,7 @@ F_BLOCKING, F_LIST, F_PRODUCER, F_STRONG = 0x1, 0x2, 0x4, 0x8
 GRAN_WI, GRAN_WG, GRAN_KERNEL = 0, 1, 2
 CELL_STRONG, CELL_BLOCKING = 0x4, 0x8
 PLAIN, PERSISTENT, GRAPH = 0, 1, 2
-CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS = 0x1, 0x2, 0x4, 0x8
+CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS, CFG_DOORBELL = 0x1, 0x2, 0x4, 0x8, 0x10
 FD_READ, FD_WRITE, FD_SOCK, FD_DIR = 0x1, 0x2, 0x4, 0x8
 BUF_HOST, BUF_DEVICE = 1, 2
 EMU_BLOCKING, EMU_LIST = 0x1, 0x2
@@ -63,14 +63,16 @@ class gsys_config(C.Structure):
                 ("stripe", C.c_uint32), ("flags", C.c_uint32),
                 ("arena_bytes", C.c_uint64), ("device_timeout_ns", C.c_uint64),
                 ("first_cpu", C.c_int32), ("ledger_capacity", C.c_uint32),
-                ("sleep_max", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("sleep_max", C.c_uint32), ("doorbell_idle_us", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
 class gsys_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "requests", "host_calls", "bytes_in", "bytes_out", "errors", "rejected", "bundles",
         "merged", "idle_polls", "retired_lo", "claimed", "service_ns")] + [
-        ("bundle_hist", C.c_uint64 * 8), ("errno_hist", C.c_uint64 * 8)]
+        ("bundle_hist", C.c_uint64 * 8), ("errno_hist", C.c_uint64 * 8),
+        ("doorbell_sleeps", C.c_uint64)]
 
 
 class gsys_dev_ctx(C.Structure):
@@ -78,7 +80,8 @@ class gsys_dev_ctx(C.Structure):
                 ("retired_lo", C.c_uint64), ("ring_mask", C.c_uint64),
                 ("comp_mask", C.c_uint64), ("timeout_ticks", C.c_uint64),
                 ("sleep_max", C.c_uint32), ("flags", C.c_uint32),
-                ("arena", C.c_uint64), ("arena_bytes", C.c_uint64)]
+                ("arena", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("doorbell", C.c_uint64), ("sleepers", C.c_uint64)]
 
 
 class gsys_launch_desc(C.Structure):
@@ -212,7 +215,7 @@ class Context:
 
     def __init__(self, ring_slots=0, service_threads=0, coalesce_max=1, coalesce_window_ns=0,
                  stripe=0, flags=0, arena_bytes=0, device_timeout_ns=0, first_cpu=-1, device=0,
-                 ledger_capacity=0, sleep_max=0):
+                 ledger_capacity=0, sleep_max=0, doorbell_idle_us=0):
         cfg = gsys_config()
         cfg.abi_version = ABI_VERSION
         cfg.device = device
@@ -227,6 +230,7 @@ class Context:
         cfg.first_cpu = first_cpu
         cfg.ledger_capacity = ledger_capacity
         cfg.sleep_max = sleep_max
+        cfg.doorbell_idle_us = doorbell_idle_us
         h = C.c_void_p()
         check(lib.gsys_init(C.byref(cfg), C.byref(h)), "gsys_init")
         self.h = h.value
@@ -267,6 +271,7 @@ class Context:
         d = {n: getattr(s, n) for n, _ in gsys_stats._fields_[:12]}
         d["bundle_hist"] = list(s.bundle_hist)
         d["errno_hist"] = list(s.errno_hist)
+        d["doorbell_sleeps"] = s.doorbell_sleeps
         return d
 
     def ledger(self, max_records: int = 1 << 22, reset: bool = False) -> np.ndarray:

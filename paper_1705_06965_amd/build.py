@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
     objs = [j[j.index("-o") + 1] for j in jobs]
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
-         + ["-pthread", "-Wl,--no-undefined", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64"])
+         + ["-pthread", "-Wl,--no-undefined", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhsa-runtime64"])
     os.replace(tmp, LIB)
     return LIB
 

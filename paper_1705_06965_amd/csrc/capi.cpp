@@ -1,15 +1,22 @@
 // C ABI of libgsys.so: context set-up and tear-down, whitelist registration,
 // launches and the drain call.  See include/gsys.h for the contract.
 #include <errno.h>
+#include <linux/futex.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <sys/mman.h>
+#include <sys/syscall.h>
 #include <time.h>
 #include <unistd.h>
 
 #include <hip/hip_runtime.h>
+#include <hsa/amd_hsa_signal.h>
+#include <hsa/hsa.h>
+#include <hsa/hsa_ext_amd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -19,6 +26,70 @@
 #include "gsys_testing.h"
 #include "host_pool.hpp"
 #include "kernels.hpp"
+
+namespace {
+
+// Pollers block on a futex word.  In CPU-only contexts the emulated callers
+// raise it directly; device contexts put a relay thread in front of it.
+class FutexDoorbell : public gsys_host::Doorbell {
+ public:
+  uint64_t value() override { return v_.load(std::memory_order_acquire); }
+  void wait(uint64_t seen, uint64_t timeout_ns) override {
+    // the kernel blocks only while the word still holds `seen`
+    timespec ts{(time_t)(timeout_ns / 1000000000ull), (long)(timeout_ns % 1000000000ull)};
+    syscall(SYS_futex, reinterpret_cast<uint32_t*>(&v_), FUTEX_WAIT_PRIVATE, (uint32_t)seen, &ts,
+            nullptr, 0);
+  }
+  void ring() override {
+    v_.fetch_add(1, std::memory_order_acq_rel);
+    syscall(SYS_futex, reinterpret_cast<uint32_t*>(&v_), FUTEX_WAKE_PRIVATE, INT32_MAX, nullptr,
+            nullptr, 0);
+  }
+
+ private:
+  std::atomic<uint32_t> v_{0};
+  static_assert(sizeof(std::atomic<uint32_t>) == 4, "futex word");
+};
+
+// Device contexts: the GPU raises an HSA interrupt signal (it stores
+// ticket + 1 into it; the host's own values have bit 62 set, so no value
+// repeats).  One relay thread waits on the signal and raises the pollers'
+// futex word: the runtime's wait polls for a while before it blocks, and
+// that cost is paid by one thread instead of by every poller.  The relay
+// reads the signal's new value before it raises the word, so a poller that
+// read the word after a raise is covered by the relay's next wait.
+class HsaDoorbell final : public FutexDoorbell {
+ public:
+  HsaDoorbell(hsa_signal_t s, uint64_t ticks_per_s) : s_(s), hz_(ticks_per_s) {
+    relay_ = std::thread([this] { relay(); });
+  }
+  ~HsaDoorbell() override {
+    stop_.store(true, std::memory_order_release);
+    hsa_signal_store_screlease(s_, (hsa_signal_value_t)((1ull << 62) | ++n_));
+    relay_.join();
+  }
+
+ private:
+  void relay() {
+    hsa_signal_value_t v = hsa_signal_load_scacquire(s_);
+    while (!stop_.load(std::memory_order_acquire)) {
+      hsa_signal_wait_scacquire(s_, HSA_SIGNAL_CONDITION_NE, v, hz_ / 10 /* 100 ms */,
+                                HSA_WAIT_STATE_BLOCKED);
+      const hsa_signal_value_t nv = hsa_signal_load_scacquire(s_);
+      if (nv != v) {
+        v = nv;
+        ring();
+      }
+    }
+  }
+  hsa_signal_t s_;
+  uint64_t hz_;
+  std::atomic<uint64_t> n_{0};
+  std::atomic<bool> stop_{false};
+  std::thread relay_;
+};
+
+}  // namespace
 
 struct gsys_ctx {
   gsys_config cfg;
@@ -47,6 +118,12 @@ struct gsys_ctx {
   std::vector<hipGraph_t> graph_defs;
   void* ctl_host = nullptr;
   void* ctl_dev = nullptr;
+  // doorbell (GSYS_CFG_DOORBELL)
+  gsys_host::Doorbell* db = nullptr;
+  uint64_t* sleepers_dev = nullptr;  // host_words[64] as the GPU sees it
+  bool hsa_up = false;
+  bool sig_live = false;
+  hsa_signal_t sig{0};
 };
 
 namespace {
@@ -106,6 +183,68 @@ uint64_t claimed_tickets(gsys_ctx* c) {
   return v;
 }
 
+// The HIP device's HSA agent (matched by PCI location).
+struct AgentFind {
+  uint32_t bdf, domain;
+  hsa_agent_t agent;
+  bool found;
+};
+
+hsa_status_t find_agent(hsa_agent_t a, void* data) {
+  AgentFind* f = (AgentFind*)data;
+  hsa_device_type_t t;
+  if (hsa_agent_get_info(a, HSA_AGENT_INFO_DEVICE, &t) != HSA_STATUS_SUCCESS ||
+      t != HSA_DEVICE_TYPE_GPU)
+    return HSA_STATUS_SUCCESS;
+  uint32_t bdf = ~0u, dom = ~0u;
+  hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_BDFID, &bdf);
+  hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_DOMAIN, &dom);
+  if (bdf == f->bdf && dom == f->domain) {
+    f->agent = a;
+    f->found = true;
+    return HSA_STATUS_INFO_BREAK;
+  }
+  return HSA_STATUS_SUCCESS;
+}
+
+// true if the runtime reports [p, p + len) inside one allocation that
+// `agent` may access at the same address the host uses
+bool gpu_maps(hsa_agent_t agent, const void* p, uint64_t len) {
+  hsa_amd_pointer_info_t pi;
+  memset(&pi, 0, sizeof pi);
+  pi.size = sizeof pi;
+  uint32_t n = 0;
+  hsa_agent_t* acc = nullptr;
+  if (hsa_amd_pointer_info(p, &pi, malloc, &n, &acc) != HSA_STATUS_SUCCESS) return false;
+  bool ok = false;
+  for (uint32_t i = 0; i < n; ++i) ok = ok || acc[i].handle == agent.handle;
+  free(acc);
+  const uint64_t base = (uint64_t)pi.agentBaseAddress, a = (uint64_t)p;
+  return ok && pi.sizeInBytes && pi.agentBaseAddress == pi.hostBaseAddress && a >= base &&
+         a + len <= base + pi.sizeInBytes;
+}
+
+// An interrupt signal whose block and event mailbox this GPU may write.
+int make_hsa_doorbell(gsys_ctx* c, const hipDeviceProp_t& prop) {
+  if (hsa_init() != HSA_STATUS_SUCCESS) return -ENOTSUP;
+  c->hsa_up = true;
+  AgentFind f{((uint32_t)prop.pciBusID << 8) | ((uint32_t)prop.pciDeviceID << 3),
+              (uint32_t)prop.pciDomainID, hsa_agent_t{0}, false};
+  hsa_iterate_agents(find_agent, &f);
+  uint64_t hz = 0;
+  if (!f.found || hsa_system_get_info(HSA_SYSTEM_INFO_TIMESTAMP_FREQUENCY, &hz) != HSA_STATUS_SUCCESS ||
+      !hz)
+    return -ENOTSUP;
+  if (hsa_signal_create(0, 0, nullptr, &c->sig) != HSA_STATUS_SUCCESS) return -ENOTSUP;
+  c->sig_live = true;
+  const amd_signal_t* s = (const amd_signal_t*)c->sig.handle;
+  if (s->kind != AMD_SIGNAL_KIND_USER || !s->event_mailbox_ptr || !gpu_maps(f.agent, s, sizeof *s) ||
+      !gpu_maps(f.agent, (const void*)s->event_mailbox_ptr, sizeof(uint64_t)))
+    return -ENOTSUP;
+  c->db = new (std::nothrow) HsaDoorbell(c->sig, hz);
+  return c->db ? 0 : -ENOMEM;
+}
+
 void destroy(gsys_ctx* c) {
   if (!c) return;
   if (c->pool) {
@@ -114,6 +253,10 @@ void destroy(gsys_ctx* c) {
     delete c->pool;
     c->pool = nullptr;
   }
+  delete c->db;
+  c->db = nullptr;
+  if (c->sig_live) hsa_signal_destroy(c->sig);
+  if (c->hsa_up) hsa_shut_down();
   if (!c->no_device) {
     hipSetDevice(c->device);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.second);
@@ -203,6 +346,20 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
   }
   c->host_words = (uint64_t*)wh;
   c->retired_lo_dev = (uint64_t*)wd;
+  c->sleepers_dev = (uint64_t*)wd + 64;
+  if (cfg.flags & GSYS_CFG_DOORBELL) {
+    if (c->no_device) {
+      c->db = new (std::nothrow) FutexDoorbell;
+      e = c->db ? 0 : -ENOMEM;
+    } else {
+      hipDeviceProp_t prop;
+      e = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? make_hsa_doorbell(c, prop) : -ENODEV;
+    }
+    if (e) {
+      destroy(c);
+      return e;
+    }
+  }
   for (uint64_t i = 0; i < c->D; ++i) c->ring[i].ctl = GSYS_CTL(i, GSYS_ST_FREE);
   if (cfg.arena_bytes) {
     const uint64_t bytes = (cfg.arena_bytes + (2u << 20) - 1) & ~((2ull << 20) - 1);
@@ -226,6 +383,14 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
     return -ENOMEM;
   }
   if (c->arena) c->pool->set_arena(c->arena, c->arena_bytes);
+  if (c->db) {
+    const uint64_t idle_us =
+        env_u64("GSYS_DOORBELL_IDLE_US", cfg.doorbell_idle_us ? cfg.doorbell_idle_us : 200);
+    // each block lasts 50 ms at most: a backstop only, the doorbell wakes
+    // first (tests raise it so that a lost wake-up shows as a time-out)
+    const uint64_t backstop_us = env_u64("GSYS_DOORBELL_BACKSTOP_US", 50000);
+    c->pool->set_doorbell(c->db, &c->host_words[64], idle_us * 1000, backstop_us * 1000);
+  }
   c->pool->start();
   *out = c;
   return 0;
@@ -293,6 +458,11 @@ int gsys_device_ctx(gsys_ctx* c, gsys_dev_ctx* out) {
   out->flags = c->cfg.flags;
   out->arena = (uint64_t)c->arena;
   out->arena_bytes = c->arena_bytes;
+  if (c->db) {
+    // CPU-only contexts: any non-zero value; the emulated callers ring c->db
+    out->doorbell = c->no_device ? 1 : c->sig.handle;
+    out->sleepers = c->sleepers_dev;
+  }
   return 0;
 }
 
@@ -381,6 +551,7 @@ const char* gsys_strerror(int code) {
     case EOVERFLOW: return "completion record reused before it was read";
     case EAGAIN: return "try again";
     case EINPROGRESS: return "not waited for";
+    case ENOTSUP: return "no interrupt signal mapped for the GPU (doorbell)";
     default: return strerror(-code);
   }
 }
@@ -391,7 +562,15 @@ namespace {
 struct EmuShared {
   gsys_dev_ctx d;
   uint64_t timeout_ns;
+  gsys_host::Doorbell* db;
 };
+
+// after publishing, as the GPU does: fence, read the sleeper count, ring
+void emu_ring(const EmuShared& e) {
+  if (!e.db) return;
+  __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  if (__atomic_load_n(e.d.sleepers, __ATOMIC_RELAXED)) e.db->ring();
+}
 
 // claim n tickets, then wait until each of their slots is free for this lap
 uint64_t emu_claim(const EmuShared& e, uint32_t n, int* err) {
@@ -444,6 +623,7 @@ int gsys_test_emulate(gsys_ctx* c, uint32_t threads, uint64_t per, uint32_t grou
   EmuShared e;
   gsys_device_ctx(c, &e.d);
   e.timeout_ns = timeout_ns ? timeout_ns : 10000000000ull;
+  e.db = c->db;
   const bool blocking = mode & GSYS_EMU_BLOCKING;
   const bool list = mode & GSYS_EMU_LIST;
   std::vector<int> errs(threads, 0);
@@ -466,6 +646,7 @@ int gsys_test_emulate(gsys_ctx* c, uint32_t threads, uint64_t per, uint32_t grou
                       (uint8_t)(GSYS_F_LIST | (blocking ? GSYS_F_BLOCKING : 0) |
                                 (GSYS_GRAN_WG << GSYS_F_GRAN_SHIFT)),
                       1, 0, a);
+          emu_ring(e);
           err = emu_wait(e, t, 1);
           if (err) { errs[w] = err; break; }
           for (uint32_t i = 0; i < n; ++i) rets[k + i] = __atomic_load_n(&L[i].len_ret, __ATOMIC_ACQUIRE);
@@ -480,6 +661,7 @@ int gsys_test_emulate(gsys_ctx* c, uint32_t threads, uint64_t per, uint32_t grou
             emu_publish(e, t + i, GSYS_NR_PREAD64,
                         (uint8_t)((blocking ? GSYS_F_BLOCKING : 0) | GSYS_F_STRONG), n, i, a);
           }
+          emu_ring(e);
           err = emu_wait(e, t, n);
           if (err) { errs[w] = err; break; }
           for (uint32_t i = 0; i < n; ++i) {
@@ -505,10 +687,12 @@ int gsys_test_raw_call(gsys_ctx* c, uint16_t nr, uint8_t flags, const uint64_t* 
   EmuShared e;
   gsys_device_ctx(c, &e.d);
   e.timeout_ns = timeout_ns ? timeout_ns : 10000000000ull;
+  e.db = c->db;
   int err = 0;
   uint64_t t = emu_claim(e, 1, &err);
   if (err) return err;
   emu_publish(e, t, nr, flags, 1, 0, args6);
+  emu_ring(e);
   err = emu_wait(e, t, 1);
   if (err) return err;
   *ret = __atomic_load_n(&e.d.comp[t & e.d.comp_mask].ret, __ATOMIC_ACQUIRE);

@@ -23,6 +23,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hsa/amd_hsa_signal.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "gsys_abi.h"
@@ -134,6 +136,40 @@ struct Waiter {
     return wall_clock64() < deadline;
   }
 };
+
+// ---------------------------------------------------------------- doorbell
+// With a doorbell (c.doorbell != 0) the host's idle pollers block on an HSA
+// interrupt signal instead of spinning, and c.sleepers counts them.  The
+// signal's handle is the address of its amd_signal_t.  Raising it takes
+// three steps: store a value never stored before (the ticket + 1; the host's
+// waits compare against the value they last saw), store the event id in the
+// event's mailbox slot, and, once that store has completed, send an
+// interrupt message; the driver finds the signalled mailbox slot and wakes
+// the threads waiting on the event.  Only stores reach host memory: no
+// read-modify-write crosses the host link.  The context checked at set-up
+// that both the signal and the mailbox are mapped for this GPU.
+__device__ __forceinline__ void raise_doorbell(uint64_t h, uint64_t t) {
+  __hip_atomic_store(gp<int64_t>(h + offsetof(amd_signal_t, value)), (int64_t)(t + 1),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const uint64_t mb = *gp<const uint64_t>(h + offsetof(amd_signal_t, event_mailbox_ptr));
+  if (mb) {
+    const uint32_t id = *gp<const uint32_t>(h + offsetof(amd_signal_t, event_id));
+    __hip_atomic_store(gp<uint64_t>(mb), (uint64_t)id, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    fence_release_sys();  // the mailbox store has completed before the message
+    __builtin_amdgcn_s_sendmsg(1 /* interrupt */, __builtin_amdgcn_readfirstlane(id));
+  }
+}
+
+// After publishing ticket t (every lane that published calls this; `lead`
+// is one of them).  The sequentially consistent fence orders this
+// wavefront's READY stores before the sleeper load; a poller counts itself
+// before its last look at the ring, so either it sees the request or the
+// load here sees it counted.
+__device__ __forceinline__ void ring_doorbell(const gsys_dev_ctx& c, uint64_t t, bool lead) {
+  if (!c.doorbell) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "");
+  if (lead && ld_sys(c.sleepers) != 0) raise_doorbell(c.doorbell, t);
+}
 
 // ------------------------------------------------------------ ring protocol
 // Wait until slot t mod D is free for ticket t.  A fresh ring holds
@@ -274,6 +310,7 @@ __device__ inline int64_t call_wi(const gsys_dev_ctx& c, uint16_t nr, const Args
   // every write this wavefront made before the call is visible to the host
   // before the request is
   publish(c, tk.t, nr, fl, n, rank, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+  ring_doorbell(c, tk.t, lane_id() == leader);
   if (out) *out = tk;
   if constexpr (b == B::Blocking) {
     return wave_wait(c, tk, true);
@@ -319,6 +356,7 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
                                    (producer ? GSYS_F_PRODUCER : 0u) | extra_flags |
                                    (GSYS_GRAN_WG << GSYS_F_GRAN_SHIFT));
       publish(c, t, nr, fl, 1, 0, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+      ring_doorbell(c, t, true);
       tk = Ticket{t, 0, 1};
       if constexpr (b == B::Blocking) {
         int e = poll_group(c, t, 1);
@@ -432,6 +470,7 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
                                      (producer ? GSYS_F_PRODUCER : 0u) | extra_flags |
                                      (GSYS_GRAN_KERNEL << GSYS_F_GRAN_SHIFT));
         publish(c, t, nr, fl, 1, 0, a.a[0], a.a[1], a.a[2], a.a[3], a.a[4], a.a[5]);
+        ring_doorbell(c, t, true);
         s_t1 = t + 1;
         s_ret = 0;
       }

@@ -119,6 +119,7 @@ void Pool::start() {
 
 void Pool::stop_and_join() {
   stop_.store(true);
+  if (db_) db_->ring();  // blocked pollers see the stop flag at once
   for (auto& t : threads_)
     if (t.joinable()) t.join();
   threads_.clear();
@@ -714,6 +715,18 @@ void Pool::poller(int idx) {
   uint64_t s = (uint64_t)idx;
   uint64_t done = 0;
   uint64_t idle = 0;
+  uint64_t idle_since = 0;
+  bool woken = false;  // back from the doorbell and nothing found yet
+  // Nothing in this poller's stripe is READY (a peek: nothing is taken).
+  auto stripe_quiet = [&]() {
+    const uint64_t t0 = s * S;
+    for (uint32_t i = 0; i < S; ++i) {
+      if ((done >> i) & 1) continue;
+      const uint64_t t = t0 + i;
+      if (ld_acq(&ring_[t & (D_ - 1)].ctl) == GSYS_CTL(t, GSYS_ST_READY)) return false;
+    }
+    return true;
+  };
   while (!stop_.load(std::memory_order_relaxed)) {
     int n = 0;
     auto scan = [&](void) {
@@ -741,6 +754,7 @@ void Pool::poller(int idx) {
       }
     }
     if (n) {
+      woken = false;
       if (K_ > 1) {
         // requests in ticket order; bundles of at most K
         std::sort(rq.begin(), rq.begin() + n, [](const Req& x, const Req& y) { return x.t < y.t; });
@@ -762,7 +776,32 @@ void Pool::poller(int idx) {
       ++idle;
       st_idle_.fetch_add(1, std::memory_order_relaxed);
       if ((idle & 63) == 0) retire_scan();
-      if (idle < 20000) {
+      if (db_) {
+        if (idle == 1) idle_since = now_ns();
+        // A poller woken for a request of another stripe blocks again at
+        // once; the idle period applies after real work (bursts).
+        if (woken || ((idle & 63) == 0 && now_ns() - idle_since >= db_idle_ns_)) {
+          // Sleep protocol.  Read the doorbell, count this poller as a
+          // sleeper (sequentially consistent), then look at the stripe once
+          // more.  A publisher stores READY, fences, then reads the count:
+          // either it sees this poller counted and raises the doorbell
+          // (changing the value read here), or its READY store came first
+          // and the look below finds the request.
+          retire_scan();
+          const uint64_t seen = db_->value();
+          __atomic_fetch_add(sleepers_, 1, __ATOMIC_SEQ_CST);
+          woken = false;
+          if (stripe_quiet() && !stop_.load(std::memory_order_relaxed)) {
+            db_->wait(seen, db_backstop_ns_);
+            st_sleeps_.fetch_add(1, std::memory_order_relaxed);
+            woken = true;
+          }
+          __atomic_fetch_sub(sleepers_, 1, __ATOMIC_SEQ_CST);
+          idle = 0;
+        } else {
+          _mm_pause();
+        }
+      } else if (idle < 20000) {
         _mm_pause();
       } else {
         timespec ts{0, 20000};
@@ -810,6 +849,7 @@ void Pool::stats(gsys_stats* o, int reset) {
   o->merged = rd(st_merged_);
   o->idle_polls = rd(st_idle_);
   o->service_ns = rd(st_ns_);
+  o->doorbell_sleeps = rd(st_sleeps_);
   for (int i = 0; i < 8; ++i) {
     o->bundle_hist[i] = rd(st_bhist_[i]);
     o->errno_hist[i] = rd(st_ehist_[i]);

@@ -61,6 +61,20 @@ struct BufSlot {
   }
 };
 
+// How an idle poller blocks until the GPU announces new requests (an HSA
+// interrupt signal on a device context, a condition variable in CPU-only
+// contexts).  Every publisher that sees a non-zero sleeper count after its
+// READY store raises the doorbell, which stores a value never stored before.
+class Doorbell {
+ public:
+  virtual ~Doorbell() = default;
+  virtual uint64_t value() = 0;
+  // return once the value differs from `seen` or `timeout_ns` has passed
+  virtual void wait(uint64_t seen, uint64_t timeout_ns) = 0;
+  // raise it from the host (wakes every blocked poller)
+  virtual void ring() = 0;
+};
+
 struct LedgerRec {
   uint64_t ticket, nr, ret, digest, t_start, t_end_poller;  // t_end << 8 | poller
 };
@@ -82,6 +96,15 @@ class Pool {
   int add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id);
   int remove_buffer(uint32_t id);
   void set_arena(uint8_t* base, uint64_t bytes) { arena_ = base; arena_bytes_ = bytes; }
+  // Before start(): idle pollers count themselves in *sleepers (a word the
+  // publishers can read) and block on `db`; `idle_ns` of finding nothing
+  // comes first, `backstop_ns` bounds each block.
+  void set_doorbell(Doorbell* db, uint64_t* sleepers, uint64_t idle_ns, uint64_t backstop_ns) {
+    db_ = db;
+    sleepers_ = sleepers;
+    db_idle_ns_ = idle_ns;
+    db_backstop_ns_ = backstop_ns;
+  }
 
   // servicing
   uint64_t serviced() const { return serviced_.load(std::memory_order_acquire); }
@@ -168,9 +191,13 @@ class Pool {
   uint8_t* arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
 
+  Doorbell* db_ = nullptr;
+  uint64_t* sleepers_ = nullptr;
+  uint64_t db_idle_ns_ = 0, db_backstop_ns_ = 0;
+
   // stats
   std::atomic<uint64_t> st_requests_{0}, st_calls_{0}, st_in_{0}, st_out_{0}, st_err_{0},
-      st_rej_{0}, st_bundles_{0}, st_merged_{0}, st_idle_{0}, st_ns_{0};
+      st_rej_{0}, st_bundles_{0}, st_merged_{0}, st_idle_{0}, st_ns_{0}, st_sleeps_{0};
   std::atomic<uint64_t> st_bhist_[8];
   std::atomic<uint64_t> st_ehist_[8];
 

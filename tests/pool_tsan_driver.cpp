@@ -4,8 +4,11 @@
 // with and without coalescing, while two more threads keep changing the fd
 // table and the registered-buffer table that the pollers read without
 // locks, and a third makes calls into an unregistered range (whose
-// validation scans the whole buffer table).  Every result is checked
-// against the file's bytes.  Exits 0 when
+// validation scans the whole buffer table).  A last phase turns the
+// doorbell on: pollers that find nothing for 20 us block, and a sparse
+// caller keeps arriving around their decision to block (the backstop is
+// raised to 30 s, so a lost wake-up shows as a time-out).  Every result is
+// checked against the file's bytes.  Exits 0 when
 // all checks pass; ThreadSanitizer turns any data race into a non-zero exit.
 //
 // Build: g++ -fsanitize=thread over this file, capi.cpp and host_pool.cpp
@@ -42,6 +45,7 @@ struct Phase {
   const char* name;
   uint32_t threads, group, mode, K, T;
   bool sequential;  // consecutive offsets, so coalesced bundles merge
+  bool doorbell;
 };
 
 int run_phase(const std::string& path, const Phase& ph) {
@@ -52,7 +56,9 @@ int run_phase(const std::string& path, const Phase& ph) {
   cfg.service_threads = 4;
   cfg.coalesce_max = ph.K;
   cfg.coalesce_window_ns = ph.T;
-  cfg.flags = GSYS_CFG_NO_DEVICE | GSYS_CFG_NO_PIN | GSYS_CFG_LEDGER;
+  cfg.flags = GSYS_CFG_NO_DEVICE | GSYS_CFG_NO_PIN | GSYS_CFG_LEDGER |
+              (ph.doorbell ? GSYS_CFG_DOORBELL : 0u);
+  cfg.doorbell_idle_us = 20;
   gsys_ctx* ctx = nullptr;
   if (int e = gsys_init(&cfg, &ctx)) return fail("gsys_init", e);
   const int fd = open(path.c_str(), O_RDONLY);
@@ -97,7 +103,8 @@ int run_phase(const std::string& path, const Phase& ph) {
   // table, the slot being rewritten included, and must fail with -EFAULT
   std::atomic<int> bad{0};
   std::thread prober([&] {
-    while (!done.load()) {
+    for (uint32_t i = 0; !done.load(); ++i) {
+      if (ph.doorbell) usleep(i % 97);  // sparse: the pollers go idle in between
       const uint64_t a[6] = {(uint64_t)fd, 1ull << 47, kItem, 0, 0, 0};
       int64_t r = 0;
       if (gsys_test_raw_call(ctx, GSYS_NR_PREAD64, GSYS_F_BLOCKING, a, &r, 10000000000ull) ||
@@ -114,14 +121,29 @@ int run_phase(const std::string& path, const Phase& ph) {
   if (rc) return fail(ph.name, rc);
   if (bad.load()) return fail("unregistered range not refused");
   if (gsys_wait(ctx, 10000000000ull)) return fail("gsys_wait");
+  if (ph.doorbell) {
+    // calls after pauses long enough for every poller to block
+    for (int i = 0; i < 50; ++i) {
+      usleep(300);
+      const uint64_t a[6] = {(uint64_t)fd, dev, kItem, (uint64_t)i * kItem, 0, 0};
+      int64_t r = 0;
+      if (gsys_test_raw_call(ctx, GSYS_NR_PREAD64, GSYS_F_BLOCKING, a, &r, 10000000000ull) ||
+          r != kItem)
+        return fail("call after a pause", i, (long)r);
+      for (uint32_t b = 0; b < kItem; ++b)
+        if (((const uint8_t*)host)[b] != pattern((uint64_t)i * kItem + b))
+          return fail("byte after a pause", i, (long)b);
+    }
+  }
   const uint8_t* h = (const uint8_t*)host;
-  for (uint64_t k = 0; k < n; ++k) {
+  for (uint64_t k = ph.doorbell ? 1 : 0; k < n; ++k) {  // the pause calls reused buffer 0
     if (rets[k] != kItem) return fail("ret", (long)k, (long)rets[k]);
     for (uint32_t b = 0; b < kItem; ++b)
       if (h[k * kItem + b] != pattern(offs[k] + b)) return fail("byte", (long)k, (long)b);
   }
   gsys_stats st;
   if (gsys_stats_get(ctx, &st, 0)) return fail("stats");
+  if (ph.doorbell && st.doorbell_sleeps == 0) return fail("no poller blocked");
   std::vector<uint64_t> led(6 * (st.claimed + 1));
   const int64_t m = gsys_ledger(ctx, led.data(), st.claimed + 1, 0);
   if ((uint64_t)m != st.claimed) return fail("ledger", (long)m, (long)st.claimed);
@@ -148,12 +170,14 @@ int main(int argc, char** argv) {
     fclose(f);
   }
   const Phase phases[] = {
-      {"wavefront groups, blocking", 6, 64, GSYS_EMU_BLOCKING, 1, 0, false},
-      {"small groups, non-blocking", 6, 8, 0, 1, 0, false},
-      {"list calls, blocking", 4, 16, GSYS_EMU_LIST | GSYS_EMU_BLOCKING, 1, 0, false},
-      {"list calls, non-blocking", 4, 32, GSYS_EMU_LIST, 1, 0, true},
-      {"coalesced bundles", 6, 64, GSYS_EMU_BLOCKING, 8, 2000, true},
+      {"wavefront groups, blocking", 6, 64, GSYS_EMU_BLOCKING, 1, 0, false, false},
+      {"small groups, non-blocking", 6, 8, 0, 1, 0, false, false},
+      {"list calls, blocking", 4, 16, GSYS_EMU_LIST | GSYS_EMU_BLOCKING, 1, 0, false, false},
+      {"list calls, non-blocking", 4, 32, GSYS_EMU_LIST, 1, 0, true, false},
+      {"coalesced bundles", 6, 64, GSYS_EMU_BLOCKING, 8, 2000, true, false},
+      {"doorbell", 4, 8, GSYS_EMU_BLOCKING, 1, 0, false, true},
   };
+  setenv("GSYS_DOORBELL_BACKSTOP_US", "30000000", 1);
   for (const Phase& ph : phases)
     if (int e = run_phase(path, ph)) return e;
   unlink(path.c_str());

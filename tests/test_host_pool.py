@@ -528,3 +528,79 @@ def test_socket_lists_keep_per_datagram_semantics():
         ctx.shutdown()
         srv.close()
         cli.close()
+
+
+def test_doorbell_wakes_blocked_pollers(datafile, monkeypatch):
+    """Idle pollers block on the doorbell; every call after a pause is still
+    served, and woken by the doorbell rather than the backstop: the backstop
+    is raised to 30 s, so one lost wake-up times the call out (5 s)."""
+    import time
+    monkeypatch.setenv("GSYS_DOORBELL_BACKSTOP_US", str(30_000_000))
+    data = np.fromfile(datafile, dtype=np.uint8)
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(flags=g.CFG_DOORBELL, doorbell_idle_us=100)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf = ctx.host_alloc(4096)
+        for i in range(30):
+            time.sleep(0.004)  # every poller has time to block
+            off = (i * 7919 % 1024) * 4096
+            assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 4096, off]) == 4096
+            assert (buf.view(np.uint8)[:4096] == data[off:off + 4096]).all()
+        st = ctx.stats()
+        assert st["doorbell_sleeps"] >= 30
+        assert st["requests"] == 30
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
+
+
+def test_doorbell_races_with_callers(datafile, monkeypatch):
+    """Calls arrive at random moments around the pollers' decision to block
+    (idle threshold 20 us, gaps of 0-300 us), from wavefront-sized groups
+    and single calls; results match the oracle and nothing waits for the
+    30 s backstop."""
+    import time
+    monkeypatch.setenv("GSYS_DOORBELL_BACKSTOP_US", str(30_000_000))
+    rng = np.random.default_rng(7)
+    n_blocks = (4 << 20) // 4096
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(flags=g.CFG_DOORBELL, doorbell_idle_us=20, ring_slots=1024)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        for burst in range(12):
+            offs = synth.sweep_offsets(256, n_blocks, config=10 + burst)
+            want_fnv, want_ret = oracle.pread_fnv(datafile, offs, 4096)
+            group, mode = [(64, g.EMU_BLOCKING), (1, 0), (16, g.EMU_LIST)][burst % 3]
+            buf, rets = _run(ctx, fd, offs, 4, group, mode)
+            assert (rets == want_ret).all()
+            data = buf.view(np.uint8).reshape(len(offs), 4096)
+            got = np.array([oracle.fnv1a64(data[i]) for i in range(len(offs))], dtype=np.uint64)
+            assert (got == want_fnv).all()
+            buf.free()
+            time.sleep(float(rng.uniform(0, 300e-6)))
+        data = np.fromfile(datafile, dtype=np.uint8)
+        one = ctx.host_alloc(4096)
+        for i in range(300):
+            time.sleep(float(rng.uniform(0, 300e-6)))
+            off = int(rng.integers(0, n_blocks)) * 4096
+            assert _raw(ctx, g.NR_PREAD64, [fd, one.dev, 4096, off]) == 4096
+            assert (one.view(np.uint8)[:4096] == data[off:off + 4096]).all()
+        assert ctx.wait(5_000_000_000) == 0
+        assert ctx.stats()["doorbell_sleeps"] > 0
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
+
+
+def test_no_doorbell_no_sleeps(datafile):
+    ctx = _ctx()
+    try:
+        fd = os.open(datafile, os.O_RDONLY)
+        ctx.allow_fd(fd, g.FD_READ)
+        buf = ctx.host_alloc(4096)
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 4096, 0]) == 4096
+        assert ctx.stats()["doorbell_sleeps"] == 0
+        os.close(fd)
+    finally:
+        ctx.shutdown()

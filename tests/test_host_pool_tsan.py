@@ -6,8 +6,9 @@ from host threads while other threads change the fd and buffer tables the
 pollers read without locks.  Built with g++ -fsanitize=thread together with
 capi.cpp and host_pool.cpp, any data race ends the run with exit code 66;
 built with -fsanitize=address,undefined, any invalid access or undefined
-operation does.  The driver also checks every result against the file's
-bytes and the ledger's exactly-once property."""
+operation does.  A last phase runs with the doorbell on, so that pollers
+block and wake while callers keep arriving.  The driver also checks every
+result against the file's bytes and the ledger's exactly-once property."""
 import os
 import shutil
 import subprocess
@@ -30,7 +31,7 @@ def test_pool_under_sanitizer(tmp_path, tmpdata, sanitizer):
            "-I" + os.path.join(ROCM, "include"), "-I" + os.path.join(ROOT, "include"),
            "-I" + CSRC, os.path.join(ROOT, "tests", "pool_tsan_driver.cpp"),
            os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "host_pool.cpp"), "-o", exe,
-           "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-pthread",
+           "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhsa-runtime64", "-pthread",
            "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     b = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     if b.returncode != 0 and ("tsan" in b.stderr or "asan" in b.stderr or "ubsan" in b.stderr):
@@ -40,4 +41,4 @@ def test_pool_under_sanitizer(tmp_path, tmpdata, sanitizer):
                ASAN_OPTIONS="detect_leaks=0 exitcode=66", UBSAN_OPTIONS="exitcode=66")
     r = subprocess.run([exe, tmpdata], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
-    assert r.stdout.count(" ok: ") == 5, r.stdout
+    assert r.stdout.count(" ok: ") == 6, r.stdout
