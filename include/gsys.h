@@ -74,15 +74,17 @@ typedef struct gsys_config {
  * The ring replaces the paper's syscall area (section 5); the polling pool
  * replaces its interrupt + work-queue dispatch (section 3 notes that the
  * design is orthogonal to interrupts versus polling).
- * GSYS_CFG_DOORBELL: the context also creates an HSA interrupt signal.  A
- * poller that has found nothing for a while counts itself in a host-coherent
- * sleeper word, scans once more and blocks on the signal (1 ms at most); a
- * GPU caller that has published a request and sees a non-zero sleeper count
- * adds 1 to the signal, which raises an interrupt and wakes the blocked
- * pollers.  Fences on both sides order the READY store / sleeper load
- * against the sleeper store / last scan, so a request is never left with
- * every poller asleep.  Pollers then cost no CPU while the GPU is quiet, at
- * the price of the interrupt's latency on the first request after a pause.
+ * GSYS_CFG_DOORBELL: the context also creates an HSA interrupt signal and a
+ * relay thread that waits on it.  A poller that has found nothing for
+ * doorbell_idle_us counts itself in a host-coherent sleeper word, looks at
+ * its stripe once more and blocks (50 ms at most, a backstop); a GPU caller
+ * that has published a request and sees a non-zero sleeper count stores a
+ * new value into the signal and raises its interrupt, and the relay wakes
+ * the blocked pollers.  Fences on both sides order the READY store /
+ * sleeper load against the sleeper count / last look, so a request is never
+ * left with its poller asleep.  Pollers then cost no CPU while the GPU is
+ * quiet, at the price of the interrupt's latency (~75 us) on the first
+ * request after a pause.
  * In a GSYS_CFG_NO_DEVICE context the doorbell is a condition variable that
  * the emulated callers (gsys_testing.h) raise the same way.
  * cfg == NULL uses all defaults.  *out receives the context.
