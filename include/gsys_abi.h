@@ -23,7 +23,7 @@
 
 #include <stdint.h>
 
-#define GSYS_ABI_VERSION 1u
+#define GSYS_ABI_VERSION 2u
 
 /* ---- slot states (low 3 bits of ctl) ---- */
 #define GSYS_ST_FREE        0u

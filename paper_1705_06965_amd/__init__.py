@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GSYS_LIB") or os.path.join(_HERE, "libgsys.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 # slot flags / states / call numbers (mirror include/gsys_abi.h)
 ST_FREE, ST_POPULATING, ST_READY, ST_PROCESSING, ST_FINISHED = 0, 1, 2, 3, 4
