@@ -252,10 +252,19 @@ def main():
         dt = time.perf_counter() - t0
         if "persistent" in out and not (of == f).all():
             raise RuntimeError("GPU checksums differ from the oracle")
+        # the same oracle on one thread, over the first eighth of the items
+        n1 = max(1, n // 8)
+        t0 = time.perf_counter()
+        of1, _ = oracle.pread_fnv(path, offs[:n1], ITEM, threads=1)
+        dt1 = time.perf_counter() - t0
+        if "persistent" in out and not (of1 == f[:n1]).all():
+            raise RuntimeError("GPU checksums differ from the oracle")
         cpu = {"value": round(reps * n / dt, 1), "unit": "syscalls/s", "cores": threads,
                "kind": "oracle",
                "sample": "%d full passes of the sweep (%d preads of 4 KiB + FNV-1a each), "
-                         "items split over %d POSIX threads" % (reps, n, threads)}
+                         "items split over %d POSIX threads" % (reps, n, threads),
+               "one_thread": {"value": round(n1 / dt1, 1), "unit": "syscalls/s",
+                              "sample": "the first %d items on one thread" % n1}}
 
     key = "persistent" if "persistent" in out else "plain"
     total, wall, kern_ms, st = out[key]
