@@ -479,6 +479,57 @@ int gsys_permute(gsys_ctx *ctx, int fd, uint64_t in, const uint16_t *sigma, cons
                  uint64_t out_ret, uint32_t cell, void *stream);
 
 /*
+ * Stateful file calls at work-group granularity (read() and write() advance
+ * the file offset; sections 4.1 and 8.1).  Work-group f (grid = nfiles, 256
+ * work-items) issues, one call at a time:
+ *     openat(dirfd, paths + f * GSYS_PATH_MAX, O_WRONLY|O_CREAT|O_TRUNC, 0600)
+ *     write(fd, piece p)        for p = 0 .. K-1, K = ceil(file_bytes / piece)
+ *     close(fd)
+ *     openat(dirfd, path, O_RDONLY)
+ *     read(fd, piece p)         for p = 0 .. K-1, then one 16-byte read at
+ *                               the end of the file (must return 0)
+ *     close(fd)
+ * and counts the bytes read back that differ from what it wrote.  Piece p
+ * of file f is data[f * file_bytes + p * piece ...] (device), at most
+ * `piece` bytes; the work-group copies it into its write area of staging
+ * before the write.  The writes are producers under the ordering of `cell`
+ * (work-group, strong or relaxed, blocking; anything else is -EINVAL); the
+ * other calls are relaxed and blocking.  Outputs (device):
+ *   rets      int64[nfiles][2K + 5], every call's result in the order above;
+ *             a failed openat ends the file's sequence (later entries are
+ *             left as they were)
+ *   mismatch  uint64[nfiles] (zeroed here): bytes read back that differ
+ * staging: registered host buffer of at least nfiles * 2 * A bytes, A =
+ * max(file_bytes, 16) rounded up to 16 (write area, then read area, per
+ * file).  dirfd must be allowed with GSYS_FD_DIR and GSYS_FD_READ |
+ * GSYS_FD_WRITE.  file_bytes <= 2 GiB, K <= 2^20.  Asynchronous on
+ * `stream`.  Errors: -EINVAL, -EFAULT (paths or staging not registered),
+ * -ENODEV.
+ */
+int gsys_file_roundtrip(gsys_ctx *ctx, int dirfd, uint64_t paths, uint32_t nfiles, uint64_t data,
+                        uint64_t file_bytes, uint32_t piece, uint64_t staging,
+                        uint64_t staging_bytes, uint64_t rets, uint64_t mismatch, uint32_t cell,
+                        void *stream);
+
+/*
+ * One stateful call for the whole kernel (kernel granularity, relaxed,
+ * blocking) through `fd`, which the caller opened and allowed.
+ *   nr = GSYS_NR_WRITE: every work-group stores its slice of `data` (device,
+ *        `bytes`) into `staging`; the last work-group to arrive calls
+ *        write(fd, staging, bytes), so the bytes land at the file offset and
+ *        consecutive launches append in launch order.
+ *   nr = GSYS_NR_READ: the first work-group to arrive calls read(fd,
+ *        staging, bytes); every work-group waits for it and counts the bytes
+ *        of its slice that differ from `data`.
+ * ret: device int64[1], the call's result; mismatch: device uint64[1]
+ * (zeroed here).  staging: registered host buffer of `bytes`.  grid: 1 ..
+ * 65535 work-groups of 256.  Errors: -EINVAL, -EFAULT, -ENODEV.
+ */
+int gsys_file_kernel_io(gsys_ctx *ctx, int fd, uint32_t nr, uint64_t data, uint64_t bytes,
+                        uint64_t staging, uint64_t ret, uint64_t mismatch, uint32_t grid,
+                        void *stream);
+
+/*
  * Kernel-split baseline (section 2, Fig. 1 left): no GPU system calls.  The
  * host has already read every item into `staging` (any device-readable
  * address: registered host memory or HBM); one kernel computes

@@ -47,6 +47,10 @@ def lib() -> C.CDLL:
         L.oracle_wordcount.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                        C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p,
                                        C.c_int]
+        L.oracle_file_roundtrip.restype = C.c_int
+        L.oracle_file_roundtrip.argtypes = [C.c_int, C.c_void_p, C.c_uint32, C.c_uint32,
+                                            C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p,
+                                            C.c_void_p, C.c_int]
         L.oracle_kv_build.restype = C.c_void_p
         L.oracle_kv_build.argtypes = [C.c_void_p, C.c_uint64]
         L.oracle_kv_free.restype = None
@@ -158,6 +162,28 @@ def wordcount_open(directory: str, names, queries, chunk: int = 1 << 20, threads
     if rc:
         raise OSError(-rc, "oracle_wordcount_open")
     return counts, rets
+
+
+def file_roundtrip(directory: str, names, data: np.ndarray, piece: int, threads: int = 1):
+    """(rets[f, 2K + 5], back[f, file_bytes]): each file created beneath
+    `directory`, written with write() in `piece`-byte pieces, closed, opened
+    read-only, read back with read() in the same pieces plus a 16-byte read at
+    the end, closed.  `data` is nfiles x file_bytes."""
+    data = np.ascontiguousarray(data, dtype=np.uint8).reshape(len(names), -1)
+    fb = data.shape[1]
+    k = (fb + piece - 1) // piece
+    paths = pack_paths(names)
+    rets = np.zeros((len(names), 2 * k + 5), dtype=np.int64)
+    back = np.zeros_like(data)
+    dfd = os.open(directory, os.O_RDONLY | os.O_DIRECTORY)
+    try:
+        rc = lib().oracle_file_roundtrip(dfd, _p(paths), len(names), paths.shape[1], _p(data), fb,
+                                         piece, _p(rets), _p(back), threads)
+    finally:
+        os.close(dfd)
+    if rc:
+        raise OSError(-rc, "oracle_file_roundtrip")
+    return rets, back
 
 
 class KVIndex:

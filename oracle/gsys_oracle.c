@@ -25,7 +25,9 @@
  *   - key-value GET replies in the style of the UDP server case study
  *     (section 7.3), with a sorted key index and bsearch;
  *   - memory release with madvise(MADV_DONTNEED) in the style of section 7.2;
- *   - the block permutation written out with pwrite of section 6 (Fig. 6).
+ *   - the block permutation written out with pwrite of section 6 (Fig. 6);
+ *   - a file written with write() and read back with read() (stateful
+ *     calls whose results follow the file offset).
  *
  * Pins (tests/test_oracle_pins.py): published FNV-1a test vectors; slicing of
  * the file bytes for every (offset, length) pair on tiny files including EOF;
@@ -271,6 +273,86 @@ int oracle_wordcount_open(int dirfd, const char *paths, uint32_t nfiles, uint32_
                                   (uint32_t)((uint64_t)nfiles * (t + 1) / threads),
                                   nq, qstride, qbytes, qlen, counts, rets};
         if (pthread_create(&tid[t], NULL, wo_worker, &jobs[t]) != 0) return -EAGAIN;
+    }
+    for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    return 0;
+}
+
+/* ---------------------------------------------- stateful write / read back */
+/*
+ * File round trip with calls whose effect depends on the file offset
+ * (read() and write() advance it; section 4.1 and section 8.1 discuss such
+ * order-dependent calls): file f is opened beneath dirfd by name, created and
+ * truncated, written in `piece`-byte pieces with write(), closed, opened
+ * read-only, read back in the same pieces with read() plus one read of 16
+ * bytes at the end of the file, and closed.  rets[f * (2K + 5) + i] records
+ * every call's result in that order (K = pieces per file); a failed openat
+ * ends the file's sequence.  back receives the bytes read (nfiles x
+ * file_bytes).  Calls run one at a time per file, files on `threads`
+ * threads.
+ */
+struct rt_job {
+    int dirfd;
+    const char *paths;
+    uint32_t stride, piece, f0, f1;
+    const uint8_t *data;
+    uint64_t file_bytes;
+    int64_t *rets;
+    uint8_t *back;
+};
+
+static int64_t sysret(int64_t r) { return r < 0 ? -(int64_t)errno : r; }
+
+static void *rt_worker(void *arg)
+{
+    struct rt_job *j = (struct rt_job *)arg;
+    const uint64_t k = (j->file_bytes + j->piece - 1) / j->piece;
+    for (uint32_t f = j->f0; f < j->f1; f++) {
+        int64_t *r = j->rets + (uint64_t)f * (2 * k + 5);
+        const char *path = j->paths + (uint64_t)f * j->stride;
+        const uint8_t *src = j->data + (uint64_t)f * j->file_bytes;
+        uint8_t *dst = j->back + (uint64_t)f * j->file_bytes;
+        uint64_t i = 0;
+        int fd = openat(j->dirfd, path, O_WRONLY | O_CREAT | O_TRUNC | O_CLOEXEC, 0600);
+        r[i++] = sysret(fd);
+        if (fd < 0) continue;
+        for (uint64_t p = 0; p < k; p++) {
+            uint64_t off = p * j->piece, n = j->file_bytes - off;
+            if (n > j->piece) n = j->piece;
+            r[i++] = sysret(write(fd, src + off, n));
+        }
+        r[i++] = sysret(close(fd));
+        fd = openat(j->dirfd, path, O_RDONLY | O_CLOEXEC);
+        r[i++] = sysret(fd);
+        if (fd < 0) continue;
+        for (uint64_t p = 0; p < k; p++) {
+            uint64_t off = p * j->piece, n = j->file_bytes - off;
+            if (n > j->piece) n = j->piece;
+            r[i++] = sysret(read(fd, dst + off, n));
+        }
+        uint8_t tail[16];
+        r[i++] = sysret(read(fd, tail, sizeof tail));
+        r[i++] = sysret(close(fd));
+    }
+    return NULL;
+}
+
+int oracle_file_roundtrip(int dirfd, const char *paths, uint32_t nfiles, uint32_t stride,
+                          const uint8_t *data, uint64_t file_bytes, uint32_t piece,
+                          int64_t *rets, uint8_t *back, int threads)
+{
+    if (!piece) return -EINVAL;
+    if (threads < 1) threads = 1;
+    if ((uint32_t)threads > nfiles) threads = nfiles ? (int)nfiles : 1;
+    if (threads > 256) threads = 256;
+    pthread_t tid[256];
+    struct rt_job jobs[256];
+    for (int t = 0; t < threads; t++) {
+        jobs[t] = (struct rt_job){dirfd, paths, stride, piece,
+                                  (uint32_t)((uint64_t)nfiles * t / threads),
+                                  (uint32_t)((uint64_t)nfiles * (t + 1) / threads),
+                                  data, file_bytes, rets, back};
+        if (pthread_create(&tid[t], NULL, rt_worker, &jobs[t]) != 0) return -EAGAIN;
     }
     for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
     return 0;

@@ -133,6 +133,11 @@ _SIGS = {
                                       C.c_uint32, C.c_uint64, C.c_uint64, _P]),
     "gsys_permute": (C.c_int, [_P, C.c_int, C.c_uint64, _P, _P, C.c_uint64, C.c_uint32,
                                C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P]),
+    "gsys_file_roundtrip": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
+                                      C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
+                                      C.c_uint64, C.c_uint64, C.c_uint32, _P]),
+    "gsys_file_kernel_io": (C.c_int, [_P, C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
+                                      C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P]),
     "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                                     C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),

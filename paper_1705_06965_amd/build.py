@@ -17,7 +17,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = os.environ.get("GSYS_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["k_fnv.hip", "k_wordscan.hip", "k_kv.hip", "k_serve.hip", "k_canary.hip",
-               "k_permute.hip"]
+               "k_permute.hip", "k_fileio.hip"]
 HOST_HIP_SOURCES = ["capi.cpp"]      # host code that calls the HIP runtime
 HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp"]     # plain C++17 + POSIX
 

@@ -324,3 +324,40 @@ def test_wordcount_open_missing_file_and_subdirectory(tmpdata):
     counts, rets = oracle.wordcount_open(d, ["s/a.txt", "nope.txt"], [b"x", b"y"])
     assert rets.tolist() == [5, -errno.ENOENT]
     assert counts.tolist() == [[2, 1], [0, 0]]
+
+
+@pytest.mark.parametrize("fb,piece", [(0, 4096), (1, 4096), (15, 7), (4096, 4096), (4097, 4096),
+                                      (100_000, 1000), (65_537, 1 << 20)])
+def test_file_roundtrip_vs_closed_form(tmpdata, fb, piece):
+    """Every write and read returns its piece's length (min(piece, fb - p *
+    piece)), the read at the end returns 0, both closes 0; the file holds the
+    bytes in piece order (read with Python's own file API) and the read-back
+    equals them."""
+    d = os.path.join(tmpdata, "rt_%d_%d" % (fb, piece))
+    os.makedirs(d, exist_ok=True)
+    names = ["f%d.bin" % i for i in range(5)]
+    data = np.random.default_rng([fb, piece]).integers(0, 256, (len(names), fb), dtype=np.uint8)
+    rets, back = oracle.file_roundtrip(d, names, data, piece, threads=3)
+    k = (fb + piece - 1) // piece
+    lens = [min(piece, fb - p * piece) for p in range(k)]
+    for f, n in enumerate(names):
+        r = rets[f].tolist()
+        assert r[0] >= 0 and r[k + 2] >= 0                       # the two openat
+        assert r[1:k + 1] == lens and r[k + 1] == 0              # writes, close
+        assert r[k + 3:2 * k + 3] == lens                        # reads
+        assert r[2 * k + 3] == 0 and r[2 * k + 4] == 0           # end of file, close
+        with open(os.path.join(d, n), "rb") as fh:
+            assert fh.read() == data[f].tobytes()
+        assert (back[f] == data[f]).all()
+
+
+def test_file_roundtrip_failed_openat_ends_the_sequence(tmpdata):
+    """A name in a missing subdirectory: openat fails with -ENOENT and no
+    later call is made for that file (its entries keep their initial 0)."""
+    d = os.path.join(tmpdata, "rt_missing")
+    os.makedirs(d, exist_ok=True)
+    data = np.full((2, 100), 7, dtype=np.uint8)
+    rets, back = oracle.file_roundtrip(d, ["ok.bin", "nodir/x.bin"], data, 64)
+    assert rets[1, 0] == -errno.ENOENT and not rets[1, 1:].any()
+    assert rets[0, 0] >= 0 and rets[0, 1:3].tolist() == [64, 36]
+    assert (back[0] == 7).all() and not back[1].any()
