@@ -62,7 +62,7 @@ def parse():
                     help="permute: permutation rounds per block before the pwrite")
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "tiny", "wordscan", "kv", "serve", "permute",
-                             "granularity", "coalesce", "wordopen", "doorbell"],
+                             "granularity", "coalesce", "wordopen", "doorbell", "fileio"],
                     help="sweep: the pread microbenchmark sweep (headline); wordscan: the "
                          "word search over 2,000 files")
     ap.add_argument("--db-gap-us", type=int, default=2000,
@@ -144,6 +144,8 @@ def main():
         return run_granularity(args)
     if args.workload == "doorbell":
         return run_doorbell(args)
+    if args.workload == "fileio":
+        return run_fileio(args)
     if args.workload == "coalesce":
         return run_coalesce(args)
     import synth
@@ -1298,6 +1300,125 @@ def run_doorbell(args):
         "modes": modes,
     }
     print(json.dumps(res_j), flush=True)
+
+
+def run_fileio(args):
+    """Stateful file calls from the GPU.  Work-group round trip: 64
+    work-groups each create a 4 MiB file on tmpfs, write it with write() in
+    1 MiB pieces (strong), close it, reopen it, read it back in 1 MiB pieces
+    plus an end-of-file read, close it and compare; one step = one launch
+    (640 calls, 512 MiB moved each way).  value = bytes written + read per
+    second.  Kernel granularity: 64 launches each appending 1 MiB through one
+    descriptor with one kernel-wide write(), then 64 launches consuming it
+    with one kernel-wide read(); per-launch latency."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.fileio import FileRoundtrip, kernel_io
+    nf, fb, piece = 64, 4 << 20, 1 << 20
+    base = os.path.join(synth.data_dir(), "fileio")
+    d = os.path.join(base, "gpu")
+    os.makedirs(d, exist_ok=True)
+    names = ["f%02d.bin" % i for i in range(nf)]
+    data = np.random.default_rng(170506965).integers(0, 256, (nf, fb), dtype=np.uint8)
+    ctx = g.Context(ring_slots=1 << 12, service_threads=max(0, args.service_threads),
+                    device_timeout_ns=60_000_000_000, flags=g.CFG_LEDGER)
+    r = FileRoundtrip(ctx, d, names)
+    k = fb // piece
+    steps = max(1, args.steps)
+    ts = []
+    r.prepare(data, piece)
+    for st in range(args.warmup + steps):
+        r.rets.fill_(-12345)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.launch("strong")
+        torch.cuda.synchronize()
+        if ctx.wait(60_000_000_000):
+            raise RuntimeError("drain failed")
+        dt = time.perf_counter() - t0
+        rets, mism, back = r.finish()
+        if mism.any() or not (rets[:, 1:k + 1] == piece).all() or \
+                not (rets[:, k + 3:2 * k + 3] == piece).all() or rets[:, 2 * k + 3].any():
+            raise RuntimeError("file round trip differs from the expected results")
+        if st >= args.warmup:
+            ts.append(dt)
+    with open(os.path.join(d, names[-1]), "rb") as fh:
+        if fh.read() != data[-1].tobytes():
+            raise RuntimeError("file contents differ from the data")
+    led = ctx.ledger(reset=True)
+    svc = ((led[:, 5] >> np.uint64(8)).astype(np.int64) - led[:, 4].astype(np.int64)) / 1e3
+    by_nr = {}
+    for nr, nm in ((g.NR_WRITE, "write"), (g.NR_READ, "read"), (g.NR_OPENAT, "openat"),
+                   (g.NR_CLOSE, "close")):
+        m = led[:, 1] == nr
+        if m.any():
+            by_nr[nm] = round(float(np.median(svc[m])), 1)
+    r.close()
+    med = float(np.median(ts))
+    # kernel granularity: append then consume through one description
+    p = os.path.join(base, "append.bin")
+    part = np.random.default_rng(5).integers(0, 256, 1 << 20, dtype=np.uint8)
+    stg = ctx.host_alloc(1 << 20)
+    wfd = os.open(p, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o600)
+    ctx.allow_fd(wfd, g.FD_WRITE)
+    lw = []
+    for _ in range(64):
+        t0 = time.perf_counter()
+        ret, mm = kernel_io(ctx, wfd, g.NR_WRITE, part, grid=64, staging=stg)
+        lw.append((time.perf_counter() - t0) * 1e6)
+        if ret != len(part):
+            raise RuntimeError("kernel-granularity write returned %d" % ret)
+    ctx.allow_fd(wfd, 0)
+    os.close(wfd)
+    rfd = os.open(p, os.O_RDONLY)
+    ctx.allow_fd(rfd, g.FD_READ)
+    lr = []
+    for _ in range(64):
+        t0 = time.perf_counter()
+        ret, mm = kernel_io(ctx, rfd, g.NR_READ, part, grid=64, staging=stg)
+        lr.append((time.perf_counter() - t0) * 1e6)
+        if ret != len(part) or mm:
+            raise RuntimeError("kernel-granularity read returned %d (%d differ)" % (ret, mm))
+    ctx.allow_fd(rfd, 0)
+    os.close(rfd)
+    stg.free()
+    ctx.shutdown()
+    cpu = None
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0))
+        dc = os.path.join(base, "cpu")
+        os.makedirs(dc, exist_ok=True)
+        tc = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.file_roundtrip(dc, names, data, piece, threads=threads)
+            tc.append(time.perf_counter() - t0)
+        cpu = {"value": round(2 * nf * fb / float(np.median(tc)) / 1e9, 3), "unit": "GB/s",
+               "cores": threads, "kind": "oracle",
+               "sample": "the same 64-file round trip issued by the oracle on %d threads, "
+                         "median of 3" % threads}
+    res = {
+        "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
+        "value": round(2 * nf * fb / med / 1e9, 3), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * med, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "stateful file round trip: 64 work-groups x (openat create, 4 x "
+                               "1 MiB write, close, openat, 4 x 1 MiB read + end-of-file read, "
+                               "close) on tmpfs, strong blocking work-group calls",
+                   "form": "plain"},
+        "calls_per_s": round(nf * (2 * k + 5) / med, 1),
+        "host_service_us_median": by_nr,
+        "kernel_append_1mib_us": {"p50": round(float(np.percentile(lw, 50)), 1),
+                                  "p99": round(float(np.percentile(lw, 99)), 1)},
+        "kernel_consume_1mib_us": {"p50": round(float(np.percentile(lr, 50)), 1),
+                                   "p99": round(float(np.percentile(lr, 99)), 1)},
+    }
+    if cpu:
+        res["cpu_baseline"] = cpu
+    print(json.dumps(res), flush=True)
 
 if __name__ == "__main__":
     main()

@@ -36,37 +36,50 @@ class FileRoundtrip:
     def area(file_bytes: int) -> int:
         return (max(file_bytes, 16) + 15) // 16 * 16
 
-    def run(self, data: np.ndarray, piece: int, o: str = "strong", stream=None):
-        """(rets[f, 2K + 5], mismatch[f], read areas[f, file_bytes]) for data
-        of shape (nfiles, file_bytes)."""
+    def prepare(self, data: np.ndarray, piece: int):
+        """Upload data of shape (nfiles, file_bytes), size and clear staging."""
         torch = self.torch
         data = np.ascontiguousarray(data, dtype=np.uint8).reshape(self.nfiles, -1)
-        fb = data.shape[1]
-        k = (fb + piece - 1) // piece
-        a = self.area(fb)
-        need = max(1, self.nfiles) * 2 * a
+        self.fb = fb = data.shape[1]
+        self.piece = piece
+        self.k = (fb + piece - 1) // piece
+        self.a = a = self.area(fb)
+        self.need = need = max(1, self.nfiles) * 2 * a
         if self.staging is None or self.staging.nbytes < need:
             if self.staging is not None:
                 self.staging.free()
             self.staging = self.ctx.host_alloc(need)
         self.staging.array[:need] = 0
-        d = torch.from_numpy(data.reshape(-1).copy()).to(self.device) if fb else \
+        self.d = torch.from_numpy(data.reshape(-1).copy()).to(self.device) if fb else \
             torch.zeros(1, dtype=torch.uint8, device=self.device)
-        rets = torch.full((max(1, self.nfiles), 2 * k + 5), -12345, dtype=torch.int64,
-                          device=self.device)
-        mism = torch.zeros(max(1, self.nfiles), dtype=torch.int64, device=self.device)
+        self.rets = torch.full((max(1, self.nfiles), 2 * self.k + 5), -12345, dtype=torch.int64,
+                               device=self.device)
+        self.mism = torch.zeros(max(1, self.nfiles), dtype=torch.int64, device=self.device)
+
+    def launch(self, o: str = "strong", stream=None):
         check(lib.gsys_file_roundtrip(self.ctx.h, self.dirfd, self.paths.dev, self.nfiles,
-                                      d.data_ptr(), fb, piece, self.staging.dev, need,
-                                      rets.data_ptr(), mism.data_ptr(),
+                                      self.d.data_ptr(), self.fb, self.piece, self.staging.dev,
+                                      self.need, self.rets.data_ptr(), self.mism.data_ptr(),
                                       cell_code("WG", o, "block"), _stream(stream)),
               "gsys_file_roundtrip")
-        torch.cuda.synchronize()
+
+    def finish(self):
+        """Wait for the GPU and the host pool; (rets[f, 2K + 5], mismatch[f],
+        read areas[f, file_bytes])."""
+        self.torch.cuda.synchronize()
         rc = self.ctx.wait(60_000_000_000)
         if rc:
             raise RuntimeError("drain failed: %d" % rc)
-        back = self.staging.array[:need].reshape(max(1, self.nfiles), 2 * a)[:self.nfiles, a:a + fb]
-        return (rets.cpu().numpy()[:self.nfiles].copy(), mism.cpu().numpy()[:self.nfiles].copy(),
-                back.copy())
+        n, a, fb = max(1, self.nfiles), self.a, self.fb
+        back = self.staging.array[:self.need].reshape(n, 2 * a)[:self.nfiles, a:a + fb]
+        return (self.rets.cpu().numpy()[:self.nfiles].copy(),
+                self.mism.cpu().numpy()[:self.nfiles].copy(), back.copy())
+
+    def run(self, data: np.ndarray, piece: int, o: str = "strong", stream=None):
+        """prepare + launch + finish."""
+        self.prepare(data, piece)
+        self.launch(o, stream)
+        return self.finish()
 
     def close(self):
         self.ctx.allow_fd(self.dirfd, 0)
