@@ -106,6 +106,10 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
   for (auto& p : fdperm_) p.store(0);
   for (auto& g : fdgen_) g.store(0);
   copy_fds_ = !(cfg.flags & GSYS_CFG_SHARED_FDS);
+  {
+    const char* e = getenv("GSYS_ARENA_HUGEPAGE");
+    arena_huge_ = !(e && *e == '0');
+  }
   fdcopies_.resize((size_t)P_);
 }
 
@@ -339,7 +343,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       // Arena policy: back 2 MiB-aligned ranges with transparent huge pages
       // where the kernel allows it (one fault per 2 MiB instead of 512).  A
       // hint only: contents and the call's result are unchanged.
-      if (((uint64_t)m & ((2ull << 20) - 1)) == 0 && len >= (2ull << 20))
+      if (arena_huge_ && ((uint64_t)m & ((2ull << 20) - 1)) == 0 && len >= (2ull << 20))
         madvise(m, len, MADV_HUGEPAGE);
       return (int64_t)(uint64_t)m;
     }

@@ -190,6 +190,7 @@ class Pool {
 
   uint8_t* arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
+  bool arena_huge_ = true;  // hint MADV_HUGEPAGE on 2 MiB-aligned arena mappings
 
   Doorbell* db_ = nullptr;
   uint64_t* sleepers_ = nullptr;

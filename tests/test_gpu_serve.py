@@ -153,3 +153,31 @@ def test_release_readback_matches_oracle_release_job(gs, mix, tmpdata):
     b = np.fromfile(out_o, dtype=np.uint8)
     lo = int(sr.jobs_np["off"].min())
     assert (a[lo:] == b[lo:]).all()
+
+
+@pytest.mark.parametrize("form", ["persistent", "plain"])
+def test_split_scans_match_oracle(gs, tmpdata, form):
+    """Scans up to 32 MiB: the persistent form cuts every scan longer than
+    its task size (4 MiB here, 16 MiB by default) into tasks run by
+    different work-groups (up to 8 per job); digests and return values must
+    equal the oracle's, as in the plain form (one work-group per job)."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    in_path = synth.random_file(6, 64 << 20, name="c6_in_64m.bin")
+    js = synth.job_stream(n_jobs=90, rate_per_s=5000, mix=(0.7, 0.2, 0.1),
+                          scan_file_bytes=64 << 20, scan_max_log2_pages=13,
+                          pwrite_max_pages=16, arena_blocks=64, config=6)
+    big = int(((js.kind == 0) & (js.arg_len > (4 << 20))).sum())
+    assert big >= 10
+    out_path = os.path.join(tmpdata, "serve_split_%s.bin" % form)
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("split scans", form, "big", big)
+    os.environ["GSYS_SERVE_SPLIT_MIB"] = "4"
+    try:
+        res, dig, lat = sr.run(g.PERSISTENT if form == "persistent" else g.PLAIN, max_inflight=32,
+                               staging_bytes=(2 << 20) * 64)
+    finally:
+        del os.environ["GSYS_SERVE_SPLIT_MIB"]
+    n_scan, n_pw, n_rel = check_outputs(sr, js, res, dig, in_path, out_path, "split-" + form)
+    assert n_scan == int((js.kind == 0).sum()) and n_pw + n_rel == len(js.kind) - n_scan
+    sr.close()
