@@ -394,9 +394,14 @@ typedef struct gsys_job {
  * madvise(MADV_DONTNEED), pwrite the first 64 bytes of page 0 to off + 64
  * (zeros) and munmap.  All calls are work-group granularity, relaxed.
  *
- *   form      GSYS_PERSISTENT: resident work-groups claim jobs as they are
- *             posted; GSYS_PLAIN: one single-work-group launch per job on
- *             `stream`, in arrival order
+ *   form      GSYS_PERSISTENT: resident work-groups claim tasks in job order
+ *             as jobs are posted; a scan longer than 16 MiB (environment
+ *             GSYS_SERVE_SPLIT_MIB overrides the size, 0 = never split) is
+ *             cut into tasks of that size run by different work-groups, and
+ *             the work-group finishing its last task publishes the job
+ *             (result: bytes read, or the first -errno of any task);
+ *             GSYS_PLAIN: one single-work-group launch per job on `stream`,
+ *             in arrival order
  *   jobs_dev / jobs_host: the same gsys_job[n] in a registered host buffer
  *             (filled by the caller; done / result are written here)
  *   staging   registered host buffer, 2 MiB per work-group (the persistent
