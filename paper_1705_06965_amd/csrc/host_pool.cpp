@@ -106,6 +106,8 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
   for (auto& p : fdperm_) p.store(0);
   for (auto& g : fdgen_) g.store(0);
   copy_fds_ = !(cfg.flags & GSYS_CFG_SHARED_FDS);
+  owned_ = std::vector<std::atomic<uint64_t>>((size_t)P_);
+  for (int i = 0; i < P_; ++i) owned_[(size_t)i].store((uint64_t)i);
   {
     const char* e = getenv("GSYS_ARENA_HUGEPAGE");
     arena_huge_ = !(e && *e == '0');
@@ -703,6 +705,14 @@ void Pool::retire_scan() {
   retire_busy_.clear(std::memory_order_release);
 }
 
+// Ticket t's request was taken by a poller (PROCESSING / FINISHED for this
+// lap) or has already been freed for a later lap.
+static inline bool taken(uint64_t c, uint64_t t) {
+  const uint64_t ct = GSYS_CTL_TICKET(c);
+  const uint32_t st = GSYS_CTL_STATE(c);
+  return ct > t || (ct == t && (st == GSYS_ST_PROCESSING || st == GSYS_ST_FINISHED));
+}
+
 void Pool::poller(int idx) {
   tls_copies_ = &fdcopies_[(size_t)idx];
   if (pin_) {
@@ -731,16 +741,45 @@ void Pool::poller(int idx) {
     }
     return true;
   };
+  // without coalescing one request at a time, leaving the rest to thieves
+  const int limit = K_ > 1 ? (int)S : 1;
+  // Serve one READY request of another poller's stripe or of one of the next
+  // two unowned stripes; false if there is none.
+  auto steal = [&]() {
+    auto try_stripe = [&](uint64_t st) {
+      if (st == s) return false;
+      for (uint32_t i = 0; i < S; ++i) {
+        const uint64_t t = st * S + i;
+        gsys_slot* sl = &ring_[t & (D_ - 1)];
+        uint64_t c = ld_acq(&sl->ctl);
+        if (c != GSYS_CTL(t, GSYS_ST_READY)) continue;
+        if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, GSYS_ST_PROCESSING), false,
+                                        __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+          Req r{t, sl};
+          serve_bundle(&r, 1, idx);
+          return true;
+        }
+      }
+      return false;
+    };
+    for (int p = 0; p < P_; ++p)
+      if (p != idx && try_stripe(owned_[(size_t)p].load(std::memory_order_relaxed))) return true;
+    const uint64_t nx = next_stripe_.load(std::memory_order_relaxed);
+    return try_stripe(nx) || try_stripe(nx + 1);
+  };
   while (!stop_.load(std::memory_order_relaxed)) {
     int n = 0;
     auto scan = [&](void) {
       const uint64_t t0 = s * S;
-      for (uint32_t i = 0; i < S && n < (int)S; ++i) {
+      for (uint32_t i = 0; i < S && n < limit; ++i) {
         if ((done >> i) & 1) continue;
         const uint64_t t = t0 + i;
         gsys_slot* sl = &ring_[t & (D_ - 1)];
         uint64_t c = ld_acq(&sl->ctl);
-        if (c != GSYS_CTL(t, GSYS_ST_READY)) continue;
+        if (c != GSYS_CTL(t, GSYS_ST_READY)) {
+          if (taken(c, t)) done |= 1ull << i;  // served by another poller
+          continue;
+        }
         if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, GSYS_ST_PROCESSING), false,
                                         __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
           rq[n++] = Req{t, sl};
@@ -773,6 +812,7 @@ void Pool::poller(int idx) {
       // the next unowned stripe goes to whichever poller finishes first, so
       // long requests (group calls) spread evenly over the pool
       s = next_stripe_.fetch_add(1, std::memory_order_relaxed);
+      owned_[(size_t)idx].store(s, std::memory_order_relaxed);
       done = 0;
       continue;
     }
@@ -780,6 +820,11 @@ void Pool::poller(int idx) {
       ++idle;
       st_idle_.fetch_add(1, std::memory_order_relaxed);
       if ((idle & 63) == 0) retire_scan();
+      if ((idle & 15) == 0 && steal()) {
+        woken = false;
+        idle = 0;
+        continue;
+      }
       if (db_) {
         if (idle == 1) idle_since = now_ns();
         // A poller woken for a request of another stripe blocks again at

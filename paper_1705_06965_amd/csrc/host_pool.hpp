@@ -16,6 +16,13 @@
 // Exactly-once: a poller takes a request only by compare-and-swap of the
 // slot's control word from READY to PROCESSING (section 5).
 //
+// Work stealing: without coalescing an owner takes one request of its stripe
+// at a time, and a poller with nothing ready in its own stripe serves a READY
+// request from another poller's stripe (or from the next unowned stripes),
+// so a short call never waits behind the long calls ahead of it in one
+// stripe.  An owner counts a request of its stripe that is no longer READY
+// for this lap (PROCESSING, FINISHED or freed) as done.
+//
 // Coalescing (section 4.2, section 5): with K > 1 a poller that finds a ready
 // request waits up to T ns for more ready requests of its stripe, up to K,
 // and executes them as one bundle, folding transfers that are adjacent both
@@ -152,6 +159,7 @@ class Pool {
   std::atomic<bool> stop_{false};
   std::atomic<uint64_t> serviced_{0};
   std::atomic<uint64_t> next_stripe_{0};  // stripes are taken in order by whichever poller is free
+  std::vector<std::atomic<uint64_t>> owned_;  // each poller's current stripe (for stealing)
   std::atomic_flag retire_busy_ = ATOMIC_FLAG_INIT;
 
   std::vector<std::atomic<uint8_t>> fdperm_;

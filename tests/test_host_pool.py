@@ -604,3 +604,47 @@ def test_no_doorbell_no_sleeps(datafile):
         os.close(fd)
     finally:
         ctx.shutdown()
+
+
+def test_idle_pollers_take_requests_from_a_busy_stripe(tmpdata):
+    """Ticket 0 is a 256 MiB pread that keeps the owner of stripe 0 busy; the
+    7 small preads that follow it in the same stripe (tickets 1..7) are
+    served by the other, idle pollers long before it ends."""
+    import threading
+    import time
+    p = os.path.join(tmpdata, "big_256m.bin")
+    with open(p, "wb") as f:
+        f.write(np.random.default_rng(3).integers(0, 256, 256 << 20, dtype=np.uint8).tobytes())
+    fd = os.open(p, os.O_RDONLY)
+    ctx = _ctx(service_threads=4, ring_slots=64)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        big = ctx.host_alloc(256 << 20)
+        small = ctx.host_alloc(7 * 4096)
+        t_big = []
+
+        def big_call():
+            t0 = time.perf_counter()
+            assert _raw(ctx, g.NR_PREAD64, [fd, big.dev, 256 << 20, 0]) == 256 << 20
+            t_big.append(time.perf_counter() - t0)
+
+        th = threading.Thread(target=big_call)
+        th.start()
+        time.sleep(0.002)  # ticket 0 is in service
+        t_small = []
+        for i in range(7):
+            t0 = time.perf_counter()
+            assert _raw(ctx, g.NR_PREAD64, [fd, small.dev + 4096 * i, 4096, 4096 * (i + 1)]) == 4096
+            t_small.append(time.perf_counter() - t0)
+        th.join()
+        assert max(t_small) < t_big[0] / 4, (t_small, t_big)
+        led = ctx.ledger()
+        assert sorted(led[:, 0].tolist()) == list(range(8))
+        owner = int(led[led[:, 0] == 0][0, 5]) & 0xff
+        thieves = {int(x) & 0xff for x in led[led[:, 0] > 0][:, 5]}
+        assert owner not in thieves
+        data = np.fromfile(p, dtype=np.uint8, count=8 * 4096)
+        assert (small.view(np.uint8)[:7 * 4096] == data[4096:8 * 4096]).all()
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
