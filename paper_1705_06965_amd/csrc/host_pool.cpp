@@ -820,7 +820,7 @@ void Pool::poller(int idx) {
       ++idle;
       st_idle_.fetch_add(1, std::memory_order_relaxed);
       if ((idle & 63) == 0) retire_scan();
-      if ((idle & 15) == 0 && steal()) {
+      if ((idle & 255) == 0 && steal()) {
         woken = false;
         idle = 0;
         continue;
