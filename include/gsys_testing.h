@@ -52,6 +52,14 @@ int64_t gsys_test_claim_only(gsys_ctx *ctx, uint32_t n);
 /* Read-only view of the ring for quiescence checks: copies D control words. */
 int gsys_test_ring_ctl(gsys_ctx *ctx, uint64_t *out, uint64_t max);
 
+/*
+ * Fault injection: the next `count` single (non-list) requests with call
+ * number `nr` are answered with -err instead of being executed (any
+ * context, device or CPU-only).  count 0 clears it.  Used to check that a
+ * caller sees exactly the -errno the host produced.  Returns 0 or -EINVAL.
+ */
+int gsys_test_inject(gsys_ctx *ctx, uint16_t nr, int32_t err, uint32_t count);
+
 #ifdef __cplusplus
 }
 #endif

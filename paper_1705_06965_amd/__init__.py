@@ -143,6 +143,7 @@ _SIGS = {
     "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),
     "gsys_test_claim_only": (C.c_int64, [_P, C.c_uint32]),
     "gsys_test_ring_ctl": (C.c_int, [_P, _P, C.c_uint64]),
+    "gsys_test_inject": (C.c_int, [_P, C.c_uint16, C.c_int32, C.c_uint32]),
 }
 
 if not os.path.exists(LIB_PATH):

@@ -707,6 +707,12 @@ int64_t gsys_test_claim_only(gsys_ctx* c, uint32_t n) {
   return (int64_t)__atomic_fetch_add(&c->host_words[32], (uint64_t)n, __ATOMIC_ACQ_REL);
 }
 
+int gsys_test_inject(gsys_ctx* c, uint16_t nr, int32_t err, uint32_t count) {
+  if (!c || err <= 0 || err > 4095) return -EINVAL;
+  c->pool->inject(nr, err, count);
+  return 0;
+}
+
 int gsys_test_ring_ctl(gsys_ctx* c, uint64_t* out, uint64_t max) {
   if (!c || !out) return -EINVAL;
   const uint64_t n = std::min<uint64_t>(max, c->D);

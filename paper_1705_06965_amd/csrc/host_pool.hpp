@@ -103,6 +103,12 @@ class Pool {
   int add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id);
   int remove_buffer(uint32_t id);
   void set_arena(uint8_t* base, uint64_t bytes) { arena_ = base; arena_bytes_ = bytes; }
+  // Answer the next `count` single requests of call `nr` with -err.
+  void inject(uint16_t nr, int32_t err, uint32_t count) {
+    inj_nr_.store(nr, std::memory_order_relaxed);
+    inj_err_.store(err, std::memory_order_relaxed);
+    inj_left_.store(count, std::memory_order_release);
+  }
   // Before start(): idle pollers count themselves in *sleepers (a word the
   // publishers can read) and block on `db`; `idle_ns` of finding nothing
   // comes first, `backstop_ns` bounds each block.
@@ -199,6 +205,11 @@ class Pool {
   uint8_t* arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
   bool arena_huge_ = true;  // hint MADV_HUGEPAGE on 2 MiB-aligned arena mappings
+
+  // fault injection (test hook)
+  std::atomic<uint32_t> inj_left_{0};
+  std::atomic<uint32_t> inj_nr_{0};
+  std::atomic<int32_t> inj_err_{0};
 
   Doorbell* db_ = nullptr;
   uint64_t* sleepers_ = nullptr;

@@ -49,8 +49,17 @@ struct RtArgs {
   int32_t dirfd;
 };
 
+// The work-group copies n bytes from HBM to host staging: 16-byte vectors
+// when both ends are 16-byte aligned, then the remaining bytes one by one.
 __device__ __forceinline__ void copy_to_host(uint64_t dst, const uint8_t* src, uint64_t n) {
-  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) gp<uint8_t>(dst)[i] = src[i];
+  uint64_t head = 0;
+  if (((dst | (uint64_t)src) & 15) == 0) {
+    const uint64_t nv = n / 16;
+    for (uint64_t i = threadIdx.x; i < nv; i += blockDim.x)
+      stg16(dst + 16 * i, ldg16((uint64_t)src + 16 * i));
+    head = nv * 16;
+  }
+  for (uint64_t i = head + threadIdx.x; i < n; i += blockDim.x) gp<uint8_t>(dst)[i] = src[i];
 }
 
 template <O o>

@@ -183,3 +183,23 @@ def test_full_sweep_sampled(gs):
     inv = np.unique(offs, return_inverse=True)[1]
     assert (f == f[first][inv]).all()
     r.close()
+
+
+def test_injected_errno_seen_by_the_gpu(gs):
+    """The host answers 7 of the 64 work-item preads with -EIO (fault
+    injection): exactly 7 items report -EIO on the GPU, the other 57 read
+    their bytes and hash to the oracle's values."""
+    import errno
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = synth.random_file(1, 262144, name="c1_256k.bin")
+    offs = synth.tiny_offsets(64)
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, 4096)
+    r = FnvRunner(ctx, p, offs, 4096, wg_size=64)
+    assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 7) == 0
+    say("tiny with 7 injected -EIO")
+    f, ret = r.run("WI", "strong", "block")
+    bad = ret == -errno.EIO
+    assert bad.sum() == 7
+    assert (ret[~bad] == want_ret[~bad]).all() and (f[~bad] == want_fnv[~bad]).all()
+    r.close()

@@ -648,3 +648,30 @@ def test_idle_pollers_take_requests_from_a_busy_stripe(tmpdata):
     finally:
         assert ctx.shutdown() == 0
         os.close(fd)
+
+
+def test_injected_errno_reaches_the_caller(datafile):
+    """With -EIO injected for the next 5 preads, exactly 5 of a wavefront's
+    64 emulated calls return -EIO and the other 59 read their bytes; the
+    errno histogram counts the 5 under 'other'."""
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=256)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 5) == 0
+        offs = synth.sweep_offsets(64, (4 << 20) // 4096)
+        buf, rets = _run(ctx, fd, offs, 1, 64, g.EMU_BLOCKING)
+        assert (rets == -errno.EIO).sum() == 5
+        ok = rets != -errno.EIO
+        assert (rets[ok] == 4096).all()
+        data = np.fromfile(datafile, dtype=np.uint8)
+        got = buf.view(np.uint8).reshape(64, 4096)
+        for i in np.nonzero(ok)[0]:
+            assert (got[i] == data[int(offs[i]):int(offs[i]) + 4096]).all()
+        assert ctx.stats()["errno_hist"][7] == 5
+        # used up: the next call runs normally
+        assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 16, 0]) == 16
+        assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, 0, 1) == -errno.EINVAL
+    finally:
+        ctx.shutdown()
+        os.close(fd)
