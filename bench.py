@@ -455,7 +455,11 @@ def run_kv(args):
     reqs = make_requests(kv.req_keys)
     print("kv set %d keys, %d requests, setup %.1fs" % (len(kv.keys), len(reqs), time.time() - t0),
           file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
+    # the pool gets the threads the oracle's CPU server gets: every core the
+    # load generator's clients leave free
+    pollers = args.service_threads if args.service_threads >= 0 else \
+        max(1, len(os.sched_getaffinity(0)) - args.kv_clients)
+    ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
                     device_timeout_ns=60_000_000_000)
     srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=args.kv_grid)
     steps = max(1, min(args.steps, 3))
@@ -523,6 +527,7 @@ def run_kv(args):
                                "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, 256-datagram "
                                "recvfrom/sendto list calls per work-group",
                    "server_workgroups": args.kv_grid, "client_threads": args.kv_clients,
+                   "service_threads": pollers,
                    "client_window": args.kv_window},
         # calls the GPU's lists asked for (datagrams received or sent) and the
         # kernel entries the host used for them (recvmmsg / sendmmsg batches)
