@@ -355,7 +355,10 @@ def run_wordscan(args):
             f.read()
     print("corpus %d files %.1f MiB, setup %.1fs" % (len(c.paths), c.total_bytes / 2**20,
                                                      time.time() - t0), file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
+    from paper_1705_06965_amd import autotune
+    pollers = args.service_threads if args.service_threads >= 0 else \
+        autotune.load("wordscan")["service_threads"]
+    ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
                     device_timeout_ns=60_000_000_000)
     r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20)
     stream = torch.cuda.current_stream()
@@ -417,7 +420,9 @@ def run_wordscan(args):
         "config": {"workload": "word search: 2,000 files, log-normal sizes (median 64 KiB, "
                                "sigma 1, cap 8 MiB), Zipf(1.1) words from a 50k vocabulary, "
                                "64 queries, 1 MiB chunk preads", "form": "persistent",
-                   "files": len(c.paths), "bytes": c.total_bytes, "chunks": r.n_chunks},
+                   "files": len(c.paths), "bytes": c.total_bytes, "chunks": r.n_chunks,
+                   "service_threads": int(ctx.cfg.service_threads) or
+                   max(1, len(os.sched_getaffinity(0)) - 1)},
         "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
         "syscalls_per_s": round(st["host_calls"] / total, 1),
         "step_ms_p50": round(1e3 * percentile(wall, 50), 3),
