@@ -38,6 +38,9 @@ namespace {
 constexpr uint8_t kPermMask = 0xF;  // GSYS_FD_READ | WRITE | SOCK | DIR
 constexpr uint8_t kOwned = 0x40;    // opened by a GPU openat: the pool closes it
 constexpr uint8_t kRegular = 0x80;  // fd refers to a regular file (transfers may merge)
+// Slot state used by the pool only: taken by its owner's scan, not yet
+// started; another poller may still take it (see host_pool.hpp).
+constexpr uint32_t kQueued = 5u;
 
 inline uint64_t now_ns() {
   timespec ts;
@@ -111,6 +114,9 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
   {
     const char* e = getenv("GSYS_ARENA_HUGEPAGE");
     arena_huge_ = !(e && *e == '0');
+    const char* st = getenv("GSYS_STEAL");
+    steal_on_ = !(st && *st == '0');
+
   }
   fdcopies_.resize((size_t)P_);
 }
@@ -716,7 +722,8 @@ void Pool::retire_scan() {
 static inline bool taken(uint64_t c, uint64_t t) {
   const uint64_t ct = GSYS_CTL_TICKET(c);
   const uint32_t st = GSYS_CTL_STATE(c);
-  return ct > t || (ct == t && (st == GSYS_ST_PROCESSING || st == GSYS_ST_FINISHED));
+  return ct > t ||
+         (ct == t && (st == GSYS_ST_PROCESSING || st == GSYS_ST_FINISHED || st == kQueued));
 }
 
 void Pool::poller(int idx) {
@@ -747,10 +754,8 @@ void Pool::poller(int idx) {
     }
     return true;
   };
-  // without coalescing one request at a time, leaving the rest to thieves
-  const int limit = K_ > 1 ? (int)S : 1;
-  // Serve one READY request of another poller's stripe or of one of the next
-  // two unowned stripes; false if there is none.
+  // Serve one READY or QUEUED request of another poller's stripe or of one of
+  // the next two unowned stripes; false if there is none.
   auto steal = [&]() {
     auto try_stripe = [&](uint64_t st) {
       if (st == s) return false;
@@ -758,7 +763,7 @@ void Pool::poller(int idx) {
         const uint64_t t = st * S + i;
         gsys_slot* sl = &ring_[t & (D_ - 1)];
         uint64_t c = ld_acq(&sl->ctl);
-        if (c != GSYS_CTL(t, GSYS_ST_READY)) continue;
+        if (c != GSYS_CTL(t, GSYS_ST_READY) && c != GSYS_CTL(t, kQueued)) continue;
         if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, GSYS_ST_PROCESSING), false,
                                         __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
           Req r{t, sl};
@@ -777,7 +782,7 @@ void Pool::poller(int idx) {
     int n = 0;
     auto scan = [&](void) {
       const uint64_t t0 = s * S;
-      for (uint32_t i = 0; i < S && n < limit; ++i) {
+      for (uint32_t i = 0; i < S && n < (int)S; ++i) {
         if ((done >> i) & 1) continue;
         const uint64_t t = t0 + i;
         gsys_slot* sl = &ring_[t & (D_ - 1)];
@@ -786,7 +791,7 @@ void Pool::poller(int idx) {
           if (taken(c, t)) done |= 1ull << i;  // served by another poller
           continue;
         }
-        if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, GSYS_ST_PROCESSING), false,
+        if (__atomic_compare_exchange_n(&sl->ctl, &c, GSYS_CTL(t, kQueued), false,
                                         __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
           rq[n++] = Req{t, sl};
           done |= 1ull << i;
@@ -804,13 +809,25 @@ void Pool::poller(int idx) {
     }
     if (n) {
       woken = false;
+      // a queued request is served by whoever moves it to PROCESSING
+      auto start = [](const Req& q) {
+        uint64_t c = GSYS_CTL(q.t, kQueued);
+        return __atomic_compare_exchange_n(&q.s->ctl, &c, GSYS_CTL(q.t, GSYS_ST_PROCESSING), false,
+                                           __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE);
+      };
       if (K_ > 1) {
-        // requests in ticket order; bundles of at most K
+        // requests in ticket order; bundles of at most K of those still here
         std::sort(rq.begin(), rq.begin() + n, [](const Req& x, const Req& y) { return x.t < y.t; });
-        for (int i = 0; i < n; i += (int)K_)
-          serve_bundle(&rq[i], std::min<int>((int)K_, n - i), idx);
+        for (int i = 0; i < n; i += (int)K_) {
+          const int e = std::min<int>((int)K_, n - i);
+          int m = 0;
+          for (int k = i; k < i + e; ++k)
+            if (start(rq[k])) rq[i + m++] = rq[k];
+          if (m) serve_bundle(&rq[i], m, idx);
+        }
       } else {
-        for (int i = 0; i < n; ++i) serve_bundle(&rq[i], 1, idx);
+        for (int i = 0; i < n; ++i)
+          if (start(rq[i])) serve_bundle(&rq[i], 1, idx);
       }
       idle = 0;
     }
@@ -826,7 +843,7 @@ void Pool::poller(int idx) {
       ++idle;
       st_idle_.fetch_add(1, std::memory_order_relaxed);
       if ((idle & 63) == 0) retire_scan();
-      if ((idle & 255) == 0 && steal()) {
+      if (steal_on_ && (idle & 255) == 0 && steal()) {
         woken = false;
         idle = 0;
         continue;
@@ -881,7 +898,8 @@ uint64_t Pool::poison_outstanding(uint64_t claimed) {
   for (uint64_t t = lo; t < claimed; ++t) {
     gsys_slot* sl = &ring_[t & (D_ - 1)];
     uint64_t c = ld_acq(&sl->ctl);
-    if (c == GSYS_CTL(t, GSYS_ST_READY) || c == GSYS_CTL(t, GSYS_ST_PROCESSING)) {
+    if (c == GSYS_CTL(t, GSYS_ST_READY) || c == GSYS_CTL(t, GSYS_ST_PROCESSING) ||
+        c == GSYS_CTL(t, kQueued)) {
       complete(t, sl, -ESHUTDOWN);
       st_ehist_[5].fetch_add(1, std::memory_order_relaxed);
       ++n;

@@ -16,12 +16,15 @@
 // Exactly-once: a poller takes a request only by compare-and-swap of the
 // slot's control word from READY to PROCESSING (section 5).
 //
-// Work stealing: without coalescing an owner takes one request of its stripe
-// at a time, and a poller with nothing ready in its own stripe serves a READY
-// request from another poller's stripe (or from the next unowned stripes),
-// so a short call never waits behind the long calls ahead of it in one
-// stripe.  An owner counts a request of its stripe that is no longer READY
-// for this lap (PROCESSING, FINISHED or freed) as done.
+// Work stealing: an owner's scan moves every READY request of its stripe to
+// QUEUED, a host-only state (the GPU never looks at it), and serves them one
+// after another, moving each to PROCESSING first.  A poller that has found
+// nothing to do for a while serves a READY or QUEUED request of another
+// poller's stripe (or of the next unowned stripes) the same way, so a short
+// call never waits behind the long calls queued ahead of it.  Whoever moves a
+// request to PROCESSING serves it; an owner skips a queued request that was
+// taken, and counts a request of its stripe that is no longer READY for this
+// lap as done.  GSYS_STEAL=0 in the environment turns stealing off.
 //
 // Coalescing (section 4.2, section 5): with K > 1 a poller that finds a ready
 // request waits up to T ns for more ready requests of its stripe, up to K,
@@ -205,6 +208,7 @@ class Pool {
   uint8_t* arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
   bool arena_huge_ = true;  // hint MADV_HUGEPAGE on 2 MiB-aligned arena mappings
+  bool steal_on_ = true;    // idle pollers serve other stripes' requests
 
   // fault injection (test hook)
   std::atomic<uint32_t> inj_left_{0};
