@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=55000, help="serve: jobs in the stream")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="serve: arrivals per second")
     ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
+    ap.add_argument("--serve-ledger", action="store_true",
+                    help="serve: record every call and report host service times by call")
     ap.add_argument("--serve-sweep", default="",
                     help="serve: offered loads (jobs/s, comma-separated) to sweep after the "
                          "main run, about 2.75 s of arrivals each")
@@ -577,7 +579,8 @@ def run_serve(args):
     print("job stream %d jobs (%s), setup %.1fs" % (len(js.kind), np.bincount(js.kind).tolist(),
                                                    time.time() - t0), file=sys.stderr, flush=True)
     ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
-                    device_timeout_ns=60_000_000_000, arena_bytes=16 << 30)
+                    device_timeout_ns=60_000_000_000, arena_bytes=16 << 30,
+                    flags=g.CFG_LEDGER if args.serve_ledger else 0, ledger_capacity=1 << 22)
     sr = ServeRun(ctx, js, in_path, out_path)
     warm = min(5000, len(js.kind) // 10)
 
@@ -687,6 +690,22 @@ def run_serve(args):
         srr.close()
         print("sweep %.0f/s done" % rate, file=sys.stderr, flush=True)
     st = ctx.stats()
+    host_us = None
+    if args.serve_ledger:
+        # host service time per call kind (claim to completion), microseconds
+        led = ctx.ledger(reset=True)
+        svc = ((led[:, 5] >> np.uint64(8)).astype(np.int64) - led[:, 4].astype(np.int64)) / 1e3
+        host_us = {}
+        for nr, nm in ((g.NR_PREAD64, "pread"), (g.NR_PWRITE64, "pwrite"), (g.NR_MMAP, "mmap"),
+                       (g.NR_MADVISE, "madvise"), (g.NR_MUNMAP, "munmap")):
+            m = led[:, 1] == nr
+            if m.any():
+                host_us[nm] = {"calls": int(m.sum()), "p50": round(float(np.percentile(svc[m], 50)), 1),
+                               "p99": round(float(np.percentile(svc[m], 99)), 1),
+                               "max": round(float(svc[m].max()), 1),
+                               "busy_s": round(float(svc[m].sum()) / 1e6, 3)}
+        pollers = int(ctx.cfg.service_threads) or max(1, len(os.sched_getaffinity(0)) - 1)
+        host_us["pool_busy_frac"] = round(float(svc.sum()) / 1e6 / (pollers * dt), 3)
     res_j = {
         "metric": "GPU-issued syscalls/s + pread-scan GB/s (frac of link roofline); p99 latency",
         "value": round((len(js.kind) - warm) / span_s, 1), "unit": "jobs/s", "n_gpus": 1,
@@ -707,6 +726,8 @@ def run_serve(args):
     }
     if sweep:
         res_j["offered_load_sweep"] = sweep
+    if host_us:
+        res_j["host_service_us"] = host_us
     if plain:
         res_j["plain_form"] = plain
     if cpu:
