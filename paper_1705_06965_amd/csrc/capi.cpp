@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <stdio.h>
 #include <sys/mman.h>
 #include <sys/syscall.h>
 #include <time.h>
@@ -734,9 +735,12 @@ void* kstate(gsys_ctx* c) { return c->dev_words + 32; }
 
 uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, lds) != hipSuccess)
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, lds);
+  if (e != hipSuccess || per_cu < 1) {
+    fprintf(stderr, "gsys: no resident work-group fits (%s; block %u, LDS %u bytes)\n",
+            e != hipSuccess ? hipGetErrorString(e) : "occupancy 0", block, lds);
     return 0;
-  if (per_cu < 1) return 0;
+  }
   return (uint32_t)per_cu * (uint32_t)c->cu_count;
 }
 
@@ -766,7 +770,12 @@ uint64_t hash_words(std::initializer_list<uint64_t> w) {
 int launch(gsys_ctx* c, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds, void** args,
            hipStream_t s) {
   hipSetDevice(c->device);
-  if (hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, s) != hipSuccess) return -ENODEV;
+  const hipError_t e = hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, s);
+  if (e != hipSuccess) {
+    fprintf(stderr, "gsys: kernel launch failed: %s (grid %u, block %u, LDS %u bytes)\n",
+            hipGetErrorString(e), grid, block, lds);
+    return -ENODEV;
+  }
   return 0;
 }
 

@@ -28,6 +28,7 @@
 #include "kernels.hpp"
 
 #include <errno.h>
+#include <stdio.h>
 #include <sys/mman.h>
 #include <time.h>
 #include <immintrin.h>
@@ -429,7 +430,11 @@ int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_h
     if (!progress) _mm_pause();
   }
   __atomic_store_n(&ctl_h[1], 1ull, __ATOMIC_RELEASE);
-  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = -ENODEV;
+  const hipError_t se = hipStreamSynchronize(s);
+  if (se != hipSuccess) {
+    fprintf(stderr, "gsys: serving stream: %s\n", hipGetErrorString(se));
+    if (!rc) rc = -ENODEV;
+  }
   if (js_dev) hipFree(js_dev);
   return rc;
 }

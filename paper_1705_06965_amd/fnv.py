@@ -60,3 +60,16 @@ class FnvRunner:
         os.close(self.fd)
         self.staging.free()
         self.lists.free()
+
+
+def consume(ctx: Context, staging: int, rets, item_bytes: int, out, wg_size: int = 256,
+            grid: int = 0, stream=None) -> int:
+    """Kernel-split form (gsys_fnv4k_consume): out[i] = FNV-1a-64 of the first
+    rets[i] bytes of staging + i * item_bytes.  `staging` is a device-readable
+    address; `rets` (int64) and `out` (int64) are device tensors of one length."""
+    n = int(rets.numel())
+    if int(out.numel()) < n:
+        raise ValueError("out holds %d items, rets %d" % (out.numel(), n))
+    return check(lib.gsys_fnv4k_consume(ctx.h, staging, rets.data_ptr(), n, item_bytes,
+                                        out.data_ptr(), wg_size, grid, _stream(stream)),
+                 "gsys_fnv4k_consume")
