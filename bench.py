@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--kv-grid", type=int, default=16, help="kv: server work-groups")
     ap.add_argument("--kv-clients", type=int, default=4, help="kv: load generator threads")
     ap.add_argument("--kv-window", type=int, default=128, help="kv: outstanding per client")
+    ap.add_argument("--kv-doorbell", action="store_true",
+                    help="kv: idle pollers block on the GPU's interrupt doorbell")
     ap.add_argument("--serve-jobs", type=int, default=55000, help="serve: jobs in the stream")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="serve: arrivals per second")
     ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
@@ -467,7 +469,8 @@ def run_kv(args):
     pollers = args.service_threads if args.service_threads >= 0 else \
         max(1, len(os.sched_getaffinity(0)) - args.kv_clients)
     ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
-                    device_timeout_ns=60_000_000_000)
+                    device_timeout_ns=60_000_000_000,
+                    flags=g.CFG_DOORBELL if args.kv_doorbell else 0)
     srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=args.kv_grid)
     steps = max(1, min(args.steps, 3))
     res_steps = []
@@ -535,7 +538,7 @@ def run_kv(args):
                                "recvfrom/sendto list calls per work-group",
                    "server_workgroups": args.kv_grid, "client_threads": args.kv_clients,
                    "service_threads": pollers,
-                   "client_window": args.kv_window},
+                   "client_window": args.kv_window, "doorbell": bool(args.kv_doorbell)},
         # calls the GPU's lists asked for (datagrams received or sent) and the
         # kernel entries the host used for them (recvmmsg / sendmmsg batches)
         "syscalls_per_s": round((stt["host_calls"] + stt["merged"]) / dts[-1], 1),
