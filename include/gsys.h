@@ -59,7 +59,7 @@ typedef struct gsys_config {
     uint64_t device_timeout_ns;  /* GPU watchdog on every wait (0 = 30 s)             */
     int32_t  first_cpu;          /* pin poller i to the (first_cpu + i)-th CPU of the
                                     affinity mask, wrapping (-1 = from the second)   */
-    uint32_t ledger_capacity;    /* ledger records kept (0 = 1<<20)                   */
+    uint32_t ledger_capacity;    /* ledger records kept between resets (0 = 1<<20)    */
     uint32_t sleep_max;          /* GPU wait backoff cap, in s_sleep steps of ~256
                                     clocks doubled up to this count (0 = 64)           */
     uint32_t doorbell_idle_us;   /* GSYS_CFG_DOORBELL: how long a poller finds nothing
@@ -216,10 +216,13 @@ typedef struct gsys_stats {
 int gsys_stats_get(gsys_ctx *ctx, gsys_stats *out, int reset);
 
 /*
- * Ledger (GSYS_CFG_LEDGER): copy up to `max` records of serviced tickets,
- * sorted by ticket, into out[6*i .. 6*i+5] = {ticket, nr, ret, args digest,
- * service start (CLOCK_MONOTONIC ns), service end ns << 8 | poller index}.
- * Returns the number of records copied; reset != 0 clears the ledger.
+ * Ledger (GSYS_CFG_LEDGER): copy the records of serviced tickets, sorted by
+ * ticket (the `max` lowest tickets when there are more), into
+ * out[6*i .. 6*i+5] = {ticket, nr, ret, args digest, service start
+ * (CLOCK_MONOTONIC ns), service end ns << 8 | poller index}.  out may be
+ * NULL to count.  Returns the number of records copied; reset != 0 clears
+ * the ledger.  Each poller records into its own shard, so recording does
+ * not serialize the pool.
  */
 int64_t gsys_ledger(gsys_ctx *ctx, uint64_t *out, uint64_t max, int reset);
 

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <sys/mman.h>
+#include <sys/prctl.h>
 #include <sys/socket.h>
 #include <sys/stat.h>
 #include <sys/syscall.h>
@@ -41,6 +42,9 @@ constexpr uint8_t kRegular = 0x80;  // fd refers to a regular file (transfers ma
 // Slot state used by the pool only: taken by its owner's scan, not yet
 // started; another poller may still take it (see host_pool.hpp).
 constexpr uint32_t kQueued = 5u;
+// A poller with nothing to do spins this long before it naps (20 us at a
+// time, timer slack 1 us) between polls.
+constexpr uint64_t kSpinNs = 2000000;
 
 inline uint64_t now_ns() {
   timespec ts;
@@ -104,12 +108,12 @@ Pool::Pool(gsys_slot* ring, gsys_comp* comp, uint64_t D, uint64_t C, uint64_t* r
   pin_ = !(cfg.flags & GSYS_CFG_NO_PIN);
   ledger_on_ = (cfg.flags & GSYS_CFG_LEDGER) != 0;
   ledger_cap_ = cfg.ledger_capacity ? cfg.ledger_capacity : (1u << 20);
-  for (auto& h : st_bhist_) h.store(0);
-  for (auto& h : st_ehist_) h.store(0);
   for (auto& p : fdperm_) p.store(0);
   for (auto& g : fdgen_) g.store(0);
   copy_fds_ = !(cfg.flags & GSYS_CFG_SHARED_FDS);
   owned_ = std::vector<std::atomic<uint64_t>>((size_t)P_);
+  for (int i = 0; i < P_; ++i) ledger_.push_back(std::make_unique<LedgerShard>());
+  for (int i = 0; i <= P_; ++i) ctr_.push_back(std::make_unique<Counters>());
   for (int i = 0; i < P_; ++i) owned_[(size_t)i].store((uint64_t)i);
   {
     const char* e = getenv("GSYS_ARENA_HUGEPAGE");
@@ -152,6 +156,7 @@ int Pool::allow_fd(int fd, uint32_t perms) {
 }
 
 thread_local Pool::FdCopies* Pool::tls_copies_ = nullptr;
+thread_local Pool::Counters* Pool::tls_ctr_ = nullptr;
 
 namespace {
 // A new open file description of the file behind `fd`, with its access mode
@@ -255,7 +260,7 @@ uint8_t* Pool::translate(uint64_t dev, uint64_t len, bool) {
 
 void Pool::note_errno(int64_t ret) {
   if (ret >= 0) return;
-  st_err_.fetch_add(1, std::memory_order_relaxed);
+  bump(ctr().err, 1);
   int b;
   switch ((int)-ret) {
     case EPERM: b = 0; break;
@@ -267,7 +272,7 @@ void Pool::note_errno(int64_t ret) {
     case ETIMEDOUT: b = 6; break;
     default: b = 7;
   }
-  st_ehist_[b].fetch_add(1, std::memory_order_relaxed);
+  bump(ctr().ehist[b], 1);
 }
 
 // Execute one single (non-list) request.
@@ -292,7 +297,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
                                           : read((int)a[0], h, a[2]);
       ++*calls;
       r = n < 0 ? -(int64_t)errno : (int64_t)n;
-      if (r > 0) st_in_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      if (r > 0) bump(ctr().in, (uint64_t)r);
       return r;
     }
     case GSYS_NR_PWRITE64:
@@ -305,7 +310,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
                                            : write((int)a[0], h, a[2]);
       ++*calls;
       r = n < 0 ? -(int64_t)errno : (int64_t)n;
-      if (r > 0) st_out_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      if (r > 0) bump(ctr().out, (uint64_t)r);
       return r;
     }
     case GSYS_NR_SENDTO: {
@@ -320,7 +325,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
                          (socklen_t)a[5]);
       ++*calls;
       r = n < 0 ? -(int64_t)errno : (int64_t)n;
-      if (r > 0) st_out_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      if (r > 0) bump(ctr().out, (uint64_t)r);
       return r;
     }
     case GSYS_NR_RECVFROM: {
@@ -340,7 +345,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
         uint8_t* out = translate(a[4], sizeof from, true);
         if (out) memcpy(out, &from, sizeof from);
       }
-      if (r > 0) st_in_.fetch_add((uint64_t)r, std::memory_order_relaxed);
+      if (r > 0) bump(ctr().in, (uint64_t)r);
       return r;
     }
     case GSYS_NR_MMAP: {
@@ -427,7 +432,7 @@ int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       return close((int)fd) ? -(int64_t)errno : 0;
     }
     default:
-      st_rej_.fetch_add(1, std::memory_order_relaxed);
+      bump(ctr().rej, 1);
       return -EPERM;
   }
 }
@@ -507,8 +512,8 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
       }
       i = j;
     }
-    if (rd) st_in_.fetch_add(total, std::memory_order_relaxed);
-    else st_out_.fetch_add(total, std::memory_order_relaxed);
+    if (rd) bump(ctr().in, total);
+    else bump(ctr().out, total);
   } else if (s.nr == GSYS_NR_RECVFROM || s.nr == GSYS_NR_SENDTO) {
     if (!fd_ok(fd, GSYS_FD_SOCK)) return -EBADF;
     if (a[4] & ~(uint64_t)MSG_DONTWAIT) return -EINVAL;
@@ -594,10 +599,10 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
         }
       }
     }
-    if (rx) st_in_.fetch_add(total, std::memory_order_relaxed);
-    else st_out_.fetch_add(total, std::memory_order_relaxed);
+    if (rx) bump(ctr().in, total);
+    else bump(ctr().out, total);
   } else {
-    st_rej_.fetch_add(1, std::memory_order_relaxed);
+    bump(ctr().rej, 1);
     return -EPERM;
   }
   return first_err ? first_err : (int64_t)total;
@@ -607,7 +612,7 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
 // field and to the ticket's completion record; a blocking slot becomes
 // FINISHED (the GPU frees it), a non-blocking one becomes FREE for the next
 // lap.  Then the claim group's completion count goes up by one.
-void Pool::complete(uint64_t t, gsys_slot* s, int64_t ret) {
+void Pool::complete(uint64_t t, gsys_slot* s, int64_t ret, StampAcc* acc) {
   const uint8_t flags = s->flags;
   const uint64_t head = t - s->grp_off;
   gsys_comp* c = &comp_[t & (C_ - 1)];
@@ -618,23 +623,36 @@ void Pool::complete(uint64_t t, gsys_slot* s, int64_t ret) {
   } else {
     st_rel(&s->ctl, GSYS_CTL(t + D_, GSYS_ST_FREE));
   }
+  if (!acc) {
+    add_stamp(head, 1);
+    return;
+  }
+  if (acc->k && acc->head != head) flush_stamp(*acc);
+  acc->head = head;
+  ++acc->k;
+}
+
+void Pool::add_stamp(uint64_t head, uint32_t k) {
+  // release: the results posted before are visible to whoever sees the count
   uint64_t* stp = &comp_[head & (C_ - 1)].stamp;
   uint64_t v = __atomic_load_n(stp, __ATOMIC_ACQUIRE);
   for (;;) {
     const uint64_t vh = v >> 8;
     if (vh > head) break;  // lapped by a later group (the waiter reports -EOVERFLOW)
-    const uint64_t nv = vh == head ? v + 1 : GSYS_STAMP(head, 1);
+    const uint64_t nv = vh == head ? v + k : GSYS_STAMP(head, k);
     if (__atomic_compare_exchange_n(stp, &v, nv, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) break;
   }
 }
 
-void Pool::serve_bundle(Req* rq, int n, int poller) {
+void Pool::serve_bundle(Req* rq, int n, int poller, StampAcc* acc) {
   const uint64_t t0 = now_ns();
   uint64_t tprev = t0;
   uint64_t calls = 0, merged = 0;
   int i = 0;
   while (i < n) {
     gsys_slot& s = *rq[i].s;
+    // counts held back for another group are posted before this request runs
+    if (acc && acc->k && acc->head != rq[i].t - s.grp_off) flush_stamp(*acc);
     // Coalesced bundle: fold single pread/pwrite requests that continue the
     // previous one in the file and in memory into one call.
     int j = i + 1;
@@ -666,13 +684,11 @@ void Pool::serve_bundle(Req* rq, int n, int poller) {
           note_errno(rk);
           if (ledger_on_) {
             const uint64_t te = now_ns();
-            std::lock_guard<std::mutex> g(ledmu_);
-            if (ledger_.size() < ledger_cap_)
-              ledger_.push_back({rq[k].t, rq[k].s->nr, (uint64_t)rk,
-                                 mix64(rq[k].s->args[0] ^ mix64(rq[k].s->args[1] ^ mix64(rq[k].s->args[3]))),
-                                 tprev, (te << 8) | (uint64_t)(poller & 0xff)});
+            record(poller, {rq[k].t, rq[k].s->nr, (uint64_t)rk,
+                            mix64(rq[k].s->args[0] ^ mix64(rq[k].s->args[1] ^ mix64(rq[k].s->args[3]))),
+                            tprev, (te << 8) | (uint64_t)(poller & 0xff)});
           }
-          complete(rq[k].t, rq[k].s, rk);
+          complete(rq[k].t, rq[k].s, rk, acc);
         }
         i = j;
         continue;
@@ -683,22 +699,21 @@ void Pool::serve_bundle(Req* rq, int n, int poller) {
     if (!(s.flags & GSYS_F_LIST)) note_errno(r);
     if (ledger_on_) {
       const uint64_t te = now_ns();
-      std::lock_guard<std::mutex> g(ledmu_);
-      if (ledger_.size() < ledger_cap_)
-        ledger_.push_back({rq[i].t, s.nr, (uint64_t)r,
-                           mix64(s.args[0] ^ mix64(s.args[1] ^ mix64(s.args[3]))), tprev,
-                           (te << 8) | (uint64_t)(poller & 0xff)});
+      record(poller, {rq[i].t, s.nr, (uint64_t)r,
+                      mix64(s.args[0] ^ mix64(s.args[1] ^ mix64(s.args[3]))), tprev,
+                      (te << 8) | (uint64_t)(poller & 0xff)});
       tprev = te;
     }
-    complete(rq[i].t, rq[i].s, r);
+    complete(rq[i].t, rq[i].s, r, acc);
     ++i;
   }
-  st_requests_.fetch_add((uint64_t)n, std::memory_order_relaxed);
-  st_calls_.fetch_add(calls, std::memory_order_relaxed);
-  st_merged_.fetch_add(merged, std::memory_order_relaxed);
-  st_bundles_.fetch_add(1, std::memory_order_relaxed);
-  st_bhist_[hist_bucket((uint64_t)n)].fetch_add(1, std::memory_order_relaxed);
-  st_ns_.fetch_add(now_ns() - t0, std::memory_order_relaxed);
+  Counters& k = ctr();
+  bump(k.requests, (uint64_t)n);
+  bump(k.calls, calls);
+  bump(k.merged, merged);
+  bump(k.bundles, 1);
+  bump(k.bhist[hist_bucket((uint64_t)n)], 1);
+  bump(k.ns, now_ns() - t0);
   serviced_.fetch_add((uint64_t)n, std::memory_order_acq_rel);
 }
 
@@ -728,6 +743,8 @@ static inline bool taken(uint64_t c, uint64_t t) {
 
 void Pool::poller(int idx) {
   tls_copies_ = &fdcopies_[(size_t)idx];
+  tls_ctr_ = ctr_[(size_t)idx].get();
+  prctl(PR_SET_TIMERSLACK, 1000ul, 0, 0, 0);  // naps end close to their 20 us
   if (pin_) {
     // poller i runs on allowed CPU number first + i (mod the allowed count)
     const size_t first = first_cpu_ >= 0 ? (size_t)first_cpu_ : 1;
@@ -815,6 +832,7 @@ void Pool::poller(int idx) {
         return __atomic_compare_exchange_n(&q.s->ctl, &c, GSYS_CTL(q.t, GSYS_ST_PROCESSING), false,
                                            __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE);
       };
+      StampAcc acc;
       if (K_ > 1) {
         // requests in ticket order; bundles of at most K of those still here
         std::sort(rq.begin(), rq.begin() + n, [](const Req& x, const Req& y) { return x.t < y.t; });
@@ -823,12 +841,13 @@ void Pool::poller(int idx) {
           int m = 0;
           for (int k = i; k < i + e; ++k)
             if (start(rq[k])) rq[i + m++] = rq[k];
-          if (m) serve_bundle(&rq[i], m, idx);
+          if (m) serve_bundle(&rq[i], m, idx, &acc);
         }
       } else {
         for (int i = 0; i < n; ++i)
-          if (start(rq[i])) serve_bundle(&rq[i], 1, idx);
+          if (start(rq[i])) serve_bundle(&rq[i], 1, idx, &acc);
       }
+      flush_stamp(acc);
       idle = 0;
     }
     if (done == full) {
@@ -841,15 +860,15 @@ void Pool::poller(int idx) {
     }
     if (!n) {
       ++idle;
-      st_idle_.fetch_add(1, std::memory_order_relaxed);
+      bump(ctr().idle, 1);
       if ((idle & 63) == 0) retire_scan();
       if (steal_on_ && (idle & 255) == 0 && steal()) {
         woken = false;
         idle = 0;
         continue;
       }
+      if (idle == 1) idle_since = now_ns();
       if (db_) {
-        if (idle == 1) idle_since = now_ns();
         // A poller woken for a request of another stripe blocks again at
         // once; the idle period applies after real work (bursts).
         if (woken || ((idle & 63) == 0 && now_ns() - idle_since >= db_idle_ns_)) {
@@ -865,7 +884,7 @@ void Pool::poller(int idx) {
           woken = false;
           if (stripe_quiet() && !stop_.load(std::memory_order_relaxed)) {
             db_->wait(seen, db_backstop_ns_);
-            st_sleeps_.fetch_add(1, std::memory_order_relaxed);
+            bump(ctr().sleeps, 1);
             woken = true;
           }
           __atomic_fetch_sub(sleepers_, 1, __ATOMIC_SEQ_CST);
@@ -873,9 +892,10 @@ void Pool::poller(int idx) {
         } else {
           _mm_pause();
         }
-      } else if (idle < 20000) {
+      } else if ((idle & 63) != 0 || now_ns() - idle_since < kSpinNs) {
         _mm_pause();
       } else {
+        // idle for a while: give the core back in short naps
         timespec ts{0, 20000};
         nanosleep(&ts, nullptr);
       }
@@ -887,6 +907,7 @@ void Pool::poller(int idx) {
     e = FdCopies::Ent{};
   }
   tls_copies_ = nullptr;
+  tls_ctr_ = nullptr;
 }
 
 uint64_t Pool::poison_outstanding(uint64_t claimed) {
@@ -901,7 +922,7 @@ uint64_t Pool::poison_outstanding(uint64_t claimed) {
     if (c == GSYS_CTL(t, GSYS_ST_READY) || c == GSYS_CTL(t, GSYS_ST_PROCESSING) ||
         c == GSYS_CTL(t, kQueued)) {
       complete(t, sl, -ESHUTDOWN);
-      st_ehist_[5].fetch_add(1, std::memory_order_relaxed);
+      bump(ctr().ehist[5], 1);
       ++n;
     }
   }
@@ -910,32 +931,84 @@ uint64_t Pool::poison_outstanding(uint64_t claimed) {
 }
 
 void Pool::stats(gsys_stats* o, int reset) {
-  auto rd = [reset](std::atomic<uint64_t>& a) { return reset ? a.exchange(0) : a.load(); };
-  memset(o, 0, sizeof *o);
-  o->requests = rd(st_requests_);
-  o->host_calls = rd(st_calls_);
-  o->bytes_in = rd(st_in_);
-  o->bytes_out = rd(st_out_);
-  o->errors = rd(st_err_);
-  o->rejected = rd(st_rej_);
-  o->bundles = rd(st_bundles_);
-  o->merged = rd(st_merged_);
-  o->idle_polls = rd(st_idle_);
-  o->service_ns = rd(st_ns_);
-  o->doorbell_sleeps = rd(st_sleeps_);
-  for (int i = 0; i < 8; ++i) {
-    o->bundle_hist[i] = rd(st_bhist_[i]);
-    o->errno_hist[i] = rd(st_ehist_[i]);
+  gsys_stats sum;
+  memset(&sum, 0, sizeof sum);
+  for (auto& cp : ctr_) {
+    const Counters& c = *cp;
+    auto rd = [](const std::atomic<uint64_t>& a) { return a.load(std::memory_order_relaxed); };
+    sum.requests += rd(c.requests);
+    sum.host_calls += rd(c.calls);
+    sum.bytes_in += rd(c.in);
+    sum.bytes_out += rd(c.out);
+    sum.errors += rd(c.err);
+    sum.rejected += rd(c.rej);
+    sum.bundles += rd(c.bundles);
+    sum.merged += rd(c.merged);
+    sum.idle_polls += rd(c.idle);
+    sum.service_ns += rd(c.ns);
+    sum.doorbell_sleeps += rd(c.sleeps);
+    for (int i = 0; i < 8; ++i) {
+      sum.bundle_hist[i] += rd(c.bhist[i]);
+      sum.errno_hist[i] += rd(c.ehist[i]);
+    }
   }
+  // counters only grow: a reset keeps the sums as the new zero
+  std::lock_guard<std::mutex> g(stmu_);
+  memset(o, 0, sizeof *o);
+  o->requests = sum.requests - base_.requests;
+  o->host_calls = sum.host_calls - base_.host_calls;
+  o->bytes_in = sum.bytes_in - base_.bytes_in;
+  o->bytes_out = sum.bytes_out - base_.bytes_out;
+  o->errors = sum.errors - base_.errors;
+  o->rejected = sum.rejected - base_.rejected;
+  o->bundles = sum.bundles - base_.bundles;
+  o->merged = sum.merged - base_.merged;
+  o->idle_polls = sum.idle_polls - base_.idle_polls;
+  o->service_ns = sum.service_ns - base_.service_ns;
+  o->doorbell_sleeps = sum.doorbell_sleeps - base_.doorbell_sleeps;
+  for (int i = 0; i < 8; ++i) {
+    o->bundle_hist[i] = sum.bundle_hist[i] - base_.bundle_hist[i];
+    o->errno_hist[i] = sum.errno_hist[i] - base_.errno_hist[i];
+  }
+  if (reset) base_ = sum;
   o->retired_lo = __atomic_load_n(retired_lo_, __ATOMIC_ACQUIRE);
 }
 
+void Pool::record(int poller, const LedgerRec& r) {
+  // At most ledger_cap_ records between resets: a shard takes capacity from
+  // the shared count 256 records at a time.
+  LedgerShard& sh = *ledger_[(size_t)poller];
+  std::lock_guard<std::mutex> g(sh.mu);
+  const uint64_t ep = ledger_epoch_.load(std::memory_order_acquire);
+  if (sh.epoch != ep) {
+    sh.epoch = ep;
+    sh.quota = 0;
+  }
+  if (!sh.quota) {
+    constexpr uint64_t kBlock = 256;
+    const uint64_t got = ledger_n_.fetch_add(kBlock, std::memory_order_relaxed);
+    if (got >= ledger_cap_) return;
+    sh.quota = std::min<uint64_t>(kBlock, ledger_cap_ - got);
+  }
+  --sh.quota;
+  sh.recs.push_back(r);
+}
+
 int64_t Pool::ledger(uint64_t* out, uint64_t max, int reset) {
-  std::lock_guard<std::mutex> g(ledmu_);
-  uint64_t n = std::min<uint64_t>(max, ledger_.size());
+  std::vector<LedgerRec> v;
+  for (auto& sh : ledger_) {
+    std::lock_guard<std::mutex> g(sh->mu);
+    v.insert(v.end(), sh->recs.begin(), sh->recs.end());
+    if (reset) sh->recs.clear();
+  }
+  if (reset) {
+    // a shard notices the new epoch (under its lock) and drops its quota
+    ledger_epoch_.fetch_add(1, std::memory_order_acq_rel);
+    ledger_n_.store(0, std::memory_order_relaxed);
+  }
+  std::sort(v.begin(), v.end(), [](const LedgerRec& x, const LedgerRec& y) { return x.ticket < y.ticket; });
+  const uint64_t n = std::min<uint64_t>(max, v.size());
   if (out) {
-    std::vector<LedgerRec> v(ledger_.begin(), ledger_.begin() + n);
-    std::sort(v.begin(), v.end(), [](const LedgerRec& x, const LedgerRec& y) { return x.ticket < y.ticket; });
     for (uint64_t i = 0; i < n; ++i) {
       out[6 * i] = v[i].ticket;
       out[6 * i + 1] = v[i].nr;
@@ -945,7 +1018,6 @@ int64_t Pool::ledger(uint64_t* out, uint64_t max, int reset) {
       out[6 * i + 5] = v[i].t_end_poller;
     }
   }
-  if (reset) ledger_.clear();
   return (int64_t)n;
 }
 

@@ -26,6 +26,11 @@
 // taken, and counts a request of its stripe that is no longer READY for this
 // lap as done.  GSYS_STEAL=0 in the environment turns stealing off.
 //
+// Nothing a poller writes per request is shared with another poller but the
+// request's own slot and completion record: statistics and ledger records
+// go to per-poller blocks, and a poller serving several members of one
+// claim group in a row counts them in the group's record with one update.
+//
 // Coalescing (section 4.2, section 5): with K > 1 a poller that finds a ready
 // request waits up to T ns for more ready requests of its stripe, up to K,
 // and executes them as one bundle, folding transfers that are adjacent both
@@ -34,6 +39,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -140,11 +146,27 @@ class Pool {
     uint64_t t;
     gsys_slot* s;
   };
+  // Completions of one claim group that a poller has posted but not yet
+  // counted in the group's completion record.  A group is done only when all
+  // its members are, so a poller that serves several members in a row counts
+  // them with one update of the shared record instead of one each.
+  struct StampAcc {
+    uint64_t head = ~0ull;
+    uint32_t k = 0;
+  };
   void poller(int idx);
-  void serve_bundle(Req* rq, int n, int poller);
+  void serve_bundle(Req* rq, int n, int poller, StampAcc* acc = nullptr);
   int64_t execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
   int64_t exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged);
-  void complete(uint64_t t, gsys_slot* s, int64_t ret);
+  // Post one request's result; its group count goes to *acc (flushed when
+  // the group changes) or, without acc, straight to the completion record.
+  void complete(uint64_t t, gsys_slot* s, int64_t ret, StampAcc* acc = nullptr);
+  void add_stamp(uint64_t head, uint32_t k);
+  void flush_stamp(StampAcc& acc) {
+    if (acc.k) add_stamp(acc.head, acc.k);
+    acc.k = 0;
+  }
+  void record(int poller, const LedgerRec& r);
   uint8_t* translate(uint64_t dev, uint64_t len, bool need_host_write);
   bool fd_ok(int64_t fd, uint32_t need) const;
   // The descriptor a positional call on regular file `fd` should use: this
@@ -219,14 +241,35 @@ class Pool {
   uint64_t* sleepers_ = nullptr;
   uint64_t db_idle_ns_ = 0, db_backstop_ns_ = 0;
 
-  // stats
-  std::atomic<uint64_t> st_requests_{0}, st_calls_{0}, st_in_{0}, st_out_{0}, st_err_{0},
-      st_rej_{0}, st_bundles_{0}, st_merged_{0}, st_idle_{0}, st_ns_{0}, st_sleeps_{0};
-  std::atomic<uint64_t> st_bhist_[8];
-  std::atomic<uint64_t> st_ehist_[8];
+  // Statistics: one block of counters per poller (only that poller writes
+  // it) and one for every other thread; stats() sums them.  Pollers never
+  // write a cache line another poller writes: shared counters cost each
+  // request several contended read-modify-writes.
+  struct alignas(64) Counters {
+    std::atomic<uint64_t> requests{0}, calls{0}, in{0}, out{0}, err{0}, rej{0}, bundles{0},
+        merged{0}, idle{0}, ns{0}, sleeps{0};
+    std::atomic<uint64_t> bhist[8] = {}, ehist[8] = {};
+  };
+  std::vector<std::unique_ptr<Counters>> ctr_;  // P pollers, then the others
+  static thread_local Counters* tls_ctr_;
+  Counters& ctr() { return tls_ctr_ ? *tls_ctr_ : *ctr_.back(); }
+  static void bump(std::atomic<uint64_t>& a, uint64_t v) { a.fetch_add(v, std::memory_order_relaxed); }
+  std::mutex stmu_;
+  gsys_stats base_{};  // sums at the last reset
 
-  std::mutex ledmu_;
-  std::vector<LedgerRec> ledger_;
+  // The ledger in one shard per poller: a poller appends to its own shard
+  // under that shard's lock, which only the reader also takes, so recording
+  // does not make the pollers wait for each other.
+  struct alignas(64) LedgerShard {
+    std::mutex mu;
+    std::vector<LedgerRec> recs;
+    uint64_t quota = 0;  // records this shard may still add
+    uint64_t epoch = 0;  // reset generation the quota belongs to
+  };
+  std::vector<std::unique_ptr<LedgerShard>> ledger_;
+  // capacity handed out to the shards in blocks (since the last reset)
+  std::atomic<uint64_t> ledger_n_{0};
+  std::atomic<uint64_t> ledger_epoch_{0};
 };
 
 }  // namespace gsys_host
