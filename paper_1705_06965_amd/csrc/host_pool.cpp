@@ -9,7 +9,6 @@
 #include <stdio.h>
 #include <string.h>
 #include <sys/mman.h>
-#include <sys/prctl.h>
 #include <sys/socket.h>
 #include <sys/stat.h>
 #include <sys/syscall.h>
@@ -42,9 +41,9 @@ constexpr uint8_t kRegular = 0x80;  // fd refers to a regular file (transfers ma
 // Slot state used by the pool only: taken by its owner's scan, not yet
 // started; another poller may still take it (see host_pool.hpp).
 constexpr uint32_t kQueued = 5u;
-// A poller with nothing to do spins this long before it naps (20 us at a
-// time, timer slack 1 us) between polls.
-constexpr uint64_t kSpinNs = 2000000;
+// A poller with nothing to do spins this long before it naps between polls
+// (20 us asked; with the default timer slack a nap lasts ~70 us).
+constexpr uint64_t kSpinNs = 5000000;
 
 inline uint64_t now_ns() {
   timespec ts;
@@ -744,7 +743,6 @@ static inline bool taken(uint64_t c, uint64_t t) {
 void Pool::poller(int idx) {
   tls_copies_ = &fdcopies_[(size_t)idx];
   tls_ctr_ = ctr_[(size_t)idx].get();
-  prctl(PR_SET_TIMERSLACK, 1000ul, 0, 0, 0);  // naps end close to their 20 us
   if (pin_) {
     // poller i runs on allowed CPU number first + i (mod the allowed count)
     const size_t first = first_cpu_ >= 0 ? (size_t)first_cpu_ : 1;
@@ -761,6 +759,7 @@ void Pool::poller(int idx) {
   uint64_t idle = 0;
   uint64_t idle_since = 0;
   bool woken = false;  // back from the doorbell and nothing found yet
+  bool napping = false;  // idle longer than kSpinNs (no doorbell)
   // Nothing in this poller's stripe is READY (a peek: nothing is taken).
   auto stripe_quiet = [&]() {
     const uint64_t t0 = s * S;
@@ -849,6 +848,7 @@ void Pool::poller(int idx) {
       }
       flush_stamp(acc);
       idle = 0;
+      napping = false;
     }
     if (done == full) {
       // the next unowned stripe goes to whichever poller finishes first, so
@@ -865,6 +865,7 @@ void Pool::poller(int idx) {
       if (steal_on_ && (idle & 255) == 0 && steal()) {
         woken = false;
         idle = 0;
+        napping = false;
         continue;
       }
       if (idle == 1) idle_since = now_ns();
@@ -892,12 +893,15 @@ void Pool::poller(int idx) {
         } else {
           _mm_pause();
         }
-      } else if ((idle & 63) != 0 || now_ns() - idle_since < kSpinNs) {
-        _mm_pause();
       } else {
-        // idle for a while: give the core back in short naps
-        timespec ts{0, 20000};
-        nanosleep(&ts, nullptr);
+        if (!napping && (idle & 63) == 0 && now_ns() - idle_since >= kSpinNs) napping = true;
+        if (napping) {
+          // idle for a while: give the core back in short naps
+          timespec ts{0, 20000};
+          nanosleep(&ts, nullptr);
+        } else {
+          _mm_pause();
+        }
       }
     }
   }
