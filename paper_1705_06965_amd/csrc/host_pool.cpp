@@ -713,7 +713,7 @@ void Pool::serve_bundle(Req* rq, int n, int poller, StampAcc* acc) {
   bump(k.bundles, 1);
   bump(k.bhist[hist_bucket((uint64_t)n)], 1);
   bump(k.ns, now_ns() - t0);
-  serviced_.fetch_add((uint64_t)n, std::memory_order_acq_rel);
+  k.serviced.fetch_add((uint64_t)n, std::memory_order_release);
 }
 
 // Advance the retire watermark: ticket lo has retired once its slot has been
@@ -930,7 +930,7 @@ uint64_t Pool::poison_outstanding(uint64_t claimed) {
       ++n;
     }
   }
-  serviced_.fetch_add(n, std::memory_order_acq_rel);
+  ctr().serviced.fetch_add(n, std::memory_order_release);
   return n;
 }
 

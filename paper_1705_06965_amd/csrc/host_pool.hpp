@@ -129,7 +129,12 @@ class Pool {
   }
 
   // servicing
-  uint64_t serviced() const { return serviced_.load(std::memory_order_acquire); }
+  // requests completed so far (each completion is visible to the caller)
+  uint64_t serviced() const {
+    uint64_t n = 0;
+    for (const auto& c : ctr_) n += c->serviced.load(std::memory_order_acquire);
+    return n;
+  }
   // Complete every request still READY with -ESHUTDOWN (called after the
   // pollers stopped).  `claimed` bounds the tickets examined.
   uint64_t poison_outstanding(uint64_t claimed);
@@ -188,7 +193,6 @@ class Pool {
 
   std::vector<std::thread> threads_;
   std::atomic<bool> stop_{false};
-  std::atomic<uint64_t> serviced_{0};
   std::atomic<uint64_t> next_stripe_{0};  // stripes are taken in order by whichever poller is free
   std::vector<std::atomic<uint64_t>> owned_;  // each poller's current stripe (for stealing)
   std::atomic_flag retire_busy_ = ATOMIC_FLAG_INIT;
@@ -248,6 +252,7 @@ class Pool {
   struct alignas(64) Counters {
     std::atomic<uint64_t> requests{0}, calls{0}, in{0}, out{0}, err{0}, rej{0}, bundles{0},
         merged{0}, idle{0}, ns{0}, sleeps{0};
+    std::atomic<uint64_t> serviced{0};  // completed requests, release-incremented
     std::atomic<uint64_t> bhist[8] = {}, ehist[8] = {};
   };
   std::vector<std::unique_ptr<Counters>> ctr_;  // P pollers, then the others
