@@ -675,3 +675,37 @@ def test_injected_errno_reaches_the_caller(datafile):
     finally:
         ctx.shutdown()
         os.close(fd)
+
+
+def test_stats_reset_and_ledger_capacity(datafile):
+    """Statistics and ledger records are kept per poller and summed when read:
+    a reset makes the current sums the new zero, the ledger keeps at most its
+    capacity of records between resets (each a distinct serviced ticket), and
+    gsys_wait sees every completion."""
+    n_blocks = (4 << 20) // 4096
+    offs = synth.sweep_offsets(2048, n_blocks)
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=1024, ledger_capacity=300)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        for run in range(2):
+            _, rets = _run(ctx, fd, offs, 8, 8, 0)
+            assert (rets == 4096).all()
+            assert ctx.wait(5_000_000_000) == 0
+            st = ctx.stats(reset=True)
+            assert st["requests"] == len(offs) and st["host_calls"] == len(offs)
+            assert st["bytes_in"] == 4096 * len(offs)
+            assert st["bundles"] >= 1 and sum(st["bundle_hist"]) == st["bundles"]
+            after = ctx.stats()
+            assert after["requests"] == 0 and after["host_calls"] == 0 and after["bytes_in"] == 0
+            led = ctx.ledger(reset=True)
+            assert 0 < len(led) <= 300
+            tickets = led[:, 0]
+            assert len(np.unique(tickets)) == len(tickets)
+            assert (np.diff(tickets.astype(np.int64)) > 0).all()       # sorted by ticket
+            assert (tickets >= run * len(offs)).all() and (tickets < (run + 1) * len(offs)).all()
+            assert (led[:, 2] == 4096).all()
+            assert len(ctx.ledger()) == 0
+    finally:
+        assert ctx.shutdown() == 0
+        os.close(fd)
