@@ -59,6 +59,12 @@ def parse():
     ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
     ap.add_argument("--serve-ledger", action="store_true",
                     help="serve: record every call and report host service times by call")
+    ap.add_argument("--serve-grid", type=int, default=0,
+                    help="serve: persistent work-groups (0 = the library default, 64)")
+    ap.add_argument("--serve-sleep-max", type=int, default=0,
+                    help="serve: cap of the device waiters' backoff (s_sleep steps, 0 = default)")
+    ap.add_argument("--serve-ledger-out", default="",
+                    help="serve: also save the raw ledger (numpy .npy, one row per call)")
     ap.add_argument("--serve-sweep", default="",
                     help="serve: offered loads (jobs/s, comma-separated) to sweep after the "
                          "main run, about 2.75 s of arrivals each")
@@ -583,13 +589,15 @@ def run_serve(args):
                                                    time.time() - t0), file=sys.stderr, flush=True)
     ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
                     device_timeout_ns=60_000_000_000, arena_bytes=16 << 30,
-                    flags=g.CFG_LEDGER if args.serve_ledger else 0, ledger_capacity=1 << 22)
+                    flags=g.CFG_LEDGER if args.serve_ledger else 0, ledger_capacity=1 << 22,
+                    sleep_max=args.serve_sleep_max)
     sr = ServeRun(ctx, js, in_path, out_path)
     warm = min(5000, len(js.kind) // 10)
 
     def session(form, inflight, n_limit=None):
         t1 = time.perf_counter()
         res, dig, lat = sr.run(form, max_inflight=inflight, staging_bytes=(2 << 20) * 256,
+                               grid=args.serve_grid if form == g.PERSISTENT else 0,
                                timeout_ns=300_000_000_000)
         dt = time.perf_counter() - t1
         return res, dig, lat, dt
@@ -697,6 +705,8 @@ def run_serve(args):
     if args.serve_ledger:
         # host service time per call kind (claim to completion), microseconds
         led = ctx.ledger(reset=True)
+        if args.serve_ledger_out:
+            np.save(args.serve_ledger_out, led)
         svc = ((led[:, 5] >> np.uint64(8)).astype(np.int64) - led[:, 4].astype(np.int64)) / 1e3
         host_us = {}
         for nr, nm in ((g.NR_PREAD64, "pread"), (g.NR_PWRITE64, "pwrite"), (g.NR_MMAP, "mmap"),
@@ -719,7 +729,8 @@ def run_serve(args):
                                "mmap/madvise release (2 MiB of a 16 GiB arena) jobs, "
                                "10/60/30%%" % args.serve_rate,
                    "jobs": len(js.kind), "warmup_jobs": warm, "max_inflight": args.serve_inflight,
-                   "form": "persistent (continuous batching)"},
+                   "form": "persistent (continuous batching)",
+                   "persistent_workgroups": args.serve_grid or 64},
         "latency_us_p50": round(float(np.percentile(lat_s, 50)), 1),
         "latency_us_p99": round(float(np.percentile(lat_s, 99)), 1),
         "offered_jobs_per_s": args.serve_rate,

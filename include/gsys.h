@@ -408,7 +408,11 @@ typedef struct gsys_job {
  *   jobs_dev / jobs_host: the same gsys_job[n] in a registered host buffer
  *             (filled by the caller; done / result are written here)
  *   staging   registered host buffer, 2 MiB per work-group (the persistent
- *             grid shrinks to fit; 0 = as many as are resident)
+ *             grid shrinks to fit)
+ *   grid      persistent work-groups; 0 = 64.  Every work-group waiting for
+ *             work polls host memory, and a few hundred of them slow the host
+ *             pool's calls enough to tip a 20k jobs/s stream into a standing
+ *             backlog; 32-64 keep it out of it.
  * Blocks until every job is done (or timeout_ns, 0 = 120 s: -ETIMEDOUT).
  * Errors: -EINVAL, -EFAULT, -ENODEV, -ETIMEDOUT.
  */

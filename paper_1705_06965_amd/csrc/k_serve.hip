@@ -47,6 +47,9 @@ constexpr uint32_t kPiece = 1u << 20;          // scan read size (256 blocks of 
 constexpr uint32_t kBlock = 4096;
 constexpr uint64_t kRelBytes = 2ull << 20;
 constexpr uint64_t kSplitMiB = 16;             // persistent form: default scan task size
+// Default persistent grid: work-groups waiting for work poll host memory,
+// and a few hundred of them slow the host pool's calls (see gsys_serve_run).
+constexpr uint32_t kServeGrid = 64;
 
 // Per-job progress of the persistent form (device memory, one per job).
 struct JobState {
@@ -379,7 +382,8 @@ int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_h
       return -ENODEV;
     }
     const uint64_t fit = staging_bytes / (2ull * kPiece);
-    if (!grid || grid > res) grid = res;
+    if (!grid) grid = kServeGrid;
+    if (grid > res) grid = res;
     if (grid > fit) grid = (uint32_t)fit;
     void* args[] = {&A};
     if (int e = gsys_internal::launch(ctx, (const void*)serve_persistent, grid, kWG, lds, args, s)) {
