@@ -19,6 +19,9 @@ namespace gsys_k {
 
 using namespace gsys;
 
+// Default persistent grid (work-groups); see gsys_fnv4k.
+constexpr uint32_t kPersistentGrid = 128;
+
 struct FnvArgs {
   gsys_dev_ctx c;
   const uint64_t* offsets;
@@ -241,6 +244,9 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
     if ((uint64_t)grid > nb) grid = (uint32_t)nb;
     const uint32_t req = gsys_internal::persistent_grid_override(ctx);
     if (req && req < grid) grid = req;
+    // waiting work-groups poll host memory: no more of them than keep the
+    // host pool and the link busy
+    if (!req && grid > kPersistentGrid) grid = kPersistentGrid;
     if (staging_bytes < stage_bytes) {
       // staging ring: two batch buffers per resident work-group
       A.ring = 1;
