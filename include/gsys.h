@@ -212,7 +212,12 @@ typedef struct gsys_stats {
     uint64_t doorbell_sleeps;   /* times a poller blocked on the doorbell        */
 } gsys_stats;
 
-/* Snapshot (and optionally reset) the counters. */
+/*
+ * Snapshot the counters since the last reset; reset != 0 makes this
+ * snapshot the new zero.  Each poller counts in its own block and the
+ * snapshot sums them, so counts from calls still being completed may land
+ * in the next snapshot.  retired_lo and claimed are read, never reset.
+ */
 int gsys_stats_get(gsys_ctx *ctx, gsys_stats *out, int reset);
 
 /*
