@@ -92,6 +92,23 @@ def test_mix_matches_oracle(gs, mix, tmpdata, form):
     assert (lat != np.uint64(2**64 - 1)).all()
 
 
+def test_default_grid_matches_oracle(gs, mix, tmpdata):
+    """The library's default persistent grid (grid 0: 64 work-groups) with
+    staging for 128: results equal the oracle's."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    out_path = os.path.join(tmpdata, "serve_out_default_grid.bin")
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("serve default grid, jobs", sr.n)
+    res, dig, lat = sr.run(g.PERSISTENT, max_inflight=256, grid=0,
+                           staging_bytes=(2 << 20) * 128)
+    sr.close()
+    counts = check_outputs(sr, js, res, dig, in_path, out_path, "persistent")
+    assert min(counts) > 0
+    assert (lat != np.uint64(2**64 - 1)).all()
+
+
 def test_jobs_alone_equal_in_mix(gs, mix, tmpdata):
     g, ctx = gs
     from paper_1705_06965_amd.serve import ServeRun
