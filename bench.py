@@ -46,6 +46,8 @@ def parse():
                     help="host pollers (-1: the autotuned value, 0: cores - 1)")
     ap.add_argument("--no-tuned", action="store_true",
                     help="sweep: ignore the autotuned knobs and use the defaults")
+    ap.add_argument("--stripe", type=int, default=0,
+                    help="sweep: tickets a poller takes per stripe (0 = the library default, 8)")
     ap.add_argument("--staging-mib", type=int, default=0,
                     help="persistent form: staging ring size (0 = one slot per item)")
     ap.add_argument("--only", default="", help="profiling aid: 'plain' or 'persistent' only")
@@ -178,7 +180,8 @@ def main():
         tp["service_threads"] = args.service_threads
     ctx = g.Context(ring_slots=tp["ring_slots"], service_threads=tp["service_threads"],
                     coalesce_max=tp["coalesce_max"], coalesce_window_ns=tp["coalesce_window_ns"],
-                    sleep_max=tp["sleep_max"], device_timeout_ns=60_000_000_000)
+                    sleep_max=tp["sleep_max"], stripe=max(0, args.stripe),
+                    device_timeout_ns=60_000_000_000)
     r = FnvRunner(ctx, path, offs, ITEM, wg_size=tp["wg_size"],
                   staging_bytes=args.staging_mib << 20)
     rp = r if (not args.staging_mib and tp["wg_size"] == WG) else \
@@ -308,6 +311,7 @@ def main():
                    len(os.sched_getaffinity(0)) - 1,
                    "staging_bytes": r.staging_bytes,
                    "tuned": {k: v for k, v in tp.items()},
+                   "stripe": int(ctx.cfg.stripe) or 8,
                    "ring_slots": int(ctx.cfg.ring_slots)},
         "pread_GBps": round(gbps, 2),
         "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
