@@ -311,7 +311,8 @@ def main():
                    len(os.sched_getaffinity(0)) - 1,
                    "staging_bytes": r.staging_bytes,
                    "tuned": {k: v for k, v in tp.items()},
-                   "stripe": int(ctx.cfg.stripe) or 8,
+                   "stripe": min(64, max(int(ctx.cfg.stripe) or 8,
+                                         min(64, int(ctx.cfg.coalesce_max)))),
                    "ring_slots": int(ctx.cfg.ring_slots)},
         "pread_GBps": round(gbps, 2),
         "link_frac": round(gbps / LINK_PEAK_GBPS, 4),

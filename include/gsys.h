@@ -53,7 +53,8 @@ typedef struct gsys_config {
                                     mask - 1, at least 1)                            */
     uint32_t coalesce_max;       /* K: max calls per coalesced bundle (0/1 = off)     */
     uint32_t coalesce_window_ns; /* T: how long a poller waits to fill a bundle       */
-    uint32_t stripe;             /* tickets per poller stripe (0 = 8)                 */
+    uint32_t stripe;             /* tickets per poller stripe (0 = 8; at least K when
+                                    coalescing, at most 64)                          */
     uint32_t flags;              /* GSYS_CFG_*                                        */
     uint64_t arena_bytes;        /* reserved address range for GPU mmap (0 = none)    */
     uint64_t device_timeout_ns;  /* GPU watchdog on every wait (0 = 30 s)             */
