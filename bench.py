@@ -27,8 +27,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# the open / read / close word search kernel is switched off in the library
-OPEN_FORM_ENABLED = False
 LINK_PEAK_GBPS = 63.0        # PCIe 5.0 x16: 32 GT/s x 16 lanes x 128/130 / 8, per direction
 N_WG, WG, ITEM = 1024, 256, 4096
 FILE_BYTES = 1 << 30
@@ -1139,11 +1137,6 @@ def run_wordopen(args):
     pieces and closed (work-group granularity, relaxed).  value = scanned
     file bytes per second; the pread form on the same corpus is timed
     beside it."""
-    if not OPEN_FORM_ENABLED:
-        print("the open / read / close word search is switched off (gsys_wordcount_open "
-              "returns -ENOSYS): its first GPU run did not finish and the cause is not found",
-              file=sys.stderr)
-        sys.exit(2)
     import numpy as np
     import torch
     import synth

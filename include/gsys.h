@@ -449,8 +449,8 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
                 uint64_t out_ret, uint32_t cell, uint32_t wg_size, void *stream);
 
 /*
- * The wordcount as section 7.1 issues it: work-group w takes files w, w +
- * grid, ...; for each it calls openat(dirfd, paths + f * GSYS_PATH_MAX,
+ * The wordcount as section 7.1 issues it: persistent work-groups take files
+ * f from a device counter; for each one calls openat(dirfd, paths + f * GSYS_PATH_MAX,
  * O_RDONLY), read(fd, buf, chunk) until a read returns fewer than chunk
  * bytes (the end of a regular file), and close(fd), all at work-group
  * granularity with relaxed ordering (the next read is in flight while the
@@ -466,16 +466,20 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
  *   staging  registered host buffer; each resident work-group uses two
  *            buffers of chunk + 16,496 bytes rounded up to 16 (the grid
  *            shrinks to fit)
+ *   progress 0, or a registered host buffer of progress_groups x 16 bytes
+ *            (the grid shrinks to progress_groups): work-group w keeps
+ *            [2w] = (file + 1) << 32 | phase (1 openat, 2 waiting for a
+ *            read, 3 scanning, 4 close, 5 no more files) and [2w + 1] =
+ *            piece << 32 | low 32 bits of the ticket waited for, stored at
+ *            system scope so the host can read them while the kernel runs
  * Asynchronous on `stream`; gsys_wait drains the host side.  Errors:
- * -EINVAL, -EFAULT (paths or staging not registered), -ENODEV.
- * Currently switched off: returns -ENOSYS after checking its arguments (a
- * GPU run did not finish and the cause is not yet known); the host side of
- * openat / read / close is available to kernels through gsys_allow_fd.
+ * -EINVAL, -EFAULT (paths, staging or progress not registered), -ENODEV.
  */
 int gsys_wordcount_open(gsys_ctx *ctx, int dirfd, uint64_t paths, uint32_t nfiles,
                         uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts,
                         uint64_t file_ret, uint32_t chunk, uint64_t staging,
-                        uint64_t staging_bytes, void *stream);
+                        uint64_t staging_bytes, uint64_t progress, uint32_t progress_groups,
+                        void *stream);
 
 /*
  * Block permutation written out with pwrite: the ordering / blocking

@@ -130,7 +130,8 @@ _SIGS = {
                               C.c_uint32, C.c_uint32, _P]),
     "gsys_wordcount_open": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
                                       C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
-                                      C.c_uint32, C.c_uint64, C.c_uint64, _P]),
+                                      C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64,
+                                      C.c_uint32, _P]),
     "gsys_permute": (C.c_int, [_P, C.c_int, C.c_uint64, _P, _P, C.c_uint64, C.c_uint32,
                                C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P]),
     "gsys_file_roundtrip": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,

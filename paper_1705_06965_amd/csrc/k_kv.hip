@@ -136,12 +136,16 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
     const bool have = got >= 0;
     const uint32_t n = (uint32_t)__syncthreads_count(have);
     if (n == 0) {
-      // empty socket: back off before asking again
+      // empty socket: back off before asking again.  The barrier ends the
+      // thread-0 region before the loop's back edge, where the next
+      // iteration opens with another one (two such regions joined across a
+      // back edge can leave thread 0 out of the following barrier).
       if (tid == 0) {
         const uint32_t reps = 1u << min(idle, 8u);
         for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(8);
       }
       ++idle;
+      __syncthreads();
       continue;
     }
     idle = 0;

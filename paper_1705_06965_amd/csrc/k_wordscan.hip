@@ -128,16 +128,19 @@ __device__ Ticket issue_chunk(const WsArgs& A, uint32_t ci, uint64_t slot) {
   return tk;
 }
 
-// Load this lane's share of the sub-block at range byte sb0 (staging bytes
-// [sb0, sb0 + kCopy) from stg, of which `lim` are inside the buffer) into
-// registers.
-__device__ __forceinline__ void load_sub(const uint8_t* stg, uint32_t lim, uint32_t sb0,
-                                         uint4 (&v)[kPerLane]) {
+// Load this lane's share of the sub-block at staging byte sb0 (bytes
+// [sb0, sb0 + kCopy) from stg) into registers.  Only 16-byte vectors that lie
+// inside the buffer (`lim` bytes from stg) and start before `data` (the end of
+// the bytes the call returned) cross the host link; the rest read as spaces,
+// which the scan treats as delimiters, as it does every position past the
+// valid extent.
+__device__ __forceinline__ void load_sub(const uint8_t* stg, uint32_t lim, uint32_t data,
+                                         uint32_t sb0, uint4 (&v)[kPerLane]) {
 #pragma unroll
   for (uint32_t k = 0; k < kPerLane; ++k) {
     const uint32_t i = threadIdx.x + k * kWG;
     v[k] = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
-    if (i < kCopyVec && sb0 + i * 16 + 16 <= lim)
+    if (i < kCopyVec && sb0 + i * 16 + 16 <= lim && sb0 + i * 16 < data)
       v[k] = to_uint4(ldg16((uint64_t)(stg + sb0 + i * 16)));
   }
 }
@@ -151,8 +154,10 @@ __device__ __forceinline__ void load_sub(const uint8_t* stg, uint32_t lim, uint3
 __device__ void scan_range(const WsArgs& A, Shared& S, uint32_t file, const uint8_t* stg,
                            uint32_t lim, uint32_t own_total, int64_t ext, bool lb_ok) {
   const uint32_t wave = threadIdx.x >> 6;
+  // staging bytes that hold data: the look-behind byte and positions < ext
+  const uint32_t data = (uint32_t)min<int64_t>((int64_t)lim, (int64_t)kHead + max<int64_t>(ext, 0));
   uint4 v[kPerLane];
-  if (own_total) load_sub(stg, lim, 0, v);
+  if (own_total) load_sub(stg, lim, data, 0, v);
   for (uint32_t sb0 = 0; sb0 < own_total; sb0 += kSB) {
     // LDS buf[i] = staging[sb0 + i], i.e. chunk position sb0 + i - kHead
 #pragma unroll
@@ -161,7 +166,7 @@ __device__ void scan_range(const WsArgs& A, Shared& S, uint32_t file, const uint
       if (i < kCopyVec) *reinterpret_cast<uint4*>(S.buf + i * 16) = v[k];
     }
     __syncthreads();
-    if (sb0 + kSB < own_total) load_sub(stg, lim, sb0 + kSB, v);  // in flight during the scan
+    if (sb0 + kSB < own_total) load_sub(stg, lim, data, sb0 + kSB, v);  // in flight during the scan
     const int64_t sb_ext = ext - (int64_t)sb0;                    // valid positions: p < sb_ext
     const uint32_t own = min(kSB, own_total - sb0);               // tokens may start at p < own
     const uint32_t p0 = threadIdx.x * kSeg;
@@ -252,7 +257,15 @@ __device__ void scan_chunk(const WsArgs& A, Shared& S, uint32_t ci, uint64_t slo
   scan_range(A, S, ch.file, stg, A.cbuf, ch.len, ext, lb_ok);
 }
 
+// The next work item for the whole work-group.  The leading barrier closes
+// whatever thread-0-only code ran before it (a weak blocking call's wait, a
+// result store): without it such code joins the atomic below into one
+// thread-0 region across the loop's back edge, and the compiled loop then
+// lets the other work-items of thread 0's wavefront pass the barrier below
+// before thread 0 has taken the item, read a stale S.next, and never leave
+// the loop.
 __device__ __forceinline__ uint32_t grab(const WsArgs& A, Shared& S) {
+  __syncthreads();
   if (threadIdx.x == 0) S.next = atomicAdd(A.work, 1u);
   __syncthreads();
   const uint32_t v = S.next;
@@ -311,7 +324,6 @@ __global__ __launch_bounds__(kWG) void wordscan_plain(WsArgs A) {
 // carry's 16 bytes sit at [kOpenHead - 16, kOpenHead), the byte before them
 // at kOpenHead - 17, each piece's data on a fresh 64-byte line.
 
-constexpr int kOpenKernelEnabled = 0;
 constexpr uint32_t kOpenHead = 64;
 constexpr uint32_t kCarry = kOverlap;  // deferred bytes
 
@@ -319,14 +331,28 @@ struct WoArgs {
   WsArgs w;             // queries, counts, staging (2 buffers of w.cbuf per group)
   uint64_t paths;       // registered host buffer: nfiles x GSYS_PATH_MAX bytes
   int64_t* file_ret;    // device: bytes read per file, or -errno
+  uint64_t progress;    // host-visible: 2 x u64 per work-group, or 0
   uint32_t nfiles;
   uint32_t chunk;       // bytes per read()
   int32_t dirfd;
 };
 
+// Where a work-group is (thread 0 only): word 0 = (file + 1) << 32 | phase,
+// word 1 = piece << 32 | low 32 bits of the last call's ticket.  Written
+// with system-scope stores, so the host can read it while the kernel runs.
+enum : uint32_t { kPhOpen = 1, kPhRead = 2, kPhScan = 3, kPhClose = 4, kPhDone = 5 };
+__device__ __forceinline__ void progress(const WoArgs& A, uint32_t f, uint32_t phase,
+                                         uint32_t piece, uint64_t ticket) {
+  if (!A.progress || threadIdx.x != 0) return;
+  uint64_t* p = reinterpret_cast<uint64_t*>(A.progress) + 2ull * blockIdx.x;
+  st_sys(p + 1, ((uint64_t)piece << 32) | (uint32_t)ticket);
+  st_sys(p, ((uint64_t)(f + 1) << 32) | phase);
+}
+
 __device__ void open_and_scan(const WoArgs& A, Shared& S, uint32_t f) {
   const gsys_dev_ctx& c = A.w.c;
   const uint64_t base = A.w.staging + (uint64_t)blockIdx.x * 2 * A.w.cbuf;
+  progress(A, f, kPhOpen, 0, 0);
   // openat: a consumer call, blocking: every work-item needs the descriptor
   const int64_t fd = call_wg<O::Relaxed, B::Blocking>(
       c, GSYS_NR_OPENAT, 0,
@@ -344,10 +370,11 @@ __device__ void open_and_scan(const WoArgs& A, Shared& S, uint32_t f) {
     return tk;
   };
   int64_t total = 0, err = 0;
-  uint32_t b = 0;
+  uint32_t b = 0, piece = 0;
   bool first = true;
   Ticket tk = issue(0);
   for (;;) {
+    progress(A, f, kPhRead, piece, tk.t);
     const int64_t r = wait_wg(c, tk);
     if (r < 0) {
       err = r;
@@ -369,15 +396,18 @@ __device__ void open_and_scan(const WoArgs& A, Shared& S, uint32_t f) {
     const int64_t ext = (int64_t)carry + r;
     const uint32_t own = end ? (uint32_t)ext : (uint32_t)(ext - kCarry);
     const uint32_t p0 = kOpenHead - carry;  // buffer byte of range position 0
+    progress(A, f, kPhScan, piece, tk.t);
     scan_range(A.w, S, f, reinterpret_cast<const uint8_t*>(buf + p0 - kHead),
                A.w.cbuf - (p0 - kHead), own, ext, !first);
     total += r;
     if (end) break;
     b ^= 1u;
     first = false;
+    ++piece;
   }
   // close: a producer call (every work-item is done with the descriptor);
   // the designated caller records the file's result
+  progress(A, f, kPhClose, piece, 0);
   const int64_t rc = call_wg<O::Relaxed, B::Blocking>(c, GSYS_NR_CLOSE, 0,
                                                       Args6{{(uint64_t)fd, 0, 0, 0, 0, 0}});
   if (threadIdx.x == 0) A.file_ret[f] = err ? err : (rc < 0 ? rc : total);
@@ -386,11 +416,16 @@ __device__ void open_and_scan(const WoArgs& A, Shared& S, uint32_t f) {
 __global__ __launch_bounds__(kWG) void wordopen_persistent(WoArgs A) {
   __shared__ Shared S;
   build_table(A.w, S);
+  uint32_t last = ~0u;
   for (;;) {
+    // grab() opens with a barrier: the thread-0-only result store that ends
+    // open_and_scan never shares a region with the next grab's atomic
     const uint32_t f = grab(A.w, S);
     if (f >= A.nfiles) break;
     open_and_scan(A, S, f);
+    last = f;
   }
+  progress(A, last, kPhDone, 0, 0);
 }
 
 __global__ void zero_u32(uint32_t* p, uint64_t n) {
@@ -449,14 +484,11 @@ int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
 int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfiles,
                         uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts,
                         uint64_t file_ret, uint32_t chunk, uint64_t staging,
-                        uint64_t staging_bytes, void* stream) {
+                        uint64_t staging_bytes, uint64_t progress, uint32_t progress_groups,
+                        void* stream) {
   if (!ctx || !queries || !qlens || !counts || !file_ret) return -EINVAL;
   if (nq == 0 || nq > kMaxQ) return -EINVAL;
   if (chunk < 64 || chunk % 64 || chunk > (64u << 20)) return -EINVAL;
-  // Switched off: the first GPU run of this kernel (64-byte reads, 40
-  // work-groups) did not finish within 120 s, and the cause has not been
-  // found; the launch below stays unreachable until it is.
-  if (kOpenKernelEnabled == 0) return -ENOSYS;
   if (!nfiles) return 0;
   if (gsys_internal::check_host_range(ctx, paths, (uint64_t)nfiles * GSYS_PATH_MAX)) return -EFAULT;
   // carry head + data + the scanner's window past the last valid byte
@@ -464,6 +496,9 @@ int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
   const uint64_t per_wg = 2ull * cbuf;
   if (staging_bytes < per_wg) return -EINVAL;
   if (gsys_internal::check_host_range(ctx, staging, staging_bytes)) return -EFAULT;
+  if (progress && (!progress_groups ||
+                   gsys_internal::check_host_range(ctx, progress, 16ull * progress_groups)))
+    return progress_groups ? -EFAULT : -EINVAL;
   hipStream_t s = (hipStream_t)stream;
   WoArgs A;
   if (int e = gsys_device_ctx(ctx, &A.w.c)) return e;
@@ -491,6 +526,8 @@ int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
   grid = (uint32_t)std::min<uint64_t>({(uint64_t)grid, staging_bytes / per_wg, (uint64_t)nfiles});
   const uint32_t req = gsys_internal::persistent_grid_override(ctx);
   if (req && req < grid) grid = req;
+  if (progress && progress_groups < grid) grid = progress_groups;  // one record per work-group
+  A.progress = progress;
   void* args[] = {&A};
   return gsys_internal::launch(ctx, (const void*)wordopen_persistent, grid, kWG, 0, args, s);
 }

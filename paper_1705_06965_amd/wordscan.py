@@ -136,8 +136,13 @@ class WordOpenRunner:
         self.qlens = torch.from_numpy(ql.view(np.int32)).to(device)
         self.counts = torch.zeros(max(1, self.nfiles * self.nq), dtype=torch.int32, device=device)
         self.file_ret = torch.zeros(max(1, self.nfiles), dtype=torch.int64, device=device)
-        self.staging_bytes = 2 * open_buffer_bytes(chunk) * max(1, min(groups, self.nfiles))
+        self.groups = max(1, min(groups, self.nfiles))
+        self.staging_bytes = 2 * open_buffer_bytes(chunk) * self.groups
         self.staging = ctx.host_alloc(self.staging_bytes)
+        # per work-group progress records (host memory the kernel writes at
+        # system scope): where each work-group is, readable while it runs
+        self.progress = ctx.host_alloc(16 * self.groups)
+        self.progress.array[:16 * self.groups] = 0
 
     def launch(self, stream=None):
         return check(lib.gsys_wordcount_open(self.ctx.h, self.dirfd, self.paths.dev, self.nfiles,
@@ -145,12 +150,33 @@ class WordOpenRunner:
                                              self.nq, self.counts.data_ptr(),
                                              self.file_ret.data_ptr(), self.chunk,
                                              self.staging.dev, self.staging_bytes,
+                                             self.progress.dev, self.groups,
                                              _stream(stream)), "gsys_wordcount_open")
 
-    def run(self, stream=None):
-        """(counts[f, q], bytes read per file or -errno)."""
+    def progress_records(self):
+        """One (file or -1, phase, piece, ticket low bits) per work-group."""
+        w = self.progress.array[:16 * self.groups].view(np.uint64).reshape(self.groups, 2)
+        return [(int(a >> 32) - 1, int(a & 0xffffffff), int(b >> 32), int(b & 0xffffffff))
+                for a, b in w.tolist()]
+
+    def run(self, stream=None, timeout_s: float = 0.0):
+        """(counts[f, q], bytes read per file or -errno).  With timeout_s the
+        launch is awaited with a host-side deadline; past it the work-groups'
+        progress records are raised in the error."""
+        import time
         self.file_ret.fill_(-12345)
+        self.progress.array[:16 * self.groups] = 0
+        ev = self.torch.cuda.Event()
         self.launch(stream)
+        ev.record()
+        if timeout_s:
+            t0 = time.monotonic()
+            while not ev.query():
+                if time.monotonic() - t0 > timeout_s:
+                    raise TimeoutError("open-form launch still running after %.0f s; "
+                                       "progress (file, phase, piece, ticket) per work-group: %r"
+                                       % (timeout_s, self.progress_records()))
+                time.sleep(0.002)
         self.torch.cuda.synchronize()
         rc = self.ctx.wait(60_000_000_000)
         if rc:
@@ -167,3 +193,4 @@ class WordOpenRunner:
         os.close(self.dirfd)
         self.paths.free()
         self.staging.free()
+        self.progress.free()
