@@ -394,10 +394,9 @@ typedef struct gsys_job {
 } gsys_job;
 
 /*
- * Serving (continuous batching): run n jobs arriving at arrival_ns[i] after
- * the start (open loop).  A job is admitted once it has arrived and fewer
- * than max_inflight admitted jobs are unfinished; latency_ns[i] is the time
- * from its scheduled arrival to the host seeing it done (queueing included).
+ * Serving (continuous batching, sections 2 and 6: long-lived work-groups
+ * keep taking work while the host services earlier calls): run n jobs
+ * arriving at arrival_ns[i] after the start (open loop).
  *
  * Scan jobs pread their range in 1 MiB pieces (the next piece is prefetched
  * with a non-blocking call) and store FNV-1a-64 of every 4 KiB block to
@@ -408,29 +407,58 @@ typedef struct gsys_job {
  * madvise(MADV_DONTNEED), pwrite the first 64 bytes of page 0 to off + 64
  * (zeros) and munmap.  All calls are work-group granularity, relaxed.
  *
- *   form      GSYS_PERSISTENT: resident work-groups claim tasks in job order
- *             as jobs are posted; a scan longer than 16 MiB (environment
- *             GSYS_SERVE_SPLIT_MIB overrides the size, 0 = never split) is
- *             cut into tasks of that size run by different work-groups, and
- *             the work-group finishing its last task publishes the job
- *             (result: bytes read, or the first -errno of any task);
- *             GSYS_PLAIN: one single-work-group launch per job on `stream`,
- *             in arrival order
- *   jobs_dev / jobs_host: the same gsys_job[n] in a registered host buffer
- *             (filled by the caller; done / result are written here)
- *   staging   registered host buffer, 2 MiB per work-group (the persistent
- *             grid shrinks to fit)
- *   grid      persistent work-groups; 0 = 64.  Every work-group waiting for
- *             work polls host memory, and a few hundred of them slow the host
- *             pool's calls enough to tip a 20k jobs/s stream into a standing
- *             backlog; 32-64 keep it out of it.
- * Blocks until every job is done (or timeout_ns, 0 = 120 s: -ETIMEDOUT).
- * Errors: -EINVAL, -EFAULT, -ENODEV, -ETIMEDOUT.
+ * Admission: a job that has arrived is posted while fewer than max_inflight
+ * posted jobs are unfinished and, when max_inflight_bytes is not 0, while
+ * its buffer bytes fit beside theirs (a job larger than the whole budget is
+ * posted only when nothing else is in flight).  A job's buffer bytes are
+ * what it holds while in flight: 2 MiB of staging per scan task, its length
+ * rounded up to 4 KiB for a pwrite, 2 MiB of arena for a release.
+ * latency_ns[i] is the time from job i's scheduled arrival to the host
+ * seeing it done (queueing included).
+ *
+ * Every job record is checked before anything is launched; a record that
+ * fails a check makes the call return -EINVAL with nothing run: kind is one
+ * of GSYS_JOB_*; scan: len a multiple of 4096 and src + len / 4096 <=
+ * n_digests; pwrite: len <= 1 MiB and src + len <= content_bytes; release:
+ * len < (the context's arena bytes) / 2 MiB and page < 512.
  */
-int gsys_serve_run(gsys_ctx *ctx, uint32_t form, uint64_t jobs_dev, void *jobs_host, uint32_t n,
-                   const uint64_t *arrival_ns, uint32_t max_inflight, uint64_t digests,
-                   uint64_t content, uint64_t staging, uint64_t staging_bytes, uint32_t grid,
-                   uint64_t timeout_ns, uint64_t *latency_ns, void *stream);
+typedef struct gsys_serve_params {
+    uint32_t form;               /* GSYS_PERSISTENT: resident work-groups claim tasks in
+                                    job order as jobs are posted; a scan longer than 16 MiB
+                                    (environment GSYS_SERVE_SPLIT_MIB overrides the size,
+                                    0 = never split) is cut into tasks of that size run by
+                                    different work-groups, and the work-group finishing its
+                                    last task publishes the job (result: bytes read, or the
+                                    first -errno of any task).  GSYS_PLAIN: one
+                                    single-work-group launch per job on `stream`, in
+                                    arrival order                                        */
+    uint32_t n;                  /* jobs                                                   */
+    uint64_t jobs_dev;           /* gsys_job[n] in a registered host buffer (GPU address) */
+    void    *jobs_host;          /* the same records, host address; filled by the caller,
+                                    done / result are written here                        */
+    const uint64_t *arrival_ns;  /* host uint64[n], non-decreasing                         */
+    uint64_t *latency_ns;        /* host uint64[n], out                                    */
+    uint32_t max_inflight;       /* >= 1                                                   */
+    uint32_t grid;               /* persistent work-groups; 0 = 64.  Every work-group
+                                    waiting for work polls host memory, and a few hundred of
+                                    them slow the host pool's calls enough to tip a 20k
+                                    jobs/s stream into a standing backlog                  */
+    uint64_t max_inflight_bytes; /* 0 = no byte budget                                     */
+    uint64_t digests;            /* device uint64[n_digests]                               */
+    uint64_t n_digests;
+    uint64_t content;            /* device bytes[content_bytes]                            */
+    uint64_t content_bytes;
+    uint64_t staging;            /* registered host buffer, 2 MiB per work-group (the
+                                    persistent grid shrinks to fit; at least 2 MiB)        */
+    uint64_t staging_bytes;
+    uint64_t timeout_ns;         /* 0 = 120 s                                              */
+    uint64_t peak_inflight_bytes;/* out: the most buffer bytes admitted at once            */
+} gsys_serve_params;
+
+/* Blocks until every job is done (or timeout_ns: -ETIMEDOUT).  Allocates the
+ * persistent form's per-job state (32 bytes per job) in device memory for
+ * the call.  Errors: -EINVAL, -EFAULT, -ENOMEM, -ENODEV, -ETIMEDOUT. */
+int gsys_serve_run(gsys_ctx *ctx, gsys_serve_params *params, void *stream);
 
 /*
  * Visibility canary for producer calls (section 4.1 ordering): work-item i

@@ -84,6 +84,17 @@ class gsys_dev_ctx(C.Structure):
                 ("doorbell", C.c_uint64), ("sleepers", C.c_uint64)]
 
 
+class gsys_serve_params(C.Structure):
+    _fields_ = [("form", C.c_uint32), ("n", C.c_uint32), ("jobs_dev", C.c_uint64),
+                ("jobs_host", C.c_void_p), ("arrival_ns", C.c_void_p),
+                ("latency_ns", C.c_void_p), ("max_inflight", C.c_uint32), ("grid", C.c_uint32),
+                ("max_inflight_bytes", C.c_uint64), ("digests", C.c_uint64),
+                ("n_digests", C.c_uint64), ("content", C.c_uint64),
+                ("content_bytes", C.c_uint64), ("staging", C.c_uint64),
+                ("staging_bytes", C.c_uint64), ("timeout_ns", C.c_uint64),
+                ("peak_inflight_bytes", C.c_uint64)]
+
+
 class gsys_launch_desc(C.Structure):
     _fields_ = [("kernel", C.c_void_p), ("grid", C.c_uint32 * 3), ("block", C.c_uint32 * 3),
                 ("lds_bytes", C.c_uint32), ("mode", C.c_uint32), ("args", C.c_void_p)]
@@ -123,9 +134,7 @@ _SIGS = {
     "gsys_kv_loadgen": (C.c_int64, [C.c_uint32, _P, C.c_uint32, C.c_uint64, C.c_uint32,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _P, C.c_uint32, _P, _P,
                                     _P]),
-    "gsys_serve_run": (C.c_int, [_P, C.c_uint32, C.c_uint64, _P, C.c_uint32, _P, C.c_uint32,
-                                 C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
-                                 C.c_uint64, _P, _P]),
+    "gsys_serve_run": (C.c_int, [_P, C.POINTER(gsys_serve_params), _P]),
     "gsys_canary": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                               C.c_uint32, C.c_uint32, _P]),
     "gsys_wordcount_open": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,

@@ -99,7 +99,10 @@ struct gsys_ctx {
   uint64_t D = 0, C = 0;
   gsys_slot* ring = nullptr;       // host view
   gsys_comp* comp = nullptr;       // host view
-  uint64_t* host_words = nullptr;  // [0] retired_lo (own 256-byte line); NO_DEVICE: [32] tail
+  // host-coherent page: [0] retired_lo, [32] the ticket counter of NO_DEVICE
+  // contexts, [64] sleeping pollers, [96..97] serving control words; each
+  // group on its own 256-byte line
+  uint64_t* host_words = nullptr;
   gsys_slot* ring_dev = nullptr;
   gsys_comp* comp_dev = nullptr;
   uint64_t* retired_lo_dev = nullptr;
@@ -117,8 +120,6 @@ struct gsys_ctx {
   int cu_count = 0;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
-  void* ctl_host = nullptr;
-  void* ctl_dev = nullptr;
   // doorbell (GSYS_CFG_DOORBELL)
   gsys_host::Doorbell* db = nullptr;
   uint64_t* sleepers_dev = nullptr;  // host_words[64] as the GPU sees it
@@ -270,7 +271,6 @@ void destroy(gsys_ctx* c) {
   host_coherent_free(c, c->ring);
   host_coherent_free(c, c->comp);
   host_coherent_free(c, c->host_words);
-  host_coherent_free(c, c->ctl_host);
   if (c->arena) munmap(c->arena, c->arena_bytes);
   delete c;
 }
@@ -749,14 +749,13 @@ uint32_t persistent_grid_override(gsys_ctx* c) { return c->grid_override; }
 uint64_t ticks_per_ms(gsys_ctx* c) { return c->wall_khz; }
 
 int control_page(gsys_ctx* c, void** host, uint64_t* dev) {
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!c->ctl_host) {
-    if (int e = host_coherent(c, 4096, &c->ctl_host, &c->ctl_dev)) return e;
-  }
-  *host = c->ctl_host;
-  *dev = (uint64_t)c->ctl_dev;
+  // words 96 and 97 of the context's host-coherent page (their own line)
+  *host = c->host_words + 96;
+  *dev = (uint64_t)(c->retired_lo_dev + 96);
   return 0;
 }
+
+bool no_device(gsys_ctx* c) { return c->no_device; }
 
 uint64_t hash_words(std::initializer_list<uint64_t> w) {
   uint64_t h = 0x9e3779b97f4a7c15ull;

@@ -312,97 +312,119 @@ __global__ void zero_u32(unsigned int* p, uint32_t n) {
   if (i < n) p[i] = 0;
 }
 
+// Per-job progress records of the persistent form, set from the job records
+// (host-coherent memory) before the launch: nothing done, the task count.
+__global__ void init_jobs(JobState* js, const gsys_job* jobs, uint32_t n, uint64_t split) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(jobs + i);
+  const uint32_t kind = (uint32_t)ld_sys(w);                            // kind | fd << 32
+  const uint64_t len = ld_sys(w + 2);
+  js[i] = JobState{0, 0, 0, tasks_of(kind, len, split), 0};
+}
+
 uint64_t now_ns() {
   timespec ts;
   clock_gettime(CLOCK_MONOTONIC, &ts);
   return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
-}  // namespace gsys_sv
+// Host buffer bytes a job holds while it is admitted and unfinished: a scan
+// task streams through its work-group's two 1 MiB staging buffers, a pwrite
+// stages its bytes, a release maps one 2 MiB arena block.
+uint64_t job_bytes(const gsys_job& J, uint64_t split) {
+  if (J.kind == GSYS_JOB_SCAN) return (uint64_t)tasks_of(J.kind, J.len, split) * 2ull * kPiece;
+  if (J.kind == GSYS_JOB_PWRITE) return (J.len + kBlock - 1) / kBlock * kBlock;
+  return kRelBytes;
+}
 
-using namespace gsys_sv;
+// Every job record is checked before anything is launched: the kernels copy
+// and store through the records' offsets without further bounds.
+int check_jobs(const gsys_job* jobs, uint32_t n, const gsys_serve_params& P, uint64_t arena_bytes) {
+  for (uint32_t i = 0; i < n; ++i) {
+    const gsys_job& J = jobs[i];
+    if (J.kind == GSYS_JOB_SCAN) {
+      if (J.len % kBlock) return -EINVAL;
+      if (J.src > P.n_digests || J.len / kBlock > P.n_digests - J.src) return -EINVAL;
+    } else if (J.kind == GSYS_JOB_PWRITE) {
+      if (J.len > kPiece) return -EINVAL;  // one staging buffer
+      if (J.src > P.content_bytes || J.len > P.content_bytes - J.src) return -EINVAL;
+    } else if (J.kind == GSYS_JOB_RELEASE) {
+      if (J.len >= arena_bytes / kRelBytes || J.page >= kRelBytes / kBlock) return -EINVAL;
+    } else {
+      return -EINVAL;
+    }
+  }
+  return 0;
+}
 
-int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_host, uint32_t n,
-                   const uint64_t* arrival_ns, uint32_t max_inflight, uint64_t digests,
-                   uint64_t content, uint64_t staging, uint64_t staging_bytes, uint32_t grid,
-                   uint64_t timeout_ns, uint64_t* latency_ns, void* stream) {
-  if (!ctx || !jobs_dev || !jobs_host || !arrival_ns || !latency_ns || !max_inflight) return -EINVAL;
-  if (form != GSYS_PLAIN && form != GSYS_PERSISTENT) return -EINVAL;
-  if (gsys_internal::check_host_range(ctx, jobs_dev, (uint64_t)n * sizeof(gsys_job))) return -EFAULT;
-  if (gsys_internal::check_host_range(ctx, staging, staging_bytes)) return -EFAULT;
-  if (staging_bytes < 2ull * kPiece) return -EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  gsys_job* jobs = (gsys_job*)jobs_host;
+// The serving loop shared by both entry points.  js: per-job state of the
+// persistent form (n records), ignored by the plain form.
+int serve_run(gsys_ctx* ctx, gsys_serve_params* P, JobState* js, hipStream_t s) {
+  const uint32_t n = P->n;
+  gsys_job* jobs = (gsys_job*)P->jobs_host;
   uint64_t* ctl_h = nullptr;
   uint64_t ctl_d = 0;
   if (int e = gsys_internal::control_page(ctx, (void**)&ctl_h, &ctl_d)) return e;
   SvArgs A;
   if (int e = gsys_device_ctx(ctx, &A.c)) return e;
-  A.jobs = (gsys_job*)jobs_dev;
+  A.jobs = (gsys_job*)P->jobs_dev;
   A.ctl = (const uint64_t*)ctl_d;
   A.cursor = (unsigned long long*)gsys_internal::kstate(ctx) + 8;
-  A.js = nullptr;
+  A.js = js;
   {
     // scan task size in MiB (0 = never split); overridable for tuning
     const char* e = getenv("GSYS_SERVE_SPLIT_MIB");
     const uint64_t mib = e && *e ? strtoull(e, nullptr, 0) : kSplitMiB;
     A.split = mib ? (mib << 20) : ~0ull;
   }
-  A.digests = (uint64_t*)digests;
-  A.content = (const uint8_t*)content;
-  A.staging = staging;
-  const uint64_t tmo = timeout_ns ? timeout_ns : 120000000000ull;
+  A.digests = (uint64_t*)P->digests;
+  A.content = (const uint8_t*)P->content;
+  A.staging = P->staging;
+  const uint64_t tmo = P->timeout_ns ? P->timeout_ns : 120000000000ull;
   A.lifetime_ticks = gsys_internal::ticks_per_ms(ctx) * (tmo / 1000000ull + 1000);
+  uint64_t* lat = P->latency_ns;
   for (uint32_t i = 0; i < n; ++i) {
     __atomic_store_n(&jobs[i].done, 0ull, __ATOMIC_RELAXED);
-    latency_ns[i] = ~0ull;
+    lat[i] = ~0ull;  // not finished yet
   }
+  P->peak_inflight_bytes = 0;
   __atomic_store_n(&ctl_h[0], 0ull, __ATOMIC_RELEASE);
   __atomic_store_n(&ctl_h[1], 0ull, __ATOMIC_RELEASE);
   hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, (unsigned int*)A.cursor, 2u);
   const uint32_t lds = (kWG / 64) * Tile<256>::kBytes;
-  JobState* js_dev = nullptr;
-  if (form == GSYS_PERSISTENT) {
-    // per-job task counts, fixed before the launch
-    std::vector<JobState> st(n ? n : 1);
-    for (uint32_t i = 0; i < n; ++i) {
-      st[i] = JobState{0, 0, 0, tasks_of(jobs[i].kind, jobs[i].len, A.split), 0};
-    }
-    if (hipMalloc((void**)&js_dev, st.size() * sizeof(JobState)) != hipSuccess) return -ENOMEM;
-    if (hipMemcpyAsync(js_dev, st.data(), st.size() * sizeof(JobState), hipMemcpyHostToDevice,
-                       s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      hipFree(js_dev);
-      return -ENODEV;
-    }
-    A.js = js_dev;
-    uint32_t res = gsys_internal::resident_grid(ctx, (const void*)serve_persistent, kWG, lds);
-    if (!res) {
-      hipFree(js_dev);
-      return -ENODEV;
-    }
-    const uint64_t fit = staging_bytes / (2ull * kPiece);
-    if (!grid) grid = kServeGrid;
+  if (P->form == GSYS_PERSISTENT) {
+    if (n) hipLaunchKernelGGL(init_jobs, dim3((n + 255) / 256), dim3(256), 0, s, js,
+                              (const gsys_job*)P->jobs_dev, n, A.split);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return -ENODEV;
+    const uint32_t res = gsys_internal::resident_grid(ctx, (const void*)serve_persistent, kWG, lds);
+    if (!res) return -ENODEV;
+    const uint64_t fit = P->staging_bytes / (2ull * kPiece);
+    uint32_t grid = P->grid ? P->grid : kServeGrid;
     if (grid > res) grid = res;
     if (grid > fit) grid = (uint32_t)fit;
     void* args[] = {&A};
-    if (int e = gsys_internal::launch(ctx, (const void*)serve_persistent, grid, kWG, lds, args, s)) {
-      hipFree(js_dev);
+    if (int e = gsys_internal::launch(ctx, (const void*)serve_persistent, grid, kWG, lds, args, s))
       return e;
-    }
   } else if (hipStreamSynchronize(s) != hipSuccess) {
     return -ENODEV;
   }
   const uint64_t t0 = now_ns();
   const uint64_t deadline = t0 + tmo;
+  const uint64_t budget = P->max_inflight_bytes;
   uint32_t posted = 0, completed = 0, oldest = 0;
+  uint64_t held = 0;  // buffer bytes of admitted, unfinished jobs
   int rc = 0;
-  std::vector<uint8_t> seen(n, 0);
   while (completed < n) {
     const uint64_t t = now_ns();
     bool progress = false;
-    while (posted < n && t0 + arrival_ns[posted] <= t && posted - completed < max_inflight) {
-      if (form == GSYS_PERSISTENT) {
+    // Admission: a job that has arrived is posted while fewer than
+    // max_inflight jobs are unfinished and its bytes fit the budget (a job
+    // larger than the whole budget is admitted alone).
+    while (posted < n && t0 + P->arrival_ns[posted] <= t && posted - completed < P->max_inflight) {
+      const uint64_t need = job_bytes(jobs[posted], A.split);
+      if (budget && held && held + need > budget) break;
+      if (P->form == GSYS_PERSISTENT) {
         __atomic_store_n(&ctl_h[0], (uint64_t)posted + 1, __ATOMIC_RELEASE);
       } else {
         SvArgs B = A;
@@ -413,20 +435,22 @@ int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_h
           break;
         }
       }
+      held += need;
+      if (held > P->peak_inflight_bytes) P->peak_inflight_bytes = held;
       ++posted;
       progress = true;
     }
     if (rc) break;
     const uint64_t t2 = now_ns();
     for (uint32_t i = oldest; i < posted; ++i) {
-      if (!seen[i] && __atomic_load_n(&jobs[i].done, __ATOMIC_ACQUIRE)) {
-        seen[i] = 1;
-        latency_ns[i] = t2 - (t0 + arrival_ns[i]);
+      if (lat[i] == ~0ull && __atomic_load_n(&jobs[i].done, __ATOMIC_ACQUIRE)) {
+        lat[i] = t2 - (t0 + P->arrival_ns[i]);
+        held -= job_bytes(jobs[i], A.split);
         ++completed;
         progress = true;
       }
     }
-    while (oldest < posted && seen[oldest]) ++oldest;
+    while (oldest < posted && lat[oldest] != ~0ull) ++oldest;
     if (t2 > deadline) {
       rc = -ETIMEDOUT;
       break;
@@ -439,6 +463,40 @@ int gsys_serve_run(gsys_ctx* ctx, uint32_t form, uint64_t jobs_dev, void* jobs_h
     fprintf(stderr, "gsys: serving stream: %s\n", hipGetErrorString(se));
     if (!rc) rc = -ENODEV;
   }
-  if (js_dev) hipFree(js_dev);
+  return rc;
+}
+
+// Argument checks shared by both entry points (no HIP call).
+int check_params(gsys_ctx* ctx, const gsys_serve_params* P) {
+  if (!ctx || !P || !P->jobs_dev || !P->jobs_host || !P->arrival_ns || !P->latency_ns ||
+      !P->max_inflight)
+    return -EINVAL;
+  if (P->form != GSYS_PLAIN && P->form != GSYS_PERSISTENT) return -EINVAL;
+  if ((P->n_digests && !P->digests) || (P->content_bytes && !P->content)) return -EINVAL;
+  if (gsys_internal::check_host_range(ctx, P->jobs_dev, (uint64_t)P->n * sizeof(gsys_job)))
+    return -EFAULT;
+  if (gsys_internal::check_host_range(ctx, P->staging, P->staging_bytes)) return -EFAULT;
+  if (P->staging_bytes < 2ull * kPiece) return -EINVAL;
+  gsys_dev_ctx c;
+  if (int e = gsys_device_ctx(ctx, &c)) return e;
+  if (int e = check_jobs((const gsys_job*)P->jobs_host, P->n, *P, c.arena ? c.arena_bytes : 0))
+    return e;
+  return 0;
+}
+
+}  // namespace gsys_sv
+
+using namespace gsys_sv;
+
+int gsys_serve_run(gsys_ctx* ctx, gsys_serve_params* P, void* stream) {
+  if (int e = check_params(ctx, P)) return e;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
+  hipStream_t s = (hipStream_t)stream;
+  JobState* js = nullptr;
+  if (P->form == GSYS_PERSISTENT &&
+      hipMalloc((void**)&js, (uint64_t)(P->n ? P->n : 1) * sizeof(JobState)) != hipSuccess)
+    return -ENOMEM;
+  const int rc = serve_run(ctx, P, js, s);
+  if (js) hipFree(js);
   return rc;
 }

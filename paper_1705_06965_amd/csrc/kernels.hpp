@@ -20,8 +20,11 @@ uint32_t resident_grid(gsys_ctx* ctx, const void* kernel, uint32_t block, uint32
 // A persistent grid size requested through GSYS_PERSISTENT_GRID (0 = none).
 uint32_t persistent_grid_override(gsys_ctx* ctx);
 uint64_t hash_words(std::initializer_list<uint64_t> w);
-// A context-owned page of host-coherent memory for driver control words.
+// Two host-coherent control words owned by the context (a 256-byte line of
+// the page set up by gsys_init; nothing is allocated here).
 int control_page(gsys_ctx* ctx, void** host, uint64_t* dev);
+// true for a CPU-only context (GSYS_CFG_NO_DEVICE): nothing may be launched.
+bool no_device(gsys_ctx* ctx);
 // Device wall-clock ticks per millisecond.
 uint64_t ticks_per_ms(gsys_ctx* ctx);
 int launch(gsys_ctx* ctx, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds,

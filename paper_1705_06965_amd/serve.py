@@ -3,11 +3,12 @@ runs it through gsys_serve_run (continuous batching on the GPU, or one launch
 per job)."""
 from __future__ import annotations
 
+import ctypes as C
 import os
 
 import numpy as np
 
-from . import FD_READ, FD_WRITE, check, lib, _stream
+from . import FD_READ, FD_WRITE, check, gsys_serve_params, lib, _stream
 
 JOB_SCAN, JOB_PWRITE, JOB_RELEASE = 0, 1, 2
 JOB_DTYPE = np.dtype([("kind", "<u4"), ("fd", "<i4"), ("off", "<u8"), ("len", "<u8"),
@@ -79,18 +80,31 @@ class ServeRun:
                                         np.zeros(16, dtype=np.uint8)).to(device)
         self.latency = np.zeros(n, dtype=np.uint64)
 
-    def run(self, form, max_inflight: int = 512, grid: int = 0, staging_bytes: int = 0,
-            timeout_ns: int = 120_000_000_000, stream=None):
+    def params(self, form, max_inflight: int = 512, grid: int = 0, staging_bytes: int = 0,
+               timeout_ns: int = 120_000_000_000, max_inflight_bytes: int = 0):
+        """The gsys_serve_params of one session (staging allocated on first use)."""
         staging_bytes = staging_bytes or (2 << 20) * 256
         if not hasattr(self, "staging") or self.staging.nbytes < staging_bytes:
             self.staging = self.ctx.host_alloc(staging_bytes)
         # reset records (results, done flags) between runs
         self.jobs.view(np.uint8)[:self.n * 64] = self.jobs_np.view(np.uint8)
-        check(lib.gsys_serve_run(self.ctx.h, form, self.jobs.dev, self.jobs.host, self.n,
-                                 self.arrival.ctypes.data, max_inflight, self.digests.data_ptr(),
-                                 self.content.data_ptr(), self.staging.dev, self.staging.nbytes,
-                                 grid, timeout_ns, self.latency.ctypes.data, _stream(stream)),
-              "gsys_serve_run")
+        return gsys_serve_params(
+            form=form, n=self.n, jobs_dev=self.jobs.dev, jobs_host=self.jobs.host,
+            arrival_ns=self.arrival.ctypes.data, latency_ns=self.latency.ctypes.data,
+            max_inflight=max_inflight, grid=grid, max_inflight_bytes=max_inflight_bytes,
+            digests=self.digests.data_ptr(), n_digests=self.digests.numel(),
+            content=self.content.data_ptr(), content_bytes=self.content.numel(),
+            staging=self.staging.dev, staging_bytes=self.staging.nbytes, timeout_ns=timeout_ns)
+
+    def run(self, form, max_inflight: int = 512, grid: int = 0, staging_bytes: int = 0,
+            timeout_ns: int = 120_000_000_000, stream=None, max_inflight_bytes: int = 0,
+            entry=None):
+        """One session through gsys_serve_run (or `entry`, an entry point of the
+        same signature); returns (results, digests, latencies)."""
+        P = self.params(form, max_inflight, grid, staging_bytes, timeout_ns, max_inflight_bytes)
+        fn = entry or lib.gsys_serve_run
+        check(fn(self.ctx.h, C.byref(P), _stream(stream)), fn.__name__)
+        self.peak_inflight_bytes = P.peak_inflight_bytes
         self.torch.cuda.synchronize()
         rc = self.ctx.wait(30_000_000_000)
         if rc:

@@ -198,3 +198,51 @@ def test_split_scans_match_oracle(gs, tmpdata, form):
     n_scan, n_pw, n_rel = check_outputs(sr, js, res, dig, in_path, out_path, "split-" + form)
     assert n_scan == int((js.kind == 0).sum()) and n_pw + n_rel == len(js.kind) - n_scan
     sr.close()
+
+
+def test_byte_budget_admission(gs, mix, tmpdata):
+    """Admission by buffer bytes: with a 6 MiB budget (three 2 MiB scan or
+    release jobs, or many small pwrites) the admitted, unfinished jobs never
+    hold more than the budget, and every output still equals the oracle's."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    budget = 6 << 20
+    out_path = os.path.join(tmpdata, "serve_budget.bin")
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("serve byte budget", budget)
+    res, dig, lat = sr.run(g.PERSISTENT, max_inflight=512, staging_bytes=(2 << 20) * 32,
+                           max_inflight_bytes=budget)
+    peak = sr.peak_inflight_bytes
+    sr.close()
+    assert 0 < peak <= budget, peak
+    counts = check_outputs(sr, js, res, dig, in_path, out_path, "budget")
+    assert min(counts) > 0
+    assert (lat != np.uint64(2**64 - 1)).all()
+
+
+def test_full_size_scans_default_split(gs, tmpdata):
+    """The serving config's largest scans (64 MiB, and 64 MiB - 4 KiB at an
+    unaligned-to-the-split offset) at the default 16 MiB task size, next to
+    a pwrite and a release: digests, file bytes and return values equal the
+    oracle's."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    in_path = synth.random_file(5, 64 << 20, name="c5_in_64m.bin")
+    M = 1 << 20
+    kind = np.array([0, 1, 0, 2, 0], dtype=np.uint8)
+    content = synth.rng(5, 9).integers(0, 256, 8192, dtype=np.uint8)
+    js = synth.JobStream(kind=kind,
+                         arrival_ns=np.array([0, 10_000, 20_000, 30_000, 40_000], dtype=np.uint64),
+                         arg_off=np.array([0, 0, 4096, 0, 12 * M], dtype=np.uint64),
+                         arg_len=np.array([64 * M, 8192, 64 * M - 4096, 2 * M, 32 * M + 4096],
+                                          dtype=np.uint64),
+                         content_off=np.zeros(5, dtype=np.uint64), content=content)
+    out_path = os.path.join(tmpdata, "serve_fullsize.bin")
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("serve 64 MiB scans at the default split")
+    assert "GSYS_SERVE_SPLIT_MIB" not in os.environ
+    res, dig, lat = sr.run(g.PERSISTENT, max_inflight=8, staging_bytes=(2 << 20) * 16)
+    sr.close()
+    n_scan, n_pw, n_rel = check_outputs(sr, js, res, dig, in_path, out_path, "full-size")
+    assert (n_scan, n_pw, n_rel) == (3, 1, 1)
