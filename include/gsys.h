@@ -461,6 +461,21 @@ typedef struct gsys_serve_params {
 int gsys_serve_run(gsys_ctx *ctx, gsys_serve_params *params, void *stream);
 
 /*
+ * gsys_serve_run for callers that cannot allocate memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same session and results, but the persistent form's
+ * per-job state lives in a fixed array of 65,536 records (2 MiB) in device
+ * memory that the library holds on each GPU it runs on until the process
+ * ends.  Nothing is allocated by the call (no hipMalloc / hipFree, no host
+ * heap).  params and stream as for gsys_serve_run; n above 65,536 returns
+ * -E2BIG with nothing run.  Every call on one GPU shares that GPU's array
+ * (each call sets the records of its n jobs before launching), so calls that
+ * overlap on one GPU race: run them one after the other.  Errors: as for
+ * gsys_serve_run, plus -E2BIG.
+ */
+int gsys_serve_run_noalloc(gsys_ctx *ctx, gsys_serve_params *params, void *stream);
+
+/*
  * Visibility canary for producer calls (section 4.1 ordering): work-item i
  * writes 64 stamp bytes (eight little-endian words
  * (seed * 0x9E3779B97F4A7C15) ^ ((8i + k + 1) * 0xD1B54A32D192ED03), k =

@@ -135,6 +135,7 @@ _SIGS = {
                                     C.c_uint32, C.c_uint64, C.c_uint64, _P, C.c_uint32, _P, _P,
                                     _P]),
     "gsys_serve_run": (C.c_int, [_P, C.POINTER(gsys_serve_params), _P]),
+    "gsys_serve_run_noalloc": (C.c_int, [_P, C.POINTER(gsys_serve_params), _P]),
     "gsys_canary": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                               C.c_uint32, C.c_uint32, _P]),
     "gsys_wordcount_open": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,

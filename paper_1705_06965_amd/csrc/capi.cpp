@@ -321,6 +321,12 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
       return -ENODEV;
     }
     c->cu_count = prop.multiProcessorCount;
+    // the allocation-free serving entry point's scratch on this device
+    if (int e = gsys_internal::serve_scratch_setup ? gsys_internal::serve_scratch_setup(c->device)
+                                                   : -ENODEV) {
+      destroy(c);
+      return e;
+    }
     int wall_khz = 0;
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess &&
         wall_khz > 0) {
@@ -553,6 +559,7 @@ const char* gsys_strerror(int code) {
     case EAGAIN: return "try again";
     case EINPROGRESS: return "not waited for";
     case ENOTSUP: return "no interrupt signal mapped for the GPU (doorbell)";
+    case E2BIG: return "more jobs than the allocation-free scratch holds";
     default: return strerror(-code);
   }
 }
@@ -756,6 +763,8 @@ int control_page(gsys_ctx* c, void** host, uint64_t* dev) {
 }
 
 bool no_device(gsys_ctx* c) { return c->no_device; }
+
+int device_of(gsys_ctx* c) { return c->device; }
 
 uint64_t hash_words(std::initializer_list<uint64_t> w) {
   uint64_t h = 0x9e3779b97f4a7c15ull;

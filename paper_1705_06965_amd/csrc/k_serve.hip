@@ -34,6 +34,7 @@
 #include <immintrin.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 namespace gsys_sv {
@@ -59,6 +60,14 @@ struct JobState {
   unsigned int ntasks;          // set by the host before the launch
   unsigned long long pad;
 };
+
+// Per-job state of the allocation-free entry point: a fixed array in device
+// memory (2 MiB), one copy per GPU for the life of the process.  In host
+// code `scratch` only names the array; its device address on each GPU is
+// looked up once by scratch_setup() and kept in scratch_dev[].
+constexpr uint32_t kScratchJobs = 65536;
+static __device__ __align__(256) JobState scratch[kScratchJobs];
+constexpr int kMaxDevices = 64;
 
 struct SvArgs {
   gsys_dev_ctx c;
@@ -484,9 +493,43 @@ int check_params(gsys_ctx* ctx, const gsys_serve_params* P) {
   return 0;
 }
 
+std::mutex scratch_mu;
+JobState* scratch_dev[kMaxDevices];  // device address of `scratch` per device
+
 }  // namespace gsys_sv
 
 using namespace gsys_sv;
+
+// With `device` current: look up the device address of the allocation-free
+// scratch array on it (once per device).
+int gsys_internal::serve_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return -ENODEV;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (scratch_dev[device]) return 0;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    fprintf(stderr, "gsys: no device address for the serving scratch array: %s\n",
+            hipGetErrorString(e));
+    return -ENODEV;
+  }
+  scratch_dev[device] = (JobState*)p;
+  return 0;
+}
+
+int gsys_serve_run_noalloc(gsys_ctx* ctx, gsys_serve_params* P, void* stream) {
+  if (int e = check_params(ctx, P)) return e;
+  if (P->n > kScratchJobs) return -E2BIG;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
+  const int dev = gsys_internal::device_of(ctx);
+  JobState* js = nullptr;
+  {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices) js = scratch_dev[dev];
+  }
+  if (!js) return -ENODEV;  // gsys_init found no address for it
+  return serve_run(ctx, P, js, (hipStream_t)stream);
+}
 
 int gsys_serve_run(gsys_ctx* ctx, gsys_serve_params* P, void* stream) {
   if (int e = check_params(ctx, P)) return e;
@@ -497,6 +540,6 @@ int gsys_serve_run(gsys_ctx* ctx, gsys_serve_params* P, void* stream) {
       hipMalloc((void**)&js, (uint64_t)(P->n ? P->n : 1) * sizeof(JobState)) != hipSuccess)
     return -ENOMEM;
   const int rc = serve_run(ctx, P, js, s);
-  if (js) hipFree(js);
+  if (js) (void)hipFree(js);
   return rc;
 }

@@ -25,6 +25,13 @@ uint64_t hash_words(std::initializer_list<uint64_t> w);
 int control_page(gsys_ctx* ctx, void** host, uint64_t* dev);
 // true for a CPU-only context (GSYS_CFG_NO_DEVICE): nothing may be launched.
 bool no_device(gsys_ctx* ctx);
+// The HIP device ordinal of the context.
+int device_of(gsys_ctx* ctx);
+// Set-up of the allocation-free serving entry point's scratch array on
+// `device`, which must be current (called by gsys_init).  Weak: a host-only
+// build of the context and pool (the sanitizer test driver) has no kernels,
+// and there the symbol is null.
+int serve_scratch_setup(int device) __attribute__((weak));
 // Device wall-clock ticks per millisecond.
 uint64_t ticks_per_ms(gsys_ctx* ctx);
 int launch(gsys_ctx* ctx, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds,
