@@ -84,7 +84,7 @@ def parse():
     return ap.parse_args()
 
 
-COMMON_SOURCES = ["paper_1705_06965_amd/csrc/gsys_device.hpp", "include/gsys_abi.h"]
+COMMON_SOURCES = ["include/gsys_device.hpp", "include/gsys_abi.h"]
 PROFILES = {
     "sweep": ("profiles/fnv4k_persistent_pread_sweep_1g.md",
               ["paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp"]),

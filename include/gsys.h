@@ -144,15 +144,23 @@ int gsys_allow_fd(gsys_ctx *ctx, int fd, uint32_t perms);
 int gsys_register_buffer(gsys_ctx *ctx, uint64_t dev_addr, void *host_addr, uint64_t bytes,
                          uint32_t kind, uint32_t *out_id);
 
-/* Drop a registration.  Errors: -ENOENT. */
+/*
+ * Drop a registration.  Tickets the GPU has claimed may still name the
+ * buffer, so while the host has not serviced every claimed ticket (after
+ * waiting up to 10 ms for them) the call fails with -EBUSY and keeps it.
+ * On success it returns only once no service thread can still be using the
+ * buffer's memory: the caller may free it then.  Errors: -ENOENT, -EBUSY.
+ */
 int gsys_unregister_buffer(gsys_ctx *ctx, uint32_t id);
 
 /*
  * Allocate `bytes` of fine-grained, host-coherent pinned memory that GPU
  * kernels can read and write while host threads do the same, and register it
  * as GSYS_BUF_HOST.  *host_out / *dev_out receive the host and device
- * addresses, *id_out the registration.  Freed by gsys_host_free() or at
- * shutdown.  Errors: -ENOMEM, -ENODEV.
+ * addresses, *id_out the registration.  Freed by gsys_host_free() (which
+ * unregisters it first, with gsys_unregister_buffer's -EBUSY rule, and
+ * frees nothing when that fails) or at shutdown.  Errors: -ENOMEM, -ENODEV;
+ * gsys_host_free: -ENOENT, -EBUSY.
  */
 int gsys_host_alloc(gsys_ctx *ctx, uint64_t bytes, void **host_out, uint64_t *dev_out,
                     uint32_t *id_out);
@@ -176,13 +184,23 @@ typedef struct gsys_launch_desc {
 } gsys_launch_desc;
 
 /*
- * Launch a kernel that issues gsys calls.  PERSISTENT clamps grid[0] to the
- * number of work-groups of that kernel that fit on the device at once, so
- * that waits on the host never wait on a work-group that cannot run
- * (section 4.1: kernel-wide strong ordering can deadlock when not every
- * work-item is resident).  GRAPH captures the clamped launch once per
- * (kernel, shape) into a hipGraph and replays it.
- * Errors: -EINVAL, -ENODEV (HIP launch failure).
+ * Launch a kernel that issues gsys calls (the device API is
+ * include/gsys_device.hpp; pass the kernel a gsys_dev_ctx from
+ * gsys_device_ctx).  Every launch first clears the context's
+ * kernel-granularity call sites (section 5: a kernel call's designated
+ * caller is elected per launch), on the same stream.
+ *   PLAIN       the grid as given (1-3 dimensions, at most 1024 work-items
+ *               per work-group)
+ *   PERSISTENT  grid[0] (a one-dimensional grid) clamped to the work-groups
+ *               of that kernel that fit on the device at once, so that no
+ *               call waits on a work-group that cannot run (section 4.1:
+ *               kernel-wide ordering can deadlock when not every work-item
+ *               is resident)
+ *   GRAPH       as PERSISTENT, run as a hipGraph built once per (kernel,
+ *               grid, block, LDS); every launch sets its own argument values
+ *               into the graph before replaying it, so `args` may point at
+ *               the same array with new values each time
+ * Asynchronous on `stream`.  Errors: -EINVAL, -ENODEV (HIP launch failure).
  */
 int gsys_launch(gsys_ctx *ctx, const gsys_launch_desc *desc, void *stream);
 
@@ -319,7 +337,9 @@ typedef struct gsys_chunk {
  *   form      GSYS_PLAIN: one work-group per chunk, blocking relaxed
  *             work-group pread (the paper's setting); GSYS_PERSISTENT /
  *             GSYS_GRAPH: resident work-groups take chunks from a device work
- *             counter and prefetch the next chunk with a non-blocking call
+ *             counter and prefetch the next chunk with a non-blocking call;
+ *             GSYS_GRAPH runs the zeroing of counts and counter and the scan
+ *             as one hipGraph per shape, replayed with this call's arguments
  * Errors: -EINVAL (shapes), -EFAULT (staging not registered), -ENODEV.
  */
 int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t chunk_max,

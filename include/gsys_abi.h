@@ -23,7 +23,7 @@
 
 #include <stdint.h>
 
-#define GSYS_ABI_VERSION 2u
+#define GSYS_ABI_VERSION 3u
 
 /* ---- slot states (low 3 bits of ctl) ---- */
 #define GSYS_ST_FREE        0u
@@ -128,6 +128,10 @@ typedef struct gsys_dev_ctx {
     uint64_t arena_bytes;
     uint64_t doorbell;               /* interrupt signal handle (0 = pollers spin) */
     const uint64_t *sleepers;        /* host-coherent: pollers blocked on it      */
+    uint64_t ksites;                 /* device: kernel-granularity call sites (16 B each),
+                                        cleared by gsys_launch before every launch */
+    uint32_t n_ksites;
+    uint32_t pad;
 } gsys_dev_ctx;
 
 #define GSYS_ETIMEDOUT_RET (-110)    /* -ETIMEDOUT */

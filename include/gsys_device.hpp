@@ -343,6 +343,14 @@ __device__ inline int64_t call_wg(const gsys_dev_ctx& c, uint16_t nr, uint8_t ex
     fence_release_sys();  // every wavefront makes its writes visible to the host
     __syncthreads();
   }
+  if (!barrier_before && threadIdx.x < 64) {
+    // a relaxed consumer call has no group barrier before it, so only the
+    // caller's wavefront may have written memory the call reads (a
+    // descriptor list, say): each of its work-items releases its writes at
+    // system scope before work-item 0 publishes
+    fence_release_sys();
+    __builtin_amdgcn_wave_barrier();
+  }
   Ticket tk{0, 0, 0};
   int64_t ret = GSYS_NOT_WAITED;
   if (threadIdx.x == 0) {
@@ -552,5 +560,142 @@ __device__ inline int64_t wait_kernel(const gsys_dev_ctx& c, const Ticket& tk) {
   __syncthreads();  // s_ret is rewritten by the next wait before any barrier
   return r;
 }
+
+// ============================================================= public API
+// What a user kernel calls.  Every call names its granularity G, ordering O
+// and blocking B (section 4.1); work-item calls are strong only and kernel
+// calls relaxed only, both checked at compile time.  Under relaxed ordering
+// the call's role decides which side of it synchronises the group: write,
+// pwrite, sendto, munmap, madvise and close are producers (the group's
+// writes are released before the call), read, pread, recvfrom, mmap and
+// openat consumers (the group waits for the result after it).
+//
+//  G::WorkItem   every active work-item makes its own call with its own
+//                arguments; the calls of a wavefront share one claim on the
+//                ring (section 5 gives each work-item its own slot).
+//  G::WorkGroup  every work-item of the work-group makes the call together;
+//                work-item 0 is the designated caller and its arguments are
+//                the call's (section 5).  Under relaxed consumer ordering
+//                only work-item 0's wavefront may write memory the call reads.
+//  G::Kernel     every work-item of the launch makes the call together; the
+//                designated caller is the first work-group to arrive
+//                (consumer) or the last (producer), and its work-item 0's
+//                arguments are the call's.  Each such call needs its own
+//                call site: gsys_call uses site 0 of the context's
+//                kernel-call sites, gsys_call_site any of them; gsys_launch
+//                clears them all before every launch.
+//
+// Blocking calls return the call's result (>= 0) or -errno to every
+// work-item that waits for it: all of them for work-item calls and for
+// group calls with a barrier after them; only the caller's wavefront for a
+// relaxed blocking producer (the paper's weak-block: only the caller waits).
+// Non-blocking calls return at once (0, or GSYS_NOT_WAITED where the caller
+// did not issue) and hand back a Ticket through `tk` (work-item 0 of the
+// caller work-group for group calls; each work-item for work-item calls);
+// gsys_wait<G> then returns the result.  A non-blocking call whose ticket is
+// never waited for is still serviced; the host's gsys_wait drains it.
+
+// The kernel-call sites a launch may use (see gsys_launch).
+__device__ __forceinline__ KState* kernel_site(const gsys_dev_ctx& c, uint32_t site) {
+  return reinterpret_cast<KState*>(c.ksites) + (site < c.n_ksites ? site : 0);
+}
+
+template <G g, O o, B b>
+__device__ inline int64_t gsys_call(const gsys_dev_ctx& c, uint16_t nr, const Args6& a,
+                                    Ticket* tk = nullptr) {
+  (void)Legal<g, o>::ok;
+  if constexpr (g == G::WorkItem) {
+    return call_wi<b>(c, nr, a, tk);
+  } else if constexpr (g == G::WorkGroup) {
+    return call_wg<o, b>(c, nr, 0, a, tk);
+  } else {
+    return call_kernel<b>(c, kernel_site(c, 0), nr, 0, [] {}, [&] { return a; }, tk);
+  }
+}
+
+template <G g, O o, B b>
+__device__ inline int64_t gsys_call(const gsys_dev_ctx& c, uint16_t nr, uint64_t a0,
+                                    uint64_t a1 = 0, uint64_t a2 = 0, uint64_t a3 = 0,
+                                    uint64_t a4 = 0, uint64_t a5 = 0) {
+  return gsys_call<g, o, b>(c, nr, Args6{{a0, a1, a2, a3, a4, a5}});
+}
+
+// A kernel-granularity call at call site `site` (< the context's n_ksites).
+template <O o, B b>
+__device__ inline int64_t gsys_call_site(const gsys_dev_ctx& c, uint32_t site, uint16_t nr,
+                                         const Args6& a, Ticket* tk = nullptr) {
+  (void)Legal<G::Kernel, o>::ok;
+  return call_kernel<b>(c, kernel_site(c, site), nr, 0, [] {}, [&] { return a; }, tk);
+}
+
+// The result of a non-blocking call, by the same work-items that made it.
+template <G g>
+__device__ inline int64_t gsys_wait(const gsys_dev_ctx& c, const Ticket& tk) {
+  if constexpr (g == G::WorkItem) return wait_wi(c, tk);
+  else if constexpr (g == G::WorkGroup) return wait_wg(c, tk);
+  else return wait_kernel(c, tk);
+}
+
+// Typed wrappers: the call number fixes the role; arguments are the
+// system call's own (addresses are device views of registered buffers).
+#define GSYS_DEFAULT_ORDER (g == G::Kernel ? O::Relaxed : O::Strong)
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t read(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t count,
+                               Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_READ, Args6{{(uint64_t)(int64_t)fd, buf, count, 0, 0, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t write(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t count,
+                                Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_WRITE, Args6{{(uint64_t)(int64_t)fd, buf, count, 0, 0, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t pread(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t count,
+                                uint64_t off, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_PREAD64, Args6{{(uint64_t)(int64_t)fd, buf, count, off, 0, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t pwrite(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t count,
+                                 uint64_t off, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_PWRITE64, Args6{{(uint64_t)(int64_t)fd, buf, count, off, 0, 0}}, tk);
+}
+// addr: a struct sockaddr_in of addr_len bytes in a registered buffer
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t sendto(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t len,
+                                 int flags, uint64_t addr, uint64_t addr_len, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_SENDTO, Args6{{(uint64_t)(int64_t)fd, buf, len, (uint64_t)(int64_t)flags, addr, addr_len}}, tk);
+}
+// src_addr: 0, or room for a struct sockaddr_in in a registered buffer
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t recvfrom(const gsys_dev_ctx& c, int fd, uint64_t buf, uint64_t len,
+                                   int flags, uint64_t src_addr, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_RECVFROM, Args6{{(uint64_t)(int64_t)fd, buf, len, (uint64_t)(int64_t)flags, src_addr, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t mmap(const gsys_dev_ctx& c, uint64_t addr, uint64_t len, int prot,
+                               int flags, int fd, uint64_t off, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_MMAP, Args6{{addr, len, (uint64_t)(int64_t)prot, (uint64_t)(int64_t)flags, (uint64_t)(int64_t)fd, off}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t munmap(const gsys_dev_ctx& c, uint64_t addr, uint64_t len,
+                                 Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_MUNMAP, Args6{{addr, len, 0, 0, 0, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t madvise(const gsys_dev_ctx& c, uint64_t addr, uint64_t len, int advice,
+                                  Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_MADVISE, Args6{{addr, len, (uint64_t)(int64_t)advice, 0, 0, 0}}, tk);
+}
+// path: GSYS_PATH_MAX bytes (NUL-terminated) in a registered buffer
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t openat(const gsys_dev_ctx& c, int dirfd, uint64_t path, int flags,
+                                 uint32_t mode, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_OPENAT, Args6{{(uint64_t)(int64_t)dirfd, path, (uint64_t)(int64_t)flags, mode, 0, 0}}, tk);
+}
+template <G g, O o = GSYS_DEFAULT_ORDER, B b = B::Blocking>
+__device__ inline int64_t close(const gsys_dev_ctx& c, int fd, Ticket* tk = nullptr) {
+  return gsys_call<g, o, b>(c, GSYS_NR_CLOSE, Args6{{(uint64_t)(int64_t)fd, 0, 0, 0, 0, 0}}, tk);
+}
+#undef GSYS_DEFAULT_ORDER
 
 }  // namespace gsys

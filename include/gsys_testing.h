@@ -49,6 +49,14 @@ int gsys_test_raw_call(gsys_ctx *ctx, uint16_t nr, uint8_t flags, const uint64_t
  */
 int64_t gsys_test_claim_only(gsys_ctx *ctx, uint32_t n);
 
+/*
+ * Drop a registration without gsys_unregister_buffer's outstanding-ticket
+ * rule (any context): only the service threads' grace period protects it,
+ * so the call returns once no service thread can still use the buffer.
+ * Used to test that period with calls in flight.  Errors: -ENOENT.
+ */
+int gsys_test_unregister_now(gsys_ctx *ctx, uint32_t id);
+
 /* Read-only view of the ring for quiescence checks: copies D control words. */
 int gsys_test_ring_ctl(gsys_ctx *ctx, uint64_t *out, uint64_t max);
 

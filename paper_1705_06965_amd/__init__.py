@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GSYS_LIB") or os.path.join(_HERE, "libgsys.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # slot flags / states / call numbers (mirror include/gsys_abi.h)
 ST_FREE, ST_POPULATING, ST_READY, ST_PROCESSING, ST_FINISHED = 0, 1, 2, 3, 4
@@ -81,7 +81,8 @@ class gsys_dev_ctx(C.Structure):
                 ("comp_mask", C.c_uint64), ("timeout_ticks", C.c_uint64),
                 ("sleep_max", C.c_uint32), ("flags", C.c_uint32),
                 ("arena", C.c_uint64), ("arena_bytes", C.c_uint64),
-                ("doorbell", C.c_uint64), ("sleepers", C.c_uint64)]
+                ("doorbell", C.c_uint64), ("sleepers", C.c_uint64),
+                ("ksites", C.c_uint64), ("n_ksites", C.c_uint32), ("pad", C.c_uint32)]
 
 
 class gsys_serve_params(C.Structure):
@@ -155,6 +156,7 @@ _SIGS = {
     "gsys_test_claim_only": (C.c_int64, [_P, C.c_uint32]),
     "gsys_test_ring_ctl": (C.c_int, [_P, _P, C.c_uint64]),
     "gsys_test_inject": (C.c_int, [_P, C.c_uint16, C.c_int32, C.c_uint32]),
+    "gsys_test_unregister_now": (C.c_int, [_P, C.c_uint32]),
 }
 
 if not os.path.exists(LIB_PATH):
@@ -222,7 +224,7 @@ class HostBuffer:
 
     def free(self):
         if self.host and self.ctx.h:
-            lib.gsys_host_free(self.ctx.h, self.host)
+            check(lib.gsys_host_free(self.ctx.h, self.host), "gsys_host_free")
         self.host = None
         self.array = None
 

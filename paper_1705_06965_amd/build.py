@@ -17,7 +17,10 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = os.environ.get("GSYS_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["k_fnv.hip", "k_wordscan.hip", "k_kv.hip", "k_serve.hip", "k_canary.hip",
-               "k_permute.hip", "k_fileio.hip"]
+               "k_permute.hip", "k_fileio.hip", "k_launch.hip"]
+# a user program of the library, built against include/ only
+DEMO_SRC = os.path.join(HERE, "demo", "pread_fnv.hip")
+DEMO_LIB = os.path.join(HERE, "libgsys_demo.so")
 HOST_HIP_SOURCES = ["capi.cpp"]      # host code that calls the HIP runtime
 HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp"]     # plain C++17 + POSIX
 
@@ -57,9 +60,16 @@ def build(verbose: bool = False) -> str:
                 sys.stderr.write(r.stdout + r.stderr)
     objs = [j[j.index("-o") + 1] for j in jobs]
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-Wl,-soname,libgsys.so", "-o", tmp] + objs
          + ["-pthread", "-Wl,--no-undefined", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhsa-runtime64"])
     os.replace(tmp, LIB)
+    # the demo program links against the library it was built with
+    tmp = DEMO_LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "-x", "hip", DEMO_SRC, "-shared", "-fPIC", "-O3", "-std=c++17", "-Wall",
+          "-I" + os.path.join(ROOT, "include"), "-o", tmp] + DEVICE
+         + ["-L" + HERE, "-lgsys", "-Wl,-rpath,$ORIGIN", "-Wl,--no-undefined",
+            "-L" + os.path.join(ROCM, "lib"), "-lamdhip64"])
+    os.replace(tmp, DEMO_LIB)
     return LIB
 
 

@@ -107,6 +107,8 @@ struct gsys_ctx {
   gsys_comp* comp_dev = nullptr;
   uint64_t* retired_lo_dev = nullptr;
   unsigned long long* dev_words = nullptr;  // [0] tail, [32..63] kernel-call state
+  // kernel-granularity call sites of user kernels (gsys_launch clears them)
+  unsigned long long* ksites = nullptr;
   gsys_host::Pool* pool = nullptr;
   hipStream_t aux = nullptr;
   std::mutex mu;
@@ -118,8 +120,13 @@ struct gsys_ctx {
   uint32_t sleep_max = 16;
   uint32_t grid_override = 0;
   int cu_count = 0;
-  std::map<uint64_t, hipGraphExec_t> graphs;
-  std::vector<hipGraph_t> graph_defs;
+  // graph forms: per key, an instantiated chain of kernel nodes
+  struct Graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    std::vector<hipGraphNode_t> nodes;
+  };
+  std::map<uint64_t, Graph> graphs;
   // doorbell (GSYS_CFG_DOORBELL)
   gsys_host::Doorbell* db = nullptr;
   uint64_t* sleepers_dev = nullptr;  // host_words[64] as the GPU sees it
@@ -261,10 +268,13 @@ void destroy(gsys_ctx* c) {
   if (c->hsa_up) hsa_shut_down();
   if (!c->no_device) {
     hipSetDevice(c->device);
-    for (auto& g : c->graphs) hipGraphExecDestroy(g.second);
-    for (auto g : c->graph_defs) hipGraphDestroy(g);
+    for (auto& g : c->graphs) {
+      hipGraphExecDestroy(g.second.exec);
+      hipGraphDestroy(g.second.graph);
+    }
     if (c->aux) hipStreamDestroy(c->aux);
     if (c->dev_words) hipFree(c->dev_words);
+    if (c->ksites) hipFree(c->ksites);
   }
   for (auto& kv : c->host_allocs) host_coherent_free(c, kv.first);
   c->host_allocs.clear();
@@ -336,6 +346,8 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void**)&c->dev_words, 64 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->dev_words, 0, 64 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&c->ksites, gsys_internal::kSites * 16) != hipSuccess ||
+        hipMemset(c->ksites, 0, gsys_internal::kSites * 16) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
       destroy(c);
       return -ENODEV;
@@ -414,8 +426,15 @@ int gsys_register_buffer(gsys_ctx* c, uint64_t dev, void* host, uint64_t bytes, 
   return c->pool->add_buffer(dev, (uint8_t*)host, bytes, kind, out_id);
 }
 
+// Outstanding tickets may still reference any buffer: claimed tickets that
+// the pool has not all serviced after a short wait make a removal -EBUSY.
+static int quiet_for_removal(gsys_ctx* c) {
+  return gsys_wait(c, 10000000) ? -EBUSY : 0;
+}
+
 int gsys_unregister_buffer(gsys_ctx* c, uint32_t id) {
   if (!c) return -EINVAL;
+  if (int e = quiet_for_removal(c)) return e;
   return c->pool->remove_buffer(id);
 }
 
@@ -445,7 +464,9 @@ int gsys_host_free(gsys_ctx* c, void* host) {
   std::lock_guard<std::mutex> g(c->mu);
   auto it = c->host_allocs.find(host);
   if (it == c->host_allocs.end()) return -ENOENT;
-  c->pool->remove_buffer(it->second.second);
+  if (int e = quiet_for_removal(c)) return e;
+  // the memory is freed only after no service thread can still use it
+  if (int e = c->pool->remove_buffer(it->second.second)) return e;
   host_coherent_free(c, host);
   c->host_allocs.erase(it);
   return 0;
@@ -465,37 +486,15 @@ int gsys_device_ctx(gsys_ctx* c, gsys_dev_ctx* out) {
   out->flags = c->cfg.flags;
   out->arena = (uint64_t)c->arena;
   out->arena_bytes = c->arena_bytes;
+  if (c->ksites) {
+    out->ksites = (uint64_t)c->ksites;
+    out->n_ksites = gsys_internal::kSites;
+  }
   if (c->db) {
     // CPU-only contexts: any non-zero value; the emulated callers ring c->db
     out->doorbell = c->no_device ? 1 : c->sig.handle;
     out->sleepers = c->sleepers_dev;
   }
-  return 0;
-}
-
-int gsys_launch(gsys_ctx* c, const gsys_launch_desc* d, void* stream) {
-  if (!c || !d || !d->kernel || c->no_device) return -EINVAL;
-  uint32_t grid = d->grid[0];
-  if (d->mode == GSYS_PERSISTENT || d->mode == GSYS_GRAPH) {
-    uint32_t r = gsys_internal::resident_grid(c, d->kernel, d->block[0] * d->block[1] * d->block[2],
-                                              d->lds_bytes);
-    if (!r) return -ENODEV;
-    if (grid > r) grid = r;
-  } else if (d->mode != GSYS_PLAIN) {
-    return -EINVAL;
-  }
-  hipSetDevice(c->device);
-  dim3 g(grid, d->grid[1] ? d->grid[1] : 1, d->grid[2] ? d->grid[2] : 1);
-  dim3 b(d->block[0], d->block[1] ? d->block[1] : 1, d->block[2] ? d->block[2] : 1);
-  if (d->mode == GSYS_GRAPH) {
-    if (g.y != 1 || g.z != 1 || b.y != 1 || b.z != 1) return -EINVAL;
-    const uint64_t key = gsys_internal::hash_words(
-        {(uint64_t)d->kernel, grid, d->block[0], d->lds_bytes, (uint64_t)d->args});
-    return gsys_internal::launch_graph(c, key, d->kernel, grid, d->block[0], d->lds_bytes, d->args,
-                                       (hipStream_t)stream);
-  }
-  if (hipLaunchKernel(d->kernel, g, b, d->args, d->lds_bytes, (hipStream_t)stream) != hipSuccess)
-    return -ENODEV;
   return 0;
 }
 
@@ -715,6 +714,11 @@ int64_t gsys_test_claim_only(gsys_ctx* c, uint32_t n) {
   return (int64_t)__atomic_fetch_add(&c->host_words[32], (uint64_t)n, __ATOMIC_ACQ_REL);
 }
 
+int gsys_test_unregister_now(gsys_ctx* c, uint32_t id) {
+  if (!c) return -EINVAL;
+  return c->pool->remove_buffer(id);
+}
+
 int gsys_test_inject(gsys_ctx* c, uint16_t nr, int32_t err, uint32_t count) {
   if (!c || err <= 0 || err > 4095) return -EINVAL;
   c->pool->inject(nr, err, count);
@@ -787,37 +791,52 @@ int launch(gsys_ctx* c, const void* kernel, uint32_t grid, uint32_t block, uint3
   return 0;
 }
 
-int launch_graph(gsys_ctx* c, uint64_t key, const void* kernel, uint32_t grid, uint32_t block,
-                 uint32_t lds, void** args, hipStream_t s) {
+int launch_graph(gsys_ctx* c, uint64_t key, const KLaunch* k, uint32_t n, hipStream_t s) {
+  if (!n) return -EINVAL;
   hipSetDevice(c->device);
-  hipGraphExec_t ex = nullptr;
-  {
-    std::lock_guard<std::mutex> g(c->mu);
-    auto it = c->graphs.find(key);
-    if (it != c->graphs.end()) ex = it->second;
-  }
-  if (!ex) {
-    // capture on a private stream so the caller's stream is never in capture mode
-    hipStream_t cs;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return -ENODEV;
-    hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      hipStreamDestroy(cs);
+  auto params = [&](uint32_t i) {
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = const_cast<void*>(k[i].kernel);
+    p.gridDim = k[i].grid;
+    p.blockDim = k[i].block;
+    p.sharedMemBytes = k[i].lds;
+    p.kernelParams = k[i].args;
+    return p;
+  };
+  std::lock_guard<std::mutex> g(c->mu);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    // a chain of kernel nodes, each depending on the one before
+    gsys_ctx::Graph G;
+    if (hipGraphCreate(&G.graph, 0) != hipSuccess) return -ENODEV;
+    for (uint32_t i = 0; i < n; ++i) {
+      const hipKernelNodeParams p = params(i);
+      hipGraphNode_t node;
+      const hipGraphNode_t* dep = i ? &G.nodes.back() : nullptr;
+      if (hipGraphAddKernelNode(&node, G.graph, dep, i ? 1 : 0, &p) != hipSuccess) {
+        hipGraphDestroy(G.graph);
+        return -ENODEV;
+      }
+      G.nodes.push_back(node);
+    }
+    if (hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(G.graph);
       return -ENODEV;
     }
-    hipError_t le = hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, cs);
-    hipError_t ce = hipStreamEndCapture(cs, &graph);
-    hipStreamDestroy(cs);
-    if (le != hipSuccess || ce != hipSuccess || !graph) return -ENODEV;
-    if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) {
-      hipGraphDestroy(graph);
-      return -ENODEV;
+    it = c->graphs.emplace(key, std::move(G)).first;
+  } else {
+    // the same shape again: this launch's arguments go into the nodes (the
+    // runtime copies them), so a caller may reuse one argument array with
+    // new values, and every replay sees its own
+    if (it->second.nodes.size() != n) return -EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+      const hipKernelNodeParams p = params(i);
+      if (hipGraphExecKernelNodeSetParams(it->second.exec, it->second.nodes[i], &p) != hipSuccess)
+        return -ENODEV;
     }
-    std::lock_guard<std::mutex> g(c->mu);
-    c->graphs[key] = ex;
-    c->graph_defs.push_back(graph);
   }
-  if (hipGraphLaunch(ex, s) != hipSuccess) return -ENODEV;
+  if (hipGraphLaunch(it->second.exec, s) != hipSuccess) return -ENODEV;
   return 0;
 }
 

@@ -110,6 +110,9 @@ class Pool {
   // stopped).
   void close_owned();
   int add_buffer(uint64_t dev, uint8_t* host, uint64_t bytes, uint32_t kind, uint32_t* id);
+  // Drop a registration.  Returns once no service thread can still use the
+  // buffer: every poller that was serving requests when the entry went away
+  // has finished them (later requests no longer find it).
   int remove_buffer(uint32_t id);
   void set_arena(uint8_t* base, uint64_t bytes) { arena_ = base; arena_bytes_ = bytes; }
   // Answer the next `count` single requests of call `nr` with -err.
@@ -253,6 +256,9 @@ class Pool {
     std::atomic<uint64_t> requests{0}, calls{0}, in{0}, out{0}, err{0}, rej{0}, bundles{0},
         merged{0}, idle{0}, ns{0}, sleeps{0};
     std::atomic<uint64_t> serviced{0};  // completed requests, release-incremented
+    // odd while this poller serves requests (it may hold host addresses of
+    // registered buffers); remove_buffer waits for it to move on
+    std::atomic<uint64_t> serving{0};
     std::atomic<uint64_t> bhist[8] = {}, ehist[8] = {};
   };
   std::vector<std::unique_ptr<Counters>> ctr_;  // P pollers, then the others

@@ -255,10 +255,9 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
     }
     void* args[] = {&A};
     if (form == GSYS_GRAPH) {
-      const uint64_t key = gsys_internal::hash_words(
-          {0xF4Bull, (uint64_t)fd, offsets, n_items, item_bytes, staging, staging_bytes, lists,
-           out_fnv, out_ret, wg_size, grid, (uint64_t)s});
-      return gsys_internal::launch_graph(ctx, key, kp, grid, wg_size, lds, args, s);
+      const uint64_t key = gsys_internal::hash_words({0xF4Bull, (uint64_t)kp, grid, wg_size, lds});
+      const gsys_internal::KLaunch k{kp, dim3(grid), dim3(wg_size), lds, args};
+      return gsys_internal::launch_graph(ctx, key, &k, 1, s);
     }
     return gsys_internal::launch(ctx, kp, grid, wg_size, lds, args, s);
   }

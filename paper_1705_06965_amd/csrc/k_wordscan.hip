@@ -458,27 +458,46 @@ int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
   A.cbuf = cbuf;
   A.n_chunks = n_chunks;
   A.nq = nq;
-  const uint64_t ncount = (uint64_t)nfiles * nq;
-  if (ncount) {
-    hipLaunchKernelGGL(zero_u32, dim3((uint32_t)std::min<uint64_t>((ncount + 255) / 256, 4096)),
-                       dim3(256), 0, s, (uint32_t*)counts, ncount);
-  }
-  hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, (uint32_t*)A.work, (uint64_t)2);
-  if (hipGetLastError() != hipSuccess) return -ENODEV;
-  if (!n_chunks) return 0;
+  if (form != GSYS_PLAIN && form != GSYS_PERSISTENT && form != GSYS_GRAPH) return -EINVAL;
+  // zero the counts and the work counter, then scan
+  uint64_t ncount = (uint64_t)nfiles * nq;
+  uint64_t nwork = 2;
+  uint32_t* counts32 = (uint32_t*)counts;
+  uint32_t* work32 = (uint32_t*)A.work;
+  void* zc_args[] = {&counts32, &ncount};
+  void* zw_args[] = {&work32, &nwork};
   void* args[] = {&A};
+  const dim3 zc_grid((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((ncount + 255) / 256, 4096)));
+  gsys_internal::KLaunch k[3] = {{(const void*)zero_u32, zc_grid, dim3(256), 0, zc_args},
+                                 {(const void*)zero_u32, dim3(1), dim3(64), 0, zw_args},
+                                 {nullptr, dim3(1), dim3(kWG), 0, args}};
   if (form == GSYS_PLAIN) {
-    if (staging_bytes < (uint64_t)cbuf * n_chunks) return -EINVAL;
-    return gsys_internal::launch(ctx, (const void*)wordscan_plain, n_chunks, kWG, 0, args, s);
+    if (n_chunks && staging_bytes < (uint64_t)cbuf * n_chunks) return -EINVAL;
+    k[2].kernel = (const void*)wordscan_plain;
+    k[2].grid = dim3(n_chunks);
+  } else {
+    if (n_chunks && staging_bytes < per_wg) return -EINVAL;
+    uint32_t grid = gsys_internal::resident_grid(ctx, (const void*)wordscan_persistent, kWG, 0);
+    if (!grid) return -ENODEV;
+    grid = (uint32_t)std::min<uint64_t>({(uint64_t)grid, staging_bytes / per_wg, (uint64_t)n_chunks});
+    const uint32_t req = gsys_internal::persistent_grid_override(ctx);
+    if (req && req < grid) grid = req;
+    k[2].kernel = (const void*)wordscan_persistent;
+    k[2].grid = dim3(grid);
   }
-  if (form != GSYS_PERSISTENT && form != GSYS_GRAPH) return -EINVAL;
-  if (staging_bytes < per_wg) return -EINVAL;
-  uint32_t grid = gsys_internal::resident_grid(ctx, (const void*)wordscan_persistent, kWG, 0);
-  if (!grid) return -ENODEV;
-  grid = (uint32_t)std::min<uint64_t>({(uint64_t)grid, staging_bytes / per_wg, (uint64_t)n_chunks});
-  const uint32_t req = gsys_internal::persistent_grid_override(ctx);
-  if (req && req < grid) grid = req;
-  return gsys_internal::launch(ctx, (const void*)wordscan_persistent, grid, kWG, 0, args, s);
+  if (form == GSYS_GRAPH && n_chunks) {
+    // one graph per shape: both fills and the scan, replayed with this
+    // call's arguments
+    const uint64_t key = gsys_internal::hash_words(
+        {0x3C5ull, zc_grid.x, k[2].grid.x});
+    return gsys_internal::launch_graph(ctx, key, k, 3, s);
+  }
+  for (uint32_t i = 0; i < 3; ++i) {
+    if (i == 2 && !n_chunks) break;
+    if (int e = gsys_internal::launch(ctx, k[i].kernel, k[i].grid.x, k[i].block.x, 0, k[i].args, s))
+      return e;
+  }
+  return 0;
 }
 
 int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfiles,

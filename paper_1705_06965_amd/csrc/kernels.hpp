@@ -36,9 +36,19 @@ int serve_scratch_setup(int device) __attribute__((weak));
 uint64_t ticks_per_ms(gsys_ctx* ctx);
 int launch(gsys_ctx* ctx, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds,
            void** args, hipStream_t s);
-// Capture the launch into a hipGraph the first time `key` is seen, replay it
-// afterwards.
-int launch_graph(gsys_ctx* ctx, uint64_t key, const void* kernel, uint32_t grid, uint32_t block,
-                 uint32_t lds, void** args, hipStream_t s);
+// One kernel launch of a graph form.
+struct KLaunch {
+  const void* kernel;
+  dim3 grid, block;
+  uint32_t lds;
+  void** args;
+};
+// Launch the chain k[0], ..., k[n - 1] (each after the one before) as a
+// hipGraph: built and instantiated the first time `key` is seen (the key
+// must name the kernels and their shapes), then replayed with this call's
+// arguments set into its nodes.
+int launch_graph(gsys_ctx* ctx, uint64_t key, const KLaunch* k, uint32_t n, hipStream_t s);
+// Kernel-granularity call sites per context for user kernels (16 bytes each).
+constexpr uint32_t kSites = 64;
 
 }  // namespace gsys_internal

@@ -8,8 +8,12 @@
 // doorbell on: pollers that find nothing for 20 us block, and a sparse
 // caller keeps arriving around their decision to block (the backstop is
 // raised to 30 s, so a lost wake-up shows as a time-out).  Every result is
-// checked against the file's bytes.  Exits 0 when
-// all checks pass; ThreadSanitizer turns any data race into a non-zero exit.
+// checked against the file's bytes.  A final phase unregisters and frees
+// descriptor-list buffers while list calls run over them: the pool reads and
+// writes those lists from user space, so AddressSanitizer reports any use
+// after the free if a service thread could still hold the list when
+// unregistering returned.  Exits 0 when all checks pass; ThreadSanitizer
+// turns any data race into a non-zero exit.
 //
 // Build: g++ -fsanitize=thread over this file, capi.cpp and host_pool.cpp
 // (host code only; contexts use GSYS_CFG_NO_DEVICE and make no HIP calls).
@@ -94,7 +98,7 @@ int run_phase(const std::string& path, const Phase& ph) {
   std::thread buf_churn([&] {
     uint32_t bid = churn_id;
     while (!done.load()) {
-      gsys_unregister_buffer(ctx, bid);
+      gsys_test_unregister_now(ctx, bid);
       if (gsys_register_buffer(ctx, churn_base, dummy.data(), dummy.size(), GSYS_BUF_HOST, &bid))
         break;
     }
@@ -157,6 +161,93 @@ int run_phase(const std::string& path, const Phase& ph) {
   return 0;
 }
 
+// List calls whose descriptor lists are unregistered and freed while the
+// calls are in flight.  Four callers keep issuing blocking list preads of
+// 64 items, each with its own list (a call writes its results back into its
+// list) in one registered block at a fixed device address; a churner
+// replaces the host memory behind that address: it fills a fresh block,
+// drops the old registration (the grace period only), frees the old memory
+// and registers the fresh block.  A call sees either a whole list (every
+// item read) or no registration (-EFAULT), never freed memory.
+int run_list_free_phase(const std::string& path) {
+  gsys_config cfg;
+  memset(&cfg, 0, sizeof cfg);
+  cfg.abi_version = GSYS_ABI_VERSION;
+  cfg.ring_slots = 4096;
+  cfg.service_threads = 4;
+  cfg.flags = GSYS_CFG_NO_DEVICE | GSYS_CFG_NO_PIN;
+  gsys_ctx* ctx = nullptr;
+  if (int e = gsys_init(&cfg, &ctx)) return fail("gsys_init", e);
+  const int fd = open(path.c_str(), O_RDONLY);
+  if (fd < 0 || gsys_allow_fd(ctx, fd, GSYS_FD_READ)) return fail("open / allow_fd");
+  constexpr uint32_t kN = 64, kLen = 512;
+  void* host = nullptr;
+  uint64_t dev = 0;
+  uint32_t id = 0;
+  if (gsys_host_alloc(ctx, 8ull * kN * kLen, &host, &dev, &id)) return fail("host_alloc");
+  constexpr uint32_t kCallers = 4;
+  const uint64_t list_dev = 1ull << 45;  // the lists' device address (any unused range)
+  const uint64_t block = kCallers * kN * sizeof(gsys_iodesc);
+  auto fresh = [&]() {
+    gsys_iodesc* L = new gsys_iodesc[kCallers * kN];
+    for (uint32_t i = 0; i < kCallers * kN; ++i)
+      L[i] = gsys_iodesc{(uint64_t)(i % kN) * kLen, (i % kN) * kLen, (int32_t)kLen};
+    return L;
+  };
+  gsys_iodesc* cur = fresh();
+  uint32_t lid = 0;
+  if (gsys_register_buffer(ctx, list_dev, cur, block, GSYS_BUF_HOST, &lid))
+    return fail("register list");
+  std::atomic<bool> done{false};
+  std::atomic<int> bad{0};
+  std::atomic<uint64_t> whole{0}, refused{0};
+  std::vector<std::thread> callers;
+  for (uint32_t t = 0; t < kCallers; ++t)
+    callers.emplace_back([&, t] {
+      const uint64_t a[6] = {(uint64_t)fd, list_dev + t * kN * sizeof(gsys_iodesc), kN,
+                             dev + (uint64_t)t * 2 * kN * kLen, 0, 0};
+      for (int i = 0; i < 400 && !bad.load(); ++i) {
+        int64_t r = 0;
+        if (gsys_test_raw_call(ctx, GSYS_NR_PREAD64, GSYS_F_BLOCKING | GSYS_F_LIST, a, &r,
+                               30000000000ull)) {
+          bad.store(1);
+        } else if (r == (int64_t)kN * kLen) {
+          whole.fetch_add(1);
+        } else if (r == -EFAULT) {
+          refused.fetch_add(1);
+        } else {
+          bad.store(2);
+        }
+      }
+    });
+  std::thread churner([&] {
+    while (!done.load()) {
+      gsys_iodesc* next = fresh();
+      if (gsys_test_unregister_now(ctx, lid)) { bad.store(3); break; }
+      delete[] cur;  // no service thread may touch it any more
+      cur = next;
+      if (gsys_register_buffer(ctx, list_dev, cur, block, GSYS_BUF_HOST, &lid)) {
+        bad.store(4);
+        break;
+      }
+    }
+  });
+  for (auto& c : callers) c.join();
+  done.store(true);
+  churner.join();
+  if (bad.load()) return fail("list calls while freeing lists", bad.load());
+  if (!whole.load()) return fail("no list call saw a whole list");
+  if (gsys_wait(ctx, 10000000000ull)) return fail("gsys_wait");
+  // with nothing outstanding the public call may drop and free it
+  if (gsys_unregister_buffer(ctx, lid)) return fail("unregister when quiet");
+  delete[] cur;
+  if (gsys_shutdown(ctx, 5000000000ull)) return fail("shutdown");
+  close(fd);
+  printf("lists freed in flight ok: %lu whole, %lu refused\n", (unsigned long)whole.load(),
+         (unsigned long)refused.load());
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -180,6 +271,7 @@ int main(int argc, char** argv) {
   setenv("GSYS_DOORBELL_BACKSTOP_US", "30000000", 1);
   for (const Phase& ph : phases)
     if (int e = run_phase(path, ph)) return e;
+  if (int e = run_list_free_phase(path)) return e;
   unlink(path.c_str());
   return 0;
 }

@@ -41,4 +41,4 @@ def test_pool_under_sanitizer(tmp_path, tmpdata, sanitizer):
                ASAN_OPTIONS="detect_leaks=0 exitcode=66", UBSAN_OPTIONS="exitcode=66")
     r = subprocess.run([exe, tmpdata], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
-    assert r.stdout.count(" ok: ") == 6, r.stdout
+    assert r.stdout.count(" ok: ") == 7, r.stdout

@@ -40,3 +40,37 @@ def test_illegal_cells_fail_to_compile(g, o, tmp_path):
 def test_legal_cells_compile(g, o, tmp_path):
     rc, err = _compile(g, o, tmp_path)
     assert rc == 0, err
+
+
+API_SRC = """
+#include "gsys_device.hpp"
+__global__ void k(gsys_dev_ctx c) {
+  (void)gsys::gsys_call<gsys::G::%s, gsys::O::%s, gsys::B::Blocking>(c, GSYS_NR_PREAD64, 0, 0, 0, 0);
+  (void)gsys::pwrite<gsys::G::%s, gsys::O::%s>(c, 3, 0, 64, 0);
+}
+"""
+
+
+def _compile_api(g, o, tmp_path):
+    src = tmp_path / ("api_%s_%s.hip" % (g, o))
+    src.write_text(API_SRC % (g, o, g, o))
+    r = subprocess.run([HIPCC, "-x", "hip", "-std=c++17", "--offload-arch=gfx950",
+                        "-fsyntax-only", "-I" + os.path.join(ROOT, "include"), str(src)],
+                       capture_output=True, text=True)
+    return r.returncode, r.stderr
+
+
+@pytest.mark.parametrize("g,o", [("WorkItem", "Relaxed"), ("Kernel", "Strong")])
+def test_public_api_rejects_illegal_cells(g, o, tmp_path):
+    """The public calls (gsys_call and the typed wrappers), compiled against
+    include/ alone, refuse the two illegal cells."""
+    rc, err = _compile_api(g, o, tmp_path)
+    assert rc != 0
+    assert "static assertion failed" in err or "static_assert" in err
+
+
+@pytest.mark.parametrize("g,o", [("WorkItem", "Strong"), ("WorkGroup", "Strong"),
+                                 ("WorkGroup", "Relaxed"), ("Kernel", "Relaxed")])
+def test_public_api_compiles_legal_cells(g, o, tmp_path):
+    rc, err = _compile_api(g, o, tmp_path)
+    assert rc == 0, err
