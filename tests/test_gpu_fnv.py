@@ -70,12 +70,23 @@ def mid(gs):
 def test_all_legal_cells_match_oracle(gs, mid, cell):
     g, ctx = gs
     r, (want_fnv, want_ret) = mid
+    ctx.ledger(reset=True)
     say("cell", cell, "n", r.n)
     f, ret = r.run(*cell)
     assert (ret == want_ret).all()
     assert (f == want_fnv).all()
-    st = ctx.stats()
-    assert st["claimed"] == st["requests"] or st["claimed"] >= st["retired_lo"]
+    # exactly once: one ledger record per ring request of the cell (one per
+    # work-item, per work-group or per launch), each ticket once, and each
+    # request's result the bytes its items read
+    led = ctx.ledger(reset=True)
+    per = {"WI": 1, "WG": 256, "K": r.n}[cell[0]]
+    want_requests = (r.n + per - 1) // per
+    assert len(led) == want_requests
+    assert len(np.unique(led[:, 0])) == want_requests
+    assert (led[:, 1] == g.NR_PREAD64).all()
+    got_bytes = np.sort(led[:, 2].astype(np.int64))
+    sizes = [min(per, r.n - k * per) * 4096 for k in range(want_requests)]
+    assert (got_bytes == np.sort(np.array(sizes, dtype=np.int64))).all()
 
 
 @pytest.mark.parametrize("form", ["persistent", "graph"])
@@ -157,32 +168,98 @@ def test_single_item_and_revoked_fd(gs):
     r.close()
 
 
-def test_full_sweep_sampled(gs):
-    """The microbenchmark sweep at its full size in the persistent form the
-    benchmark times: 262,144 preads of 4 KiB from a 1 GiB file; 4,096 sampled
-    items are recomputed by the oracle one by one, and the whole vector
-    matches the plain work-item form."""
+@pytest.fixture(scope="module")
+def full(gs):
+    """The microbenchmark sweep at its full size: 262,144 preads of 4 KiB at
+    uniform random 4 KiB-aligned offsets of a 1 GiB file, 1,024 work-groups
+    of 256; the oracle's whole vector."""
     g, ctx = gs
     from paper_1705_06965_amd.fnv import FnvRunner
     size = 1 << 30
     p = synth.random_file(2, size, name="c2_1g.bin")
     n = 1024 * 256
     offs = synth.sweep_offsets(n, size // 4096)
+    want = oracle.pread_fnv(p, offs, 4096, threads=8)
     r = FnvRunner(ctx, p, offs, 4096, wg_size=256)
-    say("full persistent")
-    f, ret = r.run(form=g.PERSISTENT)
-    idx = np.random.default_rng(3).choice(n, 4096, replace=False)
-    want_fnv, want_ret = oracle.pread_fnv(p, offs[idx], 4096, threads=8)
-    assert (ret[idx] == want_ret).all() and (ret == 4096).all()
-    assert (f[idx] == want_fnv).all()
-    say("full WI plain")
-    f2, ret2 = r.run("WI", "strong", "block")
-    assert (f2 == f).all() and (ret2 == ret).all()
-    # equal offsets give equal checksums
-    _, first = np.unique(offs, return_index=True)
-    inv = np.unique(offs, return_inverse=True)[1]
-    assert (f == f[first][inv]).all()
+    yield r, offs, want
     r.close()
+
+
+@pytest.mark.parametrize("cell", [("WI", "strong", "block"), ("WI", "strong", "nonblock"),
+                                  ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
+                                  ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
+                                  ("K", "relaxed", "block"), ("K", "relaxed", "nonblock"),
+                                  "persistent", "graph"])
+def test_full_sweep_every_cell(gs, full, cell):
+    """Every legal cell and both batching forms (the graph form in the
+    benchmark's launch configuration) give the oracle's whole vector."""
+    g, ctx = gs
+    r, offs, (want_fnv, want_ret) = full
+    say("full sweep", cell)
+    if cell == "persistent":
+        f, ret = r.run(form=g.PERSISTENT)
+    elif cell == "graph":
+        f, ret = r.run(form=g.GRAPH)
+        f, ret = r.run(form=g.GRAPH)  # a replay
+    else:
+        f, ret = r.run(*cell)
+    assert (ret == want_ret).all() and (ret == 4096).all()
+    assert (f == want_fnv).all()
+    # equal offsets give equal checksums
+    _, first, inv = np.unique(offs, return_index=True, return_inverse=True)
+    assert (f == f[first][inv]).all()
+
+
+@pytest.mark.parametrize("wg", [512, 1024])
+def test_wide_work_groups_match_oracle(gs, mid, wg):
+    """The call path with 512- and 1,024-wide work-groups (section 6, Fig. 5
+    right: work-group size): every legal cell and the persistent form, on
+    4,133 items (a ragged last work-group)."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    r0, (want_fnv, want_ret) = mid
+    offs = r0.offsets.cpu().numpy().view(np.uint64)
+    r = FnvRunner(ctx, r0.path, offs, 4096, wg_size=wg)
+    for cell in [("WI", "strong", "block"), ("WI", "strong", "nonblock"),
+                 ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
+                 ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
+                 ("K", "relaxed", "block"), ("K", "relaxed", "nonblock"), None]:
+        say("wg", wg, cell)
+        f, ret = r.run(*cell) if cell else r.run(form=g.PERSISTENT)
+        assert (ret == want_ret).all(), (wg, cell)
+        assert (f == want_fnv).all(), (wg, cell)
+    r.close()
+
+
+@pytest.mark.parametrize("piece", [64, 256, 4096, 65536])
+def test_coalesced_work_item_calls(gs, tmpdata, piece):
+    """Coalescing (section 4.2, Fig. 7): work-item preads of consecutive
+    pieces through a pool that bundles up to K = 8 ready requests for up to
+    T = 10 us and merges contiguous ones into one pread; every item's bytes
+    and checksum equal the oracle's, and small pieces were merged."""
+    g, _ = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = synth.random_file(2, 64 << 20, name="c2_64m.bin")
+    n = min(4096, (64 << 20) // piece)
+    offs = (np.arange(n, dtype=np.uint64) * np.uint64(piece))
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, piece, threads=8)
+    ctx = g.Context(ring_slots=1 << 14, device_timeout_ns=60_000_000_000, coalesce_max=8,
+                    coalesce_window_ns=10_000)
+    try:
+        r = FnvRunner(ctx, p, offs, piece, wg_size=256)
+        for cell in (("WI", "strong", "block"), ("WI", "strong", "nonblock")):
+            ctx.stats(reset=True)
+            say("coalesced", piece, cell)
+            f, ret = r.run(*cell)
+            assert (ret == want_ret).all()
+            assert (f == want_fnv).all()
+            st = ctx.stats()
+            assert st["requests"] == n
+            if piece <= 256:
+                assert st["merged"] > 0 and st["host_calls"] < n
+        r.close()
+    finally:
+        assert ctx.shutdown() == 0
 
 
 def test_injected_errno_seen_by_the_gpu(gs):

@@ -80,3 +80,34 @@ def test_kv_short_and_long_datagrams(gs):
     cli.close()
     srv.close()
     ix.close()
+
+
+def test_kv_full_table_sampled_requests(gs):
+    """The key-value config's table size: 1,000,000 keys (values 32-1,024 B,
+    load 0.5) served by the benchmark's 16 work-groups with 256-datagram
+    batches; 200,000 Zipf(0.99) GETs with planted misses, every reply
+    byte-exact per request id against the oracle."""
+    g, ctx = gs
+    from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
+    kv = synth.kv_set(n_keys=1_000_000, n_req=200_000, miss_every=64)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=16, batch=256)
+    reqs = make_requests(kv.req_keys)
+    say("kv 1M keys")
+    srv.start(lifetime_ms=120_000)
+    try:
+        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=4, window=64)
+    finally:
+        srv.stop()
+    assert got == len(reqs)
+    bad = 0
+    hits = 0
+    for k in range(len(reqs)):
+        want = ix.reply(reqs[k].tobytes())
+        hits += want[8] == 0
+        if rlen[k] != len(want) or replies[k, :rlen[k]].tobytes() != want:
+            bad += 1
+    assert bad == 0
+    assert 0 < hits < len(reqs)
+    srv.close()
+    ix.close()
