@@ -57,7 +57,10 @@ def parse():
     ap.add_argument("--staging-mib", type=int, default=0,
                     help="persistent form: staging ring size (0 = one slot per item)")
     ap.add_argument("--only", default="", help="profiling aid: 'plain' or 'persistent' only")
-    ap.add_argument("--kv-grid", type=int, default=16, help="kv: server work-groups")
+    ap.add_argument("--kv-grid", type=int, default=0,
+                    help="kv: server work-groups (0 = the autotuned value)")
+    ap.add_argument("--kv-batch", type=int, default=0,
+                    help="kv: datagrams per list call (0 = the autotuned value)")
     ap.add_argument("--kv-clients", type=int, default=4, help="kv: load generator threads")
     ap.add_argument("--kv-window", type=int, default=128, help="kv: outstanding per client")
     ap.add_argument("--kv-doorbell", action="store_true",
@@ -68,7 +71,7 @@ def parse():
     ap.add_argument("--serve-ledger", action="store_true",
                     help="serve: record every call and report host service times by call")
     ap.add_argument("--serve-grid", type=int, default=0,
-                    help="serve: persistent work-groups (0 = the library default, 64)")
+                    help="serve: persistent work-groups (0 = the autotuned value)")
     ap.add_argument("--serve-sleep-max", type=int, default=0,
                     help="serve: cap of the device waiters' backoff (s_sleep steps, 0 = default)")
     ap.add_argument("--serve-ledger-out", default="",
@@ -468,11 +471,12 @@ def run_wordscan(args, sub=False):
     print("corpus %d files %.1f MiB, setup %.1fs" % (len(c.paths), c.total_bytes / 2**20,
                                                      time.time() - t0), file=sys.stderr, flush=True)
     from paper_1705_06965_amd import autotune
-    pollers = args.service_threads if args.service_threads >= 0 else \
-        autotune.load("wordscan")["service_threads"]
-    ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
+    tw_ = autotune.load("wordscan")
+    pollers = args.service_threads if args.service_threads >= 0 else tw_["service_threads"]
+    ctx = g.Context(ring_slots=1 << 16, service_threads=pollers, sleep_max=tw_["sleep_max"],
                     device_timeout_ns=60_000_000_000)
-    r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20)
+    r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20,
+                       persistent_buffers=tw_["buffers"])
     stream = torch.cuda.current_stream()
 
     def timed(form, steps, warmup):
@@ -534,7 +538,8 @@ def run_wordscan(args, sub=False):
                                "64 queries, 1 MiB chunk preads", "form": "persistent",
                    "files": len(c.paths), "bytes": c.total_bytes, "chunks": r.n_chunks,
                    "service_threads": int(ctx.cfg.service_threads) or
-                   max(1, len(os.sched_getaffinity(0)) - 1)},
+                   max(1, len(os.sched_getaffinity(0)) - 1),
+                   "tuned": tw_},
         "link_frac": round(gbps / LINK_PEAK_GBPS, 4),
         "syscalls_per_s": round(st["host_calls"] / total, 1),
         "step_ms_p50": round(1e3 * percentile(wall, 50), 3),
@@ -574,12 +579,18 @@ def run_kv(args, sub=False):
           file=sys.stderr, flush=True)
     # the pool gets the threads the oracle's CPU server gets: every core the
     # load generator's clients leave free
-    pollers = args.service_threads if args.service_threads >= 0 else \
-        max(1, len(os.sched_getaffinity(0)) - args.kv_clients)
+    from paper_1705_06965_amd import autotune
+    tk_ = autotune.load("kv")
+    if args.kv_grid:
+        tk_["grid"] = args.kv_grid
+    if args.kv_batch:
+        tk_["batch"] = args.kv_batch
+    pollers = args.service_threads if args.service_threads >= 0 else tk_["service_threads"]
     ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
                     device_timeout_ns=60_000_000_000,
                     flags=g.CFG_DOORBELL if args.kv_doorbell else 0)
-    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=args.kv_grid)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=tk_["grid"],
+                   batch=tk_["batch"])
     # beside the sweep: one warm-up pass and two timed passes of the 4M GETs
     warmup = 1 if sub else args.warmup
     steps = 2 if sub else max(1, min(args.steps, 3))
@@ -646,7 +657,8 @@ def run_kv(args, sub=False):
         "config": {"workload": "key-value GET over loopback UDP: 1M 16-byte keys, values "
                                "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, 256-datagram "
                                "recvfrom/sendto list calls per work-group",
-                   "server_workgroups": args.kv_grid, "client_threads": args.kv_clients,
+                   "server_workgroups": tk_["grid"], "batch": tk_["batch"],
+                   "tuned": tk_, "client_threads": args.kv_clients,
                    "service_threads": pollers,
                    "client_window": args.kv_window, "doorbell": bool(args.kv_doorbell)},
         # calls the GPU's lists asked for (datagrams received or sent) and the
@@ -691,17 +703,25 @@ def run_serve(args, sub=False):
     out_path = os.path.join(synth.data_dir(), "serve_out.bin")
     print("job stream %d jobs (%s), setup %.1fs" % (len(js.kind), np.bincount(js.kind).tolist(),
                                                    time.time() - t0), file=sys.stderr, flush=True)
-    ctx = g.Context(ring_slots=1 << 16, service_threads=max(0, args.service_threads),
+    from paper_1705_06965_amd import autotune
+    ts_ = autotune.load("serve")
+    if args.serve_grid:
+        ts_["grid"] = args.serve_grid
+    if args.serve_sleep_max:
+        ts_["sleep_max"] = args.serve_sleep_max
+    if args.service_threads >= 0:
+        ts_["service_threads"] = args.service_threads
+    ctx = g.Context(ring_slots=1 << 16, service_threads=ts_["service_threads"],
                     device_timeout_ns=60_000_000_000, arena_bytes=16 << 30,
                     flags=g.CFG_LEDGER if args.serve_ledger else 0, ledger_capacity=1 << 22,
-                    sleep_max=args.serve_sleep_max)
+                    sleep_max=ts_["sleep_max"])
     sr = ServeRun(ctx, js, in_path, out_path)
     warm = min(5000, len(js.kind) // 10)
 
     def session(form, inflight, n_limit=None):
         t1 = time.perf_counter()
         res, dig, lat = sr.run(form, max_inflight=inflight, staging_bytes=(2 << 20) * 256,
-                               grid=args.serve_grid if form == g.PERSISTENT else 0,
+                               grid=ts_["grid"] if form == g.PERSISTENT else 0,
                                timeout_ns=300_000_000_000)
         dt = time.perf_counter() - t1
         return res, dig, lat, dt
@@ -834,7 +854,7 @@ def run_serve(args, sub=False):
                                "10/60/30%%" % args.serve_rate,
                    "jobs": len(js.kind), "warmup_jobs": warm, "max_inflight": args.serve_inflight,
                    "form": "persistent (continuous batching)",
-                   "persistent_workgroups": args.serve_grid or 64},
+                   "persistent_workgroups": ts_["grid"], "tuned": ts_},
         "latency_us_p50": round(float(np.percentile(lat_s, 50)), 1),
         "latency_us_p99": round(float(np.percentile(lat_s, 99)), 1),
         "offered_jobs_per_s": args.serve_rate,
