@@ -280,3 +280,22 @@ def test_injected_errno_seen_by_the_gpu(gs):
     assert bad.sum() == 7
     assert (ret[~bad] == want_ret[~bad]).all() and (f[~bad] == want_fnv[~bad]).all()
     r.close()
+
+
+@pytest.mark.parametrize("wg", [64, 256, 1024])
+def test_direct_descriptor_lists_match_oracle(gs, mid, wg, monkeypatch):
+    """Strong work-group cells with every work-item writing its own
+    descriptor straight into the host-visible list (GSYS_LDS_LISTS=0, the
+    alternative to aggregating the list in LDS): the oracle's vector."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    r0, (want_fnv, want_ret) = mid
+    offs = r0.offsets.cpu().numpy().view(np.uint64)
+    r = FnvRunner(ctx, r0.path, offs, 4096, wg_size=wg)
+    monkeypatch.setenv("GSYS_LDS_LISTS", "0")
+    for cell in [("WG", "strong", "block"), ("WG", "strong", "nonblock")]:
+        say("direct lists", wg, cell)
+        f, ret = r.run(*cell)
+        assert (ret == want_ret).all(), (wg, cell)
+        assert (f == want_fnv).all(), (wg, cell)
+    r.close()
