@@ -577,10 +577,26 @@ def run_kv(args, sub=False):
     reqs = make_requests(kv.req_keys)
     print("kv set %d keys, %d requests, setup %.1fs" % (len(kv.keys), len(reqs), time.time() - t0),
           file=sys.stderr, flush=True)
-    # the pool gets the threads the oracle's CPU server gets: every core the
-    # load generator's clients leave free
+    if not sub:
+        return emit(_kv_run(args, kv, reqs, args.kv_clients, sub), sub)
+    # beside the sweep: 4 load-generator threads, and 8 as a second figure
+    res = _kv_run(args, kv, reqs, 4, sub)
+    res["clients8"] = {k: v for k, v in _kv_run(args, kv, reqs, 8, sub).items()
+                       if k not in SUB_DROP + ("steps", "warmup")}
+    return emit(res, sub)
+
+
+def _kv_run(args, kv, reqs, clients, sub):
+    """One key-value measurement with `clients` load-generator threads; the
+    pool's knobs come from the cache entry tuned for that client count."""
+    import socket
+    import struct
+    import threading
+    import numpy as np
+    import paper_1705_06965_amd as g
+    from paper_1705_06965_amd.kv import KVServer, loadgen
     from paper_1705_06965_amd import autotune
-    tk_ = autotune.load("kv")
+    tk_ = autotune.load("kv8" if clients == 8 else "kv")
     if args.kv_grid:
         tk_["grid"] = args.kv_grid
     if args.kv_batch:
@@ -599,7 +615,7 @@ def run_kv(args, sub=False):
         ctx.stats(reset=True)
         srv.start(lifetime_ms=300_000)
         t1 = time.perf_counter()
-        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=args.kv_clients,
+        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=clients,
                                               window=args.kv_window, timeout_ns=120_000_000_000)
         dt = time.perf_counter() - t1
         srv.stop()
@@ -621,7 +637,7 @@ def run_kv(args, sub=False):
     if not args.no_cpu:
         # the oracle as a CPU server on the same loopback path, same client
         n_cpu = 1_000_000
-        threads = max(1, len(os.sched_getaffinity(0)) - args.kv_clients)
+        threads = max(1, len(os.sched_getaffinity(0)) - clients)
         sock = socket.socket(socket.AF_INET, socket.SOCK_DGRAM)
         for opt in (socket.SO_RCVBUF, socket.SO_SNDBUF):
             sock.setsockopt(socket.SOL_SOCKET, opt, 8 << 20)
@@ -633,7 +649,7 @@ def run_kv(args, sub=False):
             t.start()
         t1 = time.perf_counter()
         gc, rc_, rl_, lat_c, _ = loadgen(sock.getsockname()[1], reqs[:n_cpu],
-                                         threads=args.kv_clients, window=args.kv_window)
+                                         threads=clients, window=args.kv_window)
         dtc = time.perf_counter() - t1
         for t in ths:
             t.join()
@@ -658,13 +674,14 @@ def run_kv(args, sub=False):
                                "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, 256-datagram "
                                "recvfrom/sendto list calls per work-group",
                    "server_workgroups": tk_["grid"], "batch": tk_["batch"],
-                   "tuned": tk_, "client_threads": args.kv_clients,
+                   "tuned": tk_, "client_threads": clients,
                    "service_threads": pollers,
                    "client_window": args.kv_window, "doorbell": bool(args.kv_doorbell)},
         # calls the GPU's lists asked for (datagrams received or sent) and the
         # kernel entries the host used for them (recvmmsg / sendmmsg batches)
         "syscalls_per_s": round((stt["host_calls"] + stt["merged"]) / dts[-1], 1),
         "host_kernel_calls_per_s": round(stt["host_calls"] / dts[-1], 1),
+        "pool_busy_frac": round(stt["service_ns"] / 1e9 / max(1e-9, dts[-1]) / max(1, pollers), 3),
         "latency_us_p50": round(float(np.percentile(lat_all, 50)) / 1e3, 1),
         "latency_us_p99": round(float(np.percentile(lat_all, 99)) / 1e3, 1),
         "reply_GBps": round(reply_bytes / dt_med / 1e9, 3),
@@ -676,9 +693,10 @@ def run_kv(args, sub=False):
     }
     if cpu:
         res["cpu_baseline"] = cpu
+        res["over_cpu_baseline"] = round(res["value"] / cpu["value"], 3)
     srv.close()
     ctx.shutdown()
-    return emit(res, sub)
+    return res
 
 
 def run_serve(args, sub=False):

@@ -12,9 +12,9 @@ value so far; a new value must beat the best by 1% to replace it.
   serve     grid (persistent work-groups), sleep_max, service_threads;
             objective: p99 latency at the offered load, among settings that
             keep up with it
-  kv        grid (server work-groups), batch (datagrams per list call),
-            service_threads (with 4 load-generator threads on the same
-            host); objective: GETs per second
+  kv, kv8   grid (server work-groups), batch (datagrams per list call),
+            service_threads, with 4 (kv) or 8 (kv8) load-generator threads
+            on the same host; objective: GETs per second
 """
 from __future__ import annotations
 
@@ -37,6 +37,7 @@ DEFAULTS_BY = {
     "wordscan": {"service_threads": 12, "buffers": 256, "sleep_max": 64},
     "serve": {"grid": 64, "sleep_max": 64, "service_threads": 0},
     "kv": {"grid": 16, "batch": 256, "service_threads": 12},
+    "kv8": {"grid": 16, "batch": 256, "service_threads": 8},
 }
 SPACE_BY = {
     "wordscan": [("service_threads", [8, 10, 12, 14, 15]), ("buffers", [128, 256, 512]),
@@ -45,6 +46,8 @@ SPACE_BY = {
               ("service_threads", [12, 14, 15])],
     "kv": [("grid", [8, 16, 32]), ("batch", [64, 128, 256]),
            ("service_threads", [8, 10, 12])],
+    "kv8": [("grid", [4, 8, 16, 32]), ("service_threads", [6, 7, 8]),
+            ("batch", [128, 256])],
 }
 
 
@@ -216,7 +219,7 @@ def measure_kv(params: dict, kv, reqs, clients: int = 4) -> float:
 
 
 def tune(workload: str, log=print) -> dict:
-    """Tune one of wordscan, serve, kv on this machine; returns the cache entry."""
+    """Tune one of wordscan, serve, kv, kv8 on this machine; returns the cache entry."""
     import synth
     if workload == "wordscan":
         corpus = synth.wordcount_corpus()
@@ -231,11 +234,12 @@ def tune(workload: str, log=print) -> dict:
         out_path = os.path.join(synth.data_dir(), "tune_serve_out.bin")
         measure = lambda p: measure_serve(p, jobs, in_path, out_path, 20_000.0)  # noqa: E731
         unit, low = "p99_us", True
-    elif workload == "kv":
+    elif workload in ("kv", "kv8"):
         from paper_1705_06965_amd.kv import make_requests
         kv = synth.kv_set(n_req=1_000_000)
         reqs = make_requests(kv.req_keys)
-        measure = lambda p: measure_kv(p, kv, reqs)  # noqa: E731
+        clients = 8 if workload == "kv8" else 4
+        measure = lambda p: measure_kv(p, kv, reqs, clients)  # noqa: E731
         unit, low = "GET_per_s", False
     else:
         raise ValueError(workload)
