@@ -87,7 +87,8 @@ typedef struct gsys_config {
  * quiet, at the price of the interrupt's latency (~75 us) on the first
  * request after a pause.
  * In a GSYS_CFG_NO_DEVICE context the doorbell is a condition variable that
- * the emulated callers (gsys_testing.h) raise the same way.
+ * host threads that emulate GPU callers (the tests' hook library) raise the
+ * same way.
  * cfg == NULL uses all defaults.  *out receives the context.
  * Errors: -EINVAL (bad D / version), -ENOMEM, -ENODEV (HIP failure),
  * -ENOTSUP (GSYS_CFG_DOORBELL, but no interrupt signal mapped for the GPU).

@@ -34,7 +34,6 @@ PLAIN, PERSISTENT, GRAPH = 0, 1, 2
 CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS, CFG_DOORBELL = 0x1, 0x2, 0x4, 0x8, 0x10
 FD_READ, FD_WRITE, FD_SOCK, FD_DIR = 0x1, 0x2, 0x4, 0x8
 BUF_HOST, BUF_DEVICE = 1, 2
-EMU_BLOCKING, EMU_LIST = 0x1, 0x2
 NOT_WAITED = -115   # a non-blocking call's result slot before anyone waited
 
 
@@ -150,13 +149,6 @@ _SIGS = {
                                       C.c_uint64, C.c_uint64, C.c_uint32, _P]),
     "gsys_file_kernel_io": (C.c_int, [_P, C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
                                       C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P]),
-    "gsys_test_emulate": (C.c_int, [_P, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
-                                    C.c_uint64, C.c_uint64, C.c_uint32, _P, _P, C.c_uint64]),
-    "gsys_test_raw_call": (C.c_int, [_P, C.c_uint16, C.c_uint8, _P, _P, C.c_uint64]),
-    "gsys_test_claim_only": (C.c_int64, [_P, C.c_uint32]),
-    "gsys_test_ring_ctl": (C.c_int, [_P, _P, C.c_uint64]),
-    "gsys_test_inject": (C.c_int, [_P, C.c_uint16, C.c_int32, C.c_uint32]),
-    "gsys_test_unregister_now": (C.c_int, [_P, C.c_uint32]),
 }
 
 if not os.path.exists(LIB_PATH):

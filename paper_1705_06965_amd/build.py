@@ -21,6 +21,10 @@ HIP_SOURCES = ["k_fnv.hip", "k_wordscan.hip", "k_kv.hip", "k_serve.hip", "k_cana
 # a user program of the library, built against include/ only
 DEMO_SRC = os.path.join(HERE, "demo", "pread_fnv.hip")
 DEMO_LIB = os.path.join(HERE, "libgsys_demo.so")
+# the test-only hook library (tests load it; the product never does)
+HOOKS_DIR = os.path.join(ROOT, "tests", "native")
+HOOKS_SRC = os.path.join(HOOKS_DIR, "gsys_test_hooks.cpp")
+HOOKS_LIB = os.path.join(HOOKS_DIR, "libgsys_testing.so")
 HOST_HIP_SOURCES = ["capi.cpp"]      # host code that calls the HIP runtime
 HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp"]     # plain C++17 + POSIX
 
@@ -70,6 +74,13 @@ def build(verbose: bool = False) -> str:
          + ["-L" + HERE, "-lgsys", "-Wl,-rpath,$ORIGIN", "-Wl,--no-undefined",
             "-L" + os.path.join(ROCM, "lib"), "-lamdhip64"])
     os.replace(tmp, DEMO_LIB)
+    if os.path.exists(HOOKS_SRC):
+        tmp = HOOKS_LIB + ".tmp%d" % os.getpid()
+        _run(["g++", "-shared", "-fPIC", "-O2", "-std=c++17", "-Wall", "-pthread",
+              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + HOOKS_DIR,
+              HOOKS_SRC, "-o", tmp, "-L" + HERE, "-lgsys",
+              "-Wl,-rpath,$ORIGIN/../../paper_1705_06965_amd", "-Wl,--no-undefined"])
+        os.replace(tmp, HOOKS_LIB)
     return LIB
 
 

@@ -23,7 +23,8 @@ uint64_t hash_words(std::initializer_list<uint64_t> w);
 // Two host-coherent control words owned by the context (a 256-byte line of
 // the page set up by gsys_init; nothing is allocated here).
 int control_page(gsys_ctx* ctx, void** host, uint64_t* dev);
-// true for a CPU-only context (GSYS_CFG_NO_DEVICE): nothing may be launched.
+// true for a CPU-only context (GSYS_CFG_NO_DEVICE): nothing may be launched
+// (declared with the other test accessors in testing_access.hpp too).
 bool no_device(gsys_ctx* ctx);
 // The HIP device ordinal of the context.
 int device_of(gsys_ctx* ctx);

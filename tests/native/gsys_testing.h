@@ -1,6 +1,8 @@
 /*
- * Test hooks of libgsys.so.  They let CPU-only tests drive the host service
- * pool through exactly the protocol the GPU uses, without a GPU.
+ * Test hooks of the gsys library: libgsys_testing.so, a library only tests
+ * load, linked against libgsys.so (not part of the product ABI).  They let
+ * CPU-only tests drive the host service pool through exactly the protocol
+ * the GPU uses, without a GPU, and inject faults.
  */
 #ifndef GSYS_TESTING_H
 #define GSYS_TESTING_H

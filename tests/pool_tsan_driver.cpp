@@ -15,8 +15,9 @@
 // unregistering returned.  Exits 0 when all checks pass; ThreadSanitizer
 // turns any data race into a non-zero exit.
 //
-// Build: g++ -fsanitize=thread over this file, capi.cpp and host_pool.cpp
-// (host code only; contexts use GSYS_CFG_NO_DEVICE and make no HIP calls).
+// Build: g++ -fsanitize=thread over this file, native/gsys_test_hooks.cpp,
+// capi.cpp and host_pool.cpp (host code only; contexts use
+// GSYS_CFG_NO_DEVICE and make no HIP calls).
 #include <errno.h>
 #include <fcntl.h>
 #include <stdint.h>

@@ -273,7 +273,8 @@ def test_injected_errno_seen_by_the_gpu(gs):
     offs = synth.tiny_offsets(64)
     want_fnv, want_ret = oracle.pread_fnv(p, offs, 4096)
     r = FnvRunner(ctx, p, offs, 4096, wg_size=64)
-    assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 7) == 0
+    import gsys_hooks as hooks
+    assert hooks.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 7) == 0
     say("tiny with 7 injected -EIO")
     f, ret = r.run("WI", "strong", "block")
     bad = ret == -errno.EIO

@@ -12,6 +12,7 @@ import pytest
 import oracle
 import synth
 import paper_1705_06965_amd as g
+import gsys_hooks as hooks
 
 
 @pytest.fixture(scope="module")
@@ -34,15 +35,15 @@ def _run(ctx, fd, offs, threads, group, mode, item=4096):
     lists = ctx.host_alloc(n * 16)
     rets = np.zeros(n, dtype=np.int64)
     offs = np.ascontiguousarray(offs, dtype=np.uint64)
-    rc = g.lib.gsys_test_emulate(ctx.h, threads, n // threads, group, mode, fd, buf.dev,
+    rc = hooks.lib.gsys_test_emulate(ctx.h, threads, n // threads, group, mode, fd, buf.dev,
                                  lists.dev, item, offs.ctypes.data, rets.ctypes.data,
                                  20_000_000_000)
     assert rc == 0, g.lib.gsys_strerror(rc)
     return buf, rets
 
 
-@pytest.mark.parametrize("group,mode", [(64, g.EMU_BLOCKING), (8, 0), (1, g.EMU_BLOCKING),
-                                        (64, g.EMU_LIST | g.EMU_BLOCKING), (16, g.EMU_LIST)])
+@pytest.mark.parametrize("group,mode", [(64, hooks.EMU_BLOCKING), (8, 0), (1, hooks.EMU_BLOCKING),
+                                        (64, hooks.EMU_LIST | hooks.EMU_BLOCKING), (16, hooks.EMU_LIST)])
 def test_emulated_wavefronts_match_oracle(datafile, group, mode):
     n_blocks = (4 << 20) // 4096
     offs = synth.sweep_offsets(2048, n_blocks)
@@ -63,7 +64,7 @@ def test_emulated_wavefronts_match_oracle(datafile, group, mode):
         # exactly once: every claimed ticket serviced once, nothing else
         assert len(led) == claimed
         assert (np.sort(led[:, 0]) == np.arange(claimed, dtype=np.uint64)).all()
-        if mode & g.EMU_LIST:
+        if mode & hooks.EMU_LIST:
             assert claimed == len(offs) // group
             assert st["host_calls"] <= len(offs)
         else:
@@ -82,7 +83,7 @@ def test_tiny_ring_back_pressure_and_quiescence(datafile):
     ctx = _ctx(ring_slots=64, service_threads=3)
     try:
         ctx.allow_fd(fd, g.FD_READ)
-        buf, rets = _run(ctx, fd, offs, 8, 64, g.EMU_BLOCKING, item=256)
+        buf, rets = _run(ctx, fd, offs, 8, 64, hooks.EMU_BLOCKING, item=256)
         assert (rets == 256).all()
         data = buf.view(np.uint8).reshape(len(offs), 256)
         for i in range(0, len(offs), 97):
@@ -91,7 +92,7 @@ def test_tiny_ring_back_pressure_and_quiescence(datafile):
         st = ctx.stats()
         assert st["claimed"] == 4096 and st["retired_lo"] == 4096
         ctl = np.zeros(64, dtype=np.uint64)
-        g.lib.gsys_test_ring_ctl(ctx.h, ctl.ctypes.data, 64)
+        hooks.lib.gsys_test_ring_ctl(ctx.h, ctl.ctypes.data, 64)
         # quiescent: every slot FREE for its next lap
         t = np.arange(64, dtype=np.uint64) + np.uint64(4096)
         assert (ctl == (t << np.uint64(3))).all()
@@ -106,7 +107,7 @@ def test_coalescing_merges_adjacent_reads(datafile):
     ctx = _ctx(ring_slots=4096, service_threads=2, coalesce_max=8, coalesce_window_ns=200_000)
     try:
         ctx.allow_fd(fd, g.FD_READ)
-        buf, rets = _run(ctx, fd, offs, 1, 64, g.EMU_BLOCKING)
+        buf, rets = _run(ctx, fd, offs, 1, 64, hooks.EMU_BLOCKING)
         assert (rets == 4096).all()
         assert buf.view(np.uint8)[:4 << 20].tobytes() == open(datafile, "rb").read()
         st = ctx.stats()
@@ -128,7 +129,7 @@ def test_short_reads_at_eof(tmpdata):
     ctx = _ctx()
     try:
         ctx.allow_fd(fd, g.FD_READ)
-        for mode in (g.EMU_BLOCKING, g.EMU_LIST | g.EMU_BLOCKING):
+        for mode in (hooks.EMU_BLOCKING, hooks.EMU_LIST | hooks.EMU_BLOCKING):
             buf, rets = _run(ctx, fd, offs, 1, 8, mode)
             assert rets.tolist() == want_ret.tolist()
             d = buf.view(np.uint8).reshape(8, 4096)
@@ -143,7 +144,7 @@ def _raw(ctx, nr, args, flags=g.F_BLOCKING):
     a = np.array([int(x) & 0xFFFFFFFFFFFFFFFF for x in args] + [0] * (6 - len(args)),
                  dtype=np.uint64)
     r = np.zeros(1, dtype=np.int64)
-    rc = g.lib.gsys_test_raw_call(ctx.h, nr, flags, a.ctypes.data, r.ctypes.data, 5_000_000_000)
+    rc = hooks.lib.gsys_test_raw_call(ctx.h, nr, flags, a.ctypes.data, r.ctypes.data, 5_000_000_000)
     assert rc == 0
     return int(r[0])
 
@@ -268,17 +269,28 @@ def test_udp_loopback_sendto_recvfrom():
 
 def test_drain_times_out_on_unpublished_claims():
     ctx = _ctx()
-    t = g.lib.gsys_test_claim_only(ctx.h, 3)
+    t = hooks.lib.gsys_test_claim_only(ctx.h, 3)
     assert t == 0
     assert ctx.wait(50_000_000) == -errno.ETIMEDOUT
     assert ctx.shutdown(50_000_000) == -errno.ETIMEDOUT
 
 
 def test_exported_symbols_exist():
+    """libgsys.so exports every function include/ declares and none of the
+    test hooks; the hook library exports every hook its header declares."""
     names = g.exported_symbols()
-    assert "gsys_init" in names and "gsys_fnv4k" in names and "gsys_test_emulate" in names
+    assert "gsys_init" in names and "gsys_fnv4k" in names and "gsys_serve_run_noalloc" in names
+    assert not [n for n in names if n.startswith("gsys_test_")]
     for n in names:
         assert hasattr(g.lib, n), n
+    import subprocess
+    dyn = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    assert "gsys_test_" not in dyn
+    hook_names = hooks.declared()
+    assert "gsys_test_emulate" in hook_names and "gsys_test_inject" in hook_names
+    for n in hook_names:
+        assert hasattr(hooks.lib, n), n
 
 
 def _links_to(path):
@@ -306,7 +318,7 @@ def test_per_thread_file_copies(datafile, shared):
     ctx = _ctx(ring_slots=1024, flags=g.CFG_SHARED_FDS if shared else 0)
     try:
         ctx.allow_fd(fd, g.FD_READ)
-        buf, rets = _run(ctx, fd, offs, 8, 1, g.EMU_BLOCKING)
+        buf, rets = _run(ctx, fd, offs, 8, 1, hooks.EMU_BLOCKING)
         assert (rets == want_ret).all()
         data = buf.view(np.uint8).reshape(len(offs), 4096)
         got = np.array([oracle.fnv1a64(data[i]) for i in range(len(offs))], dtype=np.uint64)
@@ -335,14 +347,14 @@ def test_reused_fd_number_reads_the_new_file(tmpdata):
     try:
         ctx.allow_fd(fa, g.FD_READ)
         offs = np.zeros(64, dtype=np.uint64)
-        buf, rets = _run(ctx, fa, offs, 4, 1, g.EMU_BLOCKING)
+        buf, rets = _run(ctx, fa, offs, 4, 1, hooks.EMU_BLOCKING)
         assert (rets == 4096).all() and (buf.view(np.uint8)[:64 * 4096] == ord("A")).all()
         ctx.allow_fd(fa, 0)
         fb = os.open(b, os.O_RDONLY)
         os.dup2(fb, fa)                       # the same number now names fd_b.bin
         os.close(fb)
         ctx.allow_fd(fa, g.FD_READ)
-        buf2, rets2 = _run(ctx, fa, offs, 4, 1, g.EMU_BLOCKING)
+        buf2, rets2 = _run(ctx, fa, offs, 4, 1, hooks.EMU_BLOCKING)
         assert (rets2 == 4096).all() and (buf2.view(np.uint8)[:64 * 4096] == ord("B")).all()
     finally:
         assert ctx.shutdown() == 0
@@ -362,13 +374,13 @@ def test_copies_keep_append_and_write_modes(tmpdata):
         src.array[:4096] = np.arange(4096, dtype=np.uint64).astype(np.uint8)
         ret = C.c_int64(0)
         args = (C.c_uint64 * 6)(fd, src.dev, 4096, 8192, 0, 0)
-        assert g.lib.gsys_test_raw_call(ctx.h, g.NR_PWRITE64, g.F_BLOCKING, args, C.byref(ret),
+        assert hooks.lib.gsys_test_raw_call(ctx.h, g.NR_PWRITE64, g.F_BLOCKING, args, C.byref(ret),
                                         5_000_000_000) == 0
         assert ret.value == 4096
         got = open(p, "rb").read()
         assert len(got) == 12288 and got[8192:] == src.array[:4096].tobytes()
         args = (C.c_uint64 * 6)(fd, src.dev, 4096, 0, 0, 0)
-        assert g.lib.gsys_test_raw_call(ctx.h, g.NR_PREAD64, g.F_BLOCKING, args, C.byref(ret),
+        assert hooks.lib.gsys_test_raw_call(ctx.h, g.NR_PREAD64, g.F_BLOCKING, args, C.byref(ret),
                                         5_000_000_000) == 0
         assert ret.value == -errno.EBADF
     finally:
@@ -571,7 +583,7 @@ def test_doorbell_races_with_callers(datafile, monkeypatch):
         for burst in range(12):
             offs = synth.sweep_offsets(256, n_blocks, config=10 + burst)
             want_fnv, want_ret = oracle.pread_fnv(datafile, offs, 4096)
-            group, mode = [(64, g.EMU_BLOCKING), (1, 0), (16, g.EMU_LIST)][burst % 3]
+            group, mode = [(64, hooks.EMU_BLOCKING), (1, 0), (16, hooks.EMU_LIST)][burst % 3]
             buf, rets = _run(ctx, fd, offs, 4, group, mode)
             assert (rets == want_ret).all()
             data = buf.view(np.uint8).reshape(len(offs), 4096)
@@ -658,9 +670,9 @@ def test_injected_errno_reaches_the_caller(datafile):
     ctx = _ctx(ring_slots=256)
     try:
         ctx.allow_fd(fd, g.FD_READ)
-        assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 5) == 0
+        assert hooks.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 5) == 0
         offs = synth.sweep_offsets(64, (4 << 20) // 4096)
-        buf, rets = _run(ctx, fd, offs, 1, 64, g.EMU_BLOCKING)
+        buf, rets = _run(ctx, fd, offs, 1, 64, hooks.EMU_BLOCKING)
         assert (rets == -errno.EIO).sum() == 5
         ok = rets != -errno.EIO
         assert (rets[ok] == 4096).all()
@@ -671,7 +683,7 @@ def test_injected_errno_reaches_the_caller(datafile):
         assert ctx.stats()["errno_hist"][7] == 5
         # used up: the next call runs normally
         assert _raw(ctx, g.NR_PREAD64, [fd, buf.dev, 16, 0]) == 16
-        assert g.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, 0, 1) == -errno.EINVAL
+        assert hooks.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, 0, 1) == -errno.EINVAL
     finally:
         ctx.shutdown()
         os.close(fd)

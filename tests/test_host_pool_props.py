@@ -15,6 +15,7 @@ from hypothesis import strategies as st
 
 import oracle
 import paper_1705_06965_amd as g
+import gsys_hooks as hooks
 
 BUF = 1 << 16
 
@@ -59,7 +60,7 @@ def test_list_calls_equal_individual_preads(pool, data, segs):
         lst.array[:L.nbytes] = L.view(np.uint8)
         a = np.array([fd, lst.dev, len(descs), buf.dev, 0, 0], dtype=np.uint64)
         r = np.zeros(1, dtype=np.int64)
-        assert g.lib.gsys_test_raw_call(
+        assert hooks.lib.gsys_test_raw_call(
             ctx.h, g.NR_PREAD64, g.F_LIST | g.F_BLOCKING | (g.GRAN_WG << 4), a.ctypes.data,
             r.ctypes.data, 5_000_000_000) == 0
         got = lst.array[:L.nbytes].view(L.dtype)["len_ret"]
@@ -111,7 +112,7 @@ def test_contiguous_list_is_one_pread(pool):
         s0 = ctx.stats()
         a = np.array([fd, lst.dev, 8, buf.dev, 0, 0], dtype=np.uint64)
         r = np.zeros(1, dtype=np.int64)
-        assert g.lib.gsys_test_raw_call(ctx.h, g.NR_PREAD64, g.F_LIST | g.F_BLOCKING | (g.GRAN_WG << 4),
+        assert hooks.lib.gsys_test_raw_call(ctx.h, g.NR_PREAD64, g.F_LIST | g.F_BLOCKING | (g.GRAN_WG << 4),
                                         a.ctypes.data, r.ctypes.data, 5_000_000_000) == 0
         s1 = ctx.stats()
         assert int(r[0]) == 4096

@@ -29,7 +29,9 @@ def test_pool_under_sanitizer(tmp_path, tmpdata, sanitizer):
     cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=" + sanitizer,
            "-fno-sanitize-recover=all", "-D__HIP_PLATFORM_AMD__",
            "-I" + os.path.join(ROCM, "include"), "-I" + os.path.join(ROOT, "include"),
-           "-I" + CSRC, os.path.join(ROOT, "tests", "pool_tsan_driver.cpp"),
+           "-I" + CSRC, "-I" + os.path.join(ROOT, "tests", "native"),
+           os.path.join(ROOT, "tests", "pool_tsan_driver.cpp"),
+           os.path.join(ROOT, "tests", "native", "gsys_test_hooks.cpp"),
            os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "host_pool.cpp"), "-o", exe,
            "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhsa-runtime64", "-pthread",
            "-Wl,-rpath," + os.path.join(ROCM, "lib")]
