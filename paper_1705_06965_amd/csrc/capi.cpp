@@ -579,8 +579,16 @@ uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t
   int per_cu = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, lds);
   if (e != hipSuccess || per_cu < 1) {
-    fprintf(stderr, "gsys: no resident work-group fits (%s; block %u, LDS %u bytes)\n",
-            e != hipSuccess ? hipGetErrorString(e) : "occupancy 0", block, lds);
+    hipFuncAttributes a{};
+    const hipError_t ea = hipFuncGetAttributes(&a, kernel);
+    int dev = -1;
+    hipGetDevice(&dev);
+    fprintf(stderr,
+            "gsys: no resident work-group fits (%s; block %u, LDS %u bytes; device %d; "
+            "kernel: %s, %d VGPRs, %zu B private, %zu B static LDS, %d threads at most)\n",
+            e != hipSuccess ? hipGetErrorString(e) : "occupancy 0", block, lds, dev,
+            hipGetErrorString(ea), a.numRegs, a.localSizeBytes, a.sharedSizeBytes,
+            a.maxThreadsPerBlock);
     return 0;
   }
   return (uint32_t)per_cu * (uint32_t)c->cu_count;
