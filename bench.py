@@ -105,6 +105,11 @@ PROFILES = {
     "wordscan": ("profiles/wordscan_persistent_corpus_2000.md",
                  ["paper_1705_06965_amd/csrc/k_wordscan.hip"]),
     "permute": ("profiles/permute_pwrite_64m.md", ["paper_1705_06965_amd/csrc/k_permute.hip"]),
+    "tiny": ("profiles/fnv4k_plain_tiny_64.md",
+             ["paper_1705_06965_amd/csrc/k_fnv.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp"]),
+    "serve": ("profiles/serve_persistent_mix_20k.md",
+              ["paper_1705_06965_amd/csrc/k_serve.hip", "paper_1705_06965_amd/csrc/fnv_wave.hpp"]),
+    "kv": ("profiles/kv_serve_get_4m.md", ["paper_1705_06965_amd/csrc/k_kv.hip"]),
 }
 
 
@@ -688,7 +693,8 @@ def _kv_run(args, kv, reqs, clients, sub):
         "retransmits": res_steps[-1][2],
         "roofline": {"bound": "host-cpu",
                      "achieved": round((stt["host_calls"] + stt["merged"]) / dts[-1], 1),
-                     "peak": None, "unit": "syscalls/s", "frac": None, "traffic": None,
+                     "peak": None, "unit": "syscalls/s", "frac": None,
+                     "traffic": profile_traffic("kv") if clients == 4 else None,
                      "kernel": "kv_serve"},
     }
     if cpu:
