@@ -554,6 +554,12 @@ def run_wordscan(args, sub=False):
                      "traffic": profile_traffic("wordscan"), "kernel": "wordscan_persistent", "kernel_ms": round(kavg, 3),
                      "bytes_per_launch": int(link_bytes)},
     }
+    # the host's side of the roofline: the same chunk preads, same threads,
+    # same staging, without the GPU
+    from paper_1705_06965_amd.wordscan import host_pread_rate
+    hp = round(host_pread_rate(r, res["config"]["service_threads"]), 2)
+    res["roofline"]["host_pread_GBps"] = hp
+    res["roofline"]["frac_of_host_pread"] = round(achieved / hp, 4)
     if tw:
         pt, pw, pk, _ = tw
         res["plain_form"] = {"value": round(c.total_bytes * len(pw) / pt / 1e9, 3), "unit": "GB/s",

@@ -394,6 +394,21 @@ int64_t gsys_kv_loadgen(uint32_t server_port, const uint8_t *reqs, uint32_t req_
                         uint8_t *replies, uint32_t reply_stride, uint32_t *reply_len,
                         uint64_t *lat_ns, uint64_t *retransmits);
 
+/*
+ * Host read capacity (a measurement helper, no GPU involved): `threads` host
+ * threads take the n ranges (fds[i], offs[i], lens[i]) in order from a shared
+ * counter and pread range i into dst + (i mod n_slots) * slot_bytes, as the
+ * service pool does for the word search's chunk reads (section 7.1); the best
+ * of `reps` passes, in returned bytes per nanosecond (GB/s), is stored in
+ * *out_gbps.  dst must hold n_slots * slot_bytes bytes (caller-owned).
+ * Returns 0, -EINVAL (a null pointer, n, n_slots, threads or reps of 0,
+ * threads > 1024, or a range longer than slot_bytes) or the -errno of the
+ * first failed pread.
+ */
+int gsys_host_pread_rate(const int *fds, const uint64_t *offs, const uint32_t *lens, uint64_t n,
+                         uint8_t *dst, uint64_t slot_bytes, uint64_t n_slots, uint32_t threads,
+                         uint32_t reps, double *out_gbps);
+
 /* Serving job record (64 bytes, in host-coherent memory). */
 #define GSYS_JOB_SCAN    0u
 #define GSYS_JOB_PWRITE  1u
@@ -528,8 +543,8 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
  *            NUL-terminated paths relative to dirfd
  *   chunk    bytes per read: a multiple of 64, 64 .. 64 MiB
  *   staging  registered host buffer; each resident work-group uses two
- *            buffers of chunk + 16,496 bytes rounded up to 16 (the grid
- *            shrinks to fit)
+ *            buffers of gsys_wordcount_open_buffer_bytes(chunk) bytes (the
+ *            grid shrinks to fit)
  *   progress 0, or a registered host buffer of progress_groups x 16 bytes
  *            (the grid shrinks to progress_groups): work-group w keeps
  *            [2w] = (file + 1) << 32 | phase (1 openat, 2 waiting for a
@@ -539,6 +554,9 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
  * Asynchronous on `stream`; gsys_wait drains the host side.  Errors:
  * -EINVAL, -EFAULT (paths, staging or progress not registered), -ENODEV.
  */
+/* Bytes of one piece buffer of gsys_wordcount_open for reads of `chunk`
+ * bytes: the carried bytes, the piece and the scanner's window past it. */
+uint64_t gsys_wordcount_open_buffer_bytes(uint32_t chunk);
 int gsys_wordcount_open(gsys_ctx *ctx, int dirfd, uint64_t paths, uint32_t nfiles,
                         uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts,
                         uint64_t file_ret, uint32_t chunk, uint64_t staging,

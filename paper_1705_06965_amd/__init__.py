@@ -134,6 +134,10 @@ _SIGS = {
     "gsys_kv_loadgen": (C.c_int64, [C.c_uint32, _P, C.c_uint32, C.c_uint64, C.c_uint32,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _P, C.c_uint32, _P, _P,
                                     _P]),
+    "gsys_wordcount_open_buffer_bytes": (C.c_uint64, [C.c_uint32]),
+    "gsys_host_pread_rate": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64,
+                                       C.c_uint64, C.c_uint32, C.c_uint32,
+                                       C.POINTER(C.c_double)]),
     "gsys_serve_run": (C.c_int, [_P, C.POINTER(gsys_serve_params), _P]),
     "gsys_serve_run_noalloc": (C.c_int, [_P, C.POINTER(gsys_serve_params), _P]),
     "gsys_canary": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,

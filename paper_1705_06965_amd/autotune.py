@@ -34,13 +34,13 @@ SPACE = [("service_threads", [8, 10, 12, 14, 15]),
 
 DEFAULTS_BY = {
     "sweep": DEFAULTS,
-    "wordscan": {"service_threads": 12, "buffers": 256, "sleep_max": 64},
+    "wordscan": {"service_threads": 12, "buffers": 128, "sleep_max": 64},
     "serve": {"grid": 64, "sleep_max": 64, "service_threads": 0},
     "kv": {"grid": 16, "batch": 256, "service_threads": 12},
     "kv8": {"grid": 16, "batch": 256, "service_threads": 8},
 }
 SPACE_BY = {
-    "wordscan": [("service_threads", [8, 10, 12, 14, 15]), ("buffers", [128, 256, 512]),
+    "wordscan": [("service_threads", [8, 10, 12, 14, 15]), ("buffers", [96, 128, 160, 256]),
                  ("sleep_max", [16, 64, 256])],
     "serve": [("grid", [32, 48, 64, 96]), ("sleep_max", [16, 64, 256]),
               ("service_threads", [12, 14, 15])],

@@ -26,7 +26,7 @@ HOOKS_DIR = os.path.join(ROOT, "tests", "native")
 HOOKS_SRC = os.path.join(HOOKS_DIR, "gsys_test_hooks.cpp")
 HOOKS_LIB = os.path.join(HOOKS_DIR, "libgsys_testing.so")
 HOST_HIP_SOURCES = ["capi.cpp"]      # host code that calls the HIP runtime
-HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp"]     # plain C++17 + POSIX
+HOST_SOURCES = ["host_pool.cpp", "kv_loadgen.cpp", "pread_probe.cpp"]     # plain C++17 + POSIX
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -58,7 +58,7 @@ class WordScanRunner:
         self.qlens = torch.from_numpy(ql.view(np.int32)).to(device)
         self.counts = torch.zeros(max(1, self.nfiles * self.nq), dtype=torch.int32, device=device)
         if not persistent_buffers:
-            persistent_buffers = int(os.environ.get("GSYS_WS_BUFFERS", "256"))
+            persistent_buffers = int(os.environ.get("GSYS_WS_BUFFERS", "128"))
         self.persistent_bytes = staging_bytes(chunk_max, min(persistent_buffers,
                                                              2 * max(1, self.n_chunks)))
         self.plain_bytes = staging_bytes(chunk_max, max(1, self.n_chunks))
@@ -97,9 +97,26 @@ class WordScanRunner:
         self.fds = []
 
 
+def host_pread_rate(runner: "WordScanRunner", threads: int, reps: int = 3) -> float:
+    """GB/s at which `threads` host threads pread the runner's chunks into its
+    persistent staging with no GPU work (gsys_host_pread_rate): the host's
+    side of the file scan's roofline."""
+    import ctypes as C
+    tab = chunk_table(runner.fds, runner.sizes, runner.chunk_max)
+    fds = np.ascontiguousarray(tab["fd"], dtype=np.int32)
+    offs = np.ascontiguousarray(tab["off"], dtype=np.uint64)
+    lens = np.ascontiguousarray(tab["len"], dtype=np.uint32)
+    slot = staging_bytes(runner.chunk_max, 1)
+    out = C.c_double()
+    check(lib.gsys_host_pread_rate(fds.ctypes.data, offs.ctypes.data, lens.ctypes.data, len(tab),
+                                   runner.staging_p.host, slot, runner.persistent_bytes // slot,
+                                   threads, reps, C.byref(out)), "gsys_host_pread_rate")
+    return out.value
+
+
 def open_buffer_bytes(chunk: int) -> int:
     """Bytes of one of a work-group's two piece buffers in the open form."""
-    return (64 + chunk + 16384 + 48 + 15) // 16 * 16
+    return int(lib.gsys_wordcount_open_buffer_bytes(chunk))
 
 
 class WordOpenRunner:
