@@ -450,6 +450,12 @@ def run_sweep(args):
                                            "service_threads": len(os.sched_getaffinity(0)) - 1,
                                            "ms_per_step": round(1e3 * qt / len(qw), 3)}
             res["persistent_over_best_plain"] = round(value / max(pv, qv), 3)
+    # the host's side of the roofline: the same preads into the same staging
+    # on as many host threads as the pool has, without the GPU
+    hp = r.host_pread_rate(res["config"]["service_threads"])
+    res["roofline"]["host_pread_GBps"] = round(hp, 2)
+    res["roofline"]["host_pread_calls_per_s"] = round(hp * 1e9 / ITEM, 1)
+    res["roofline"]["frac_of_host_pread"] = round(achieved / hp, 4)
     if cpu:
         res["cpu_baseline"] = cpu
     r.close()

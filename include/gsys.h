@@ -397,13 +397,16 @@ int64_t gsys_kv_loadgen(uint32_t server_port, const uint8_t *reqs, uint32_t req_
 /*
  * Host read capacity (a measurement helper, no GPU involved): `threads` host
  * threads take the n ranges (fds[i], offs[i], lens[i]) in order from a shared
- * counter and pread range i into dst + (i mod n_slots) * slot_bytes, as the
- * service pool does for the word search's chunk reads (section 7.1); the best
+ * counter, in runs of up to 256 (at least 8 runs per thread), and pread
+ * range i into dst + (i mod n_slots) * slot_bytes, each
+ * through its own open file description of the file (a read-only re-open of
+ * the caller's fd), as the service pool does for GPU-issued preads (the
+ * sweep's items, the word search's chunks of section 7.1); the best
  * of `reps` passes, in returned bytes per nanosecond (GB/s), is stored in
  * *out_gbps.  dst must hold n_slots * slot_bytes bytes (caller-owned).
  * Returns 0, -EINVAL (a null pointer, n, n_slots, threads or reps of 0,
- * threads > 1024, or a range longer than slot_bytes) or the -errno of the
- * first failed pread.
+ * threads > 1024, or a range longer than slot_bytes), -EBADF (an fd that is
+ * not open) or the -errno of the first failed re-open or pread.
  */
 int gsys_host_pread_rate(const int *fds, const uint64_t *offs, const uint32_t *lens, uint64_t n,
                          uint8_t *dst, uint64_t slot_bytes, uint64_t n_slots, uint32_t threads,

@@ -2,13 +2,20 @@
 // ranges into memory with pread, with no GPU work at all.  The word search's
 // host side makes exactly these copies (section 7.1: the CPU services the
 // chunk reads whose bytes the GPU scans), so this rate bounds the file scan
-// beside the host link.
+// beside the host link.  Like the pool's pollers, each thread reads through
+// its own open file description of every file (a re-open of
+// /proc/self/fd/N), so the threads do not share a description's reference
+// count.
 #include <errno.h>
+#include <fcntl.h>
+#include <stdio.h>
 #include <time.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <atomic>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "gsys.h"
@@ -35,19 +42,50 @@ int gsys_host_pread_rate(const int* fds, const uint64_t* offs, const uint32_t* l
   for (uint32_t r = 0; r < reps; ++r) {
     std::atomic<uint64_t> next{0}, bytes{0};
     std::atomic<int> err{0};
+    auto fail = [&](int e) {
+      int z = 0;
+      err.compare_exchange_strong(z, e);
+    };
+    // ranges are claimed in runs (up to 256, as a work-group's list call
+    // carries), small enough that every thread gets several
+    const uint64_t run = std::max<uint64_t>(1, std::min<uint64_t>(256, n / (8ull * threads)));
     auto work = [&] {
+      std::unordered_map<int, int> own;  // caller's fd -> this thread's description
+      int last_fd = -1, last_own = -1;
       uint64_t mine = 0;
-      for (;;) {
-        const uint64_t i = next.fetch_add(1, std::memory_order_relaxed);
-        if (i >= n) break;
-        const ssize_t k = pread(fds[i], dst + (i % n_slots) * slot_bytes, lens[i], (off_t)offs[i]);
-        if (k < 0) {
-          int z = 0;
-          err.compare_exchange_strong(z, -errno);
-          break;
+      bool ok = true;
+      while (ok) {
+        const uint64_t i0 = next.fetch_add(run, std::memory_order_relaxed);
+        if (i0 >= n) break;
+        const uint64_t i1 = std::min(n, i0 + run);
+        for (uint64_t i = i0; i < i1; ++i) {
+          if (fds[i] != last_fd || last_own < 0) {
+            auto it = own.find(fds[i]);
+            if (it == own.end()) {
+              char path[32];
+              snprintf(path, sizeof path, "/proc/self/fd/%d", fds[i]);
+              const int fd = fds[i] < 0 ? -1 : open(path, O_RDONLY | O_CLOEXEC);
+              if (fd < 0) {
+                fail(fds[i] < 0 || errno == ENOENT ? -EBADF : -errno);
+                ok = false;
+                break;
+              }
+              it = own.emplace(fds[i], fd).first;
+            }
+            last_fd = fds[i];
+            last_own = it->second;
+          }
+          const ssize_t k = pread(last_own, dst + (i % n_slots) * slot_bytes, lens[i],
+                                  (off_t)offs[i]);
+          if (k < 0) {
+            fail(-errno);
+            ok = false;
+            break;
+          }
+          mine += (uint64_t)k;
         }
-        mine += (uint64_t)k;
       }
+      for (const auto& kv : own) close(kv.second);
       bytes.fetch_add(mine, std::memory_order_relaxed);
     };
     const uint64_t t0 = now_ns();

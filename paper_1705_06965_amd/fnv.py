@@ -54,6 +54,21 @@ class FnvRunner:
         r = self.out_ret.cpu().numpy()[:self.n].copy()
         return f, r
 
+    def host_pread_rate(self, threads: int, reps: int = 3) -> float:
+        """GB/s at which `threads` host threads make this runner's preads into
+        its staging with no GPU work (gsys_host_pread_rate): the host's side
+        of the sweep's roofline."""
+        import ctypes as C
+        offs = np.ascontiguousarray(self.offsets.cpu().numpy().view(np.uint64))
+        fds = np.full(self.n, self.fd, dtype=np.int32)
+        lens = np.full(self.n, self.item_bytes, dtype=np.uint32)
+        out = C.c_double()
+        check(lib.gsys_host_pread_rate(fds.ctypes.data, offs.ctypes.data, lens.ctypes.data,
+                                       self.n, self.staging.host, self.item_bytes,
+                                       self.staging_bytes // self.item_bytes, threads, reps,
+                                       C.byref(out)), "gsys_host_pread_rate")
+        return out.value
+
     def close(self):
         """Revoke and close the file, free the staging and list buffers."""
         self.ctx.allow_fd(self.fd, 0)

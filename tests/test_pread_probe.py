@@ -68,3 +68,18 @@ def test_refusals(datafile):
     assert probe([fd], [0], [4096], buf, 8192, 0)[0] == -errno.EINVAL
     assert probe([fd], [0], [4096], buf, 8192, 1, reps=0)[0] == -errno.EINVAL
     assert probe([-1], [0], [4096], buf, 8192, 1)[0] == -errno.EBADF
+
+
+def test_runs_of_ranges(datafile):
+    """Many short ranges (claimed 256 at a time) all land in their slots."""
+    fd, data = datafile
+    n = 4096
+    offs = (np.arange(n, dtype=np.uint64) * np.uint64(1531)) % np.uint64(6 * MIB)
+    lens = (np.arange(n, dtype=np.uint32) % 61) + 1
+    slot = 64
+    buf = np.zeros(slot * n, dtype=np.uint8)
+    rc, gbps = probe([fd] * n, offs, lens, buf, slot, n, threads=2)
+    assert rc == 0 and gbps > 0
+    for i in range(n):
+        o, k = int(offs[i]), int(lens[i])
+        assert bytes(buf[i * slot:i * slot + k]) == data[o:o + k], i
