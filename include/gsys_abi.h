@@ -137,6 +137,7 @@ typedef struct gsys_dev_ctx {
 #define GSYS_ETIMEDOUT_RET (-110)    /* -ETIMEDOUT */
 #define GSYS_ESHUTDOWN_RET (-108)    /* -ESHUTDOWN */
 #define GSYS_EOVERFLOW_RET (-75)     /* -EOVERFLOW: completion record was lapped */
+#define GSYS_EINVAL_RET (-22)        /* -EINVAL */
 #define GSYS_NOT_WAITED    (-115)    /* -EINPROGRESS: this lane did not wait */
 
 #endif /* GSYS_ABI_H */

@@ -620,11 +620,14 @@ __device__ inline int64_t gsys_call(const gsys_dev_ctx& c, uint16_t nr, uint64_t
   return gsys_call<g, o, b>(c, nr, Args6{{a0, a1, a2, a3, a4, a5}});
 }
 
-// A kernel-granularity call at call site `site` (< the context's n_ksites).
+// A kernel-granularity call at call site `site`; every work-item of the
+// launch passes the same site.  A site at or past the context's n_ksites
+// makes no call and returns -EINVAL (sites are never shared by accident).
 template <O o, B b>
 __device__ inline int64_t gsys_call_site(const gsys_dev_ctx& c, uint32_t site, uint16_t nr,
                                          const Args6& a, Ticket* tk = nullptr) {
   (void)Legal<G::Kernel, o>::ok;
+  if (site >= c.n_ksites) return GSYS_EINVAL_RET;
   return call_kernel<b>(c, kernel_site(c, site), nr, 0, [] {}, [&] { return a; }, tk);
 }
 

@@ -9,7 +9,11 @@
 //               other at off0 + i * item_bytes, in one call (relaxed,
 //               non-blocking, then gsys_wait);
 //   kernel:     one pread of all n items for the whole launch (relaxed,
-//               blocking).
+//               blocking);
+//   two sites:  two kernel-granularity preads, the first half of the items
+//               at call site 1 and the rest at call site 2 (each call of a
+//               launch needs its own site); a call at a site past the
+//               context's last one is refused with -EINVAL and makes none.
 // Every kernel loops over its items with the grid's stride, so a clamped
 // persistent grid covers them all.
 #include <gsys.h>
@@ -96,10 +100,29 @@ __global__ void by_kernel(Args A) {
   }
 }
 
+__global__ void by_kernel_sites(Args A) {
+  const uint64_t h = A.n / 2;
+  const gsys::Args6 none{{0, 0, 0, 0, 0, 0}};
+  const int64_t bad = gsys::gsys_call_site<O::Relaxed, B::Blocking>(A.c, A.c.n_ksites,
+                                                                     GSYS_NR_PREAD64, none);
+  const gsys::Args6 a1{{(uint64_t)(int64_t)A.fd, A.staging, h * A.item_bytes, A.off0, 0, 0}};
+  const int64_t r1 = gsys::gsys_call_site<O::Relaxed, B::Blocking>(A.c, 1, GSYS_NR_PREAD64, a1);
+  const gsys::Args6 a2{{(uint64_t)(int64_t)A.fd, A.staging + h * A.item_bytes,
+                        (A.n - h) * A.item_bytes, A.off0 + h * A.item_bytes, 0, 0}};
+  const int64_t r2 = gsys::gsys_call_site<O::Relaxed, B::Blocking>(A.c, 2, GSYS_NR_PREAD64, a2);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
+    const int64_t got = i < h ? share(r1, i, 0, A.item_bytes) : share(r2, i, h, A.item_bytes);
+    // a refusal that did not come back is reported as a wrong byte count
+    A.out_ret[i] = bad == GSYS_EINVAL_RET ? got : -1000;
+    A.out_fnv[i] = fnv(A.staging + i * A.item_bytes, got > 0 ? got : 0);
+  }
+}
+
 }  // namespace demo
 
-// gran: GSYS_GRAN_WI, GSYS_GRAN_WG or GSYS_GRAN_KERNEL; mode: a gsys_launch
-// mode.  The argument array lives on this function's stack, so every call
+// gran: GSYS_GRAN_WI, GSYS_GRAN_WG, GSYS_GRAN_KERNEL, or 3 for two
+// kernel-granularity calls at two call sites; mode: a gsys_launch mode.  The argument array lives on this function's stack, so every call
 // passes gsys_launch the same address with new values.
 extern "C" int gsys_demo_pread_fnv(gsys_ctx* ctx, uint32_t gran, uint32_t mode, uint32_t grid,
                                    uint32_t block, int fd, uint64_t staging, uint64_t offsets,
@@ -119,7 +142,8 @@ extern "C" int gsys_demo_pread_fnv(gsys_ctx* ctx, uint32_t gran, uint32_t mode, 
   A.item_bytes = item_bytes;
   const void* k = gran == GSYS_GRAN_WI ? (const void*)demo::by_work_item
                   : gran == GSYS_GRAN_WG ? (const void*)demo::by_work_group
-                  : gran == GSYS_GRAN_KERNEL ? (const void*)demo::by_kernel : nullptr;
+                  : gran == GSYS_GRAN_KERNEL ? (const void*)demo::by_kernel
+                  : gran == 3 ? (const void*)demo::by_kernel_sites : nullptr;
   if (!k || (gran == GSYS_GRAN_WI && !offsets)) return -EINVAL;
   void* args[] = {&A};
   gsys_launch_desc d;

@@ -1,7 +1,8 @@
 """The boundary as a user program sees it: paper_1705_06965_amd/demo/pread_fnv.hip,
 built against include/gsys.h and include/gsys_device.hpp only, preads items
 of a file with gsys::pread at work-item, work-group (non-blocking, then
-gsys_wait) and kernel granularity (section 4.1) and hashes them; it is
+gsys_wait) and kernel granularity (section 4.1; also two kernel calls at
+two call sites, and a refused call at a site past the last) and hashes them; it is
 started through gsys_launch in the plain, persistent and graph modes.
 Every launch's per-item FNV-1a-64 and byte counts equal the oracle's, also
 when one argument array is reused with new buffers, offsets and item counts
@@ -64,7 +65,8 @@ def launch(env, gran, mode, n, seed):
     out_fnv = torch.zeros(n, dtype=torch.int64, device="cuda")
     out_ret = torch.full((n,), -999, dtype=torch.int64, device="cuda")
     block = 256
-    grid = {g.PLAIN: (n + block - 1) // block if gran != g.GRAN_KERNEL else 16}.get(mode, 100000)
+    grid = {g.PLAIN: (n + block - 1) // block if gran not in (g.GRAN_KERNEL, GRAN_SITES)
+            else 16}.get(mode, 100000)
     rc = demo.gsys_demo_pread_fnv(ctx.h, gran, mode, grid, block, fd, staging.dev,
                                   offs_d.data_ptr(), off0, n, ITEM, out_fnv.data_ptr(),
                                   out_ret.data_ptr(), None)
@@ -81,14 +83,15 @@ def check(env, got_fnv, got_ret, offs, label):
     assert (got_fnv == want_fnv).all(), label
 
 
-GRANS = ["WI", "WG", "K"]
+GRANS = ["WI", "WG", "K", "K2"]
+GRAN_SITES = 3       # the demo's two kernel-granularity calls at call sites 1 and 2
 
 
 @pytest.mark.parametrize("gname", GRANS)
 @pytest.mark.parametrize("mname", ["PLAIN", "PERSISTENT", "GRAPH"])
 def test_user_kernel_matches_oracle(env, gname, mname):
     g = env[0]
-    gran = {"WI": g.GRAN_WI, "WG": g.GRAN_WG, "K": g.GRAN_KERNEL}[gname]
+    gran = {"WI": g.GRAN_WI, "WG": g.GRAN_WG, "K": g.GRAN_KERNEL, "K2": GRAN_SITES}[gname]
     mode = getattr(g, mname)
     # new offsets, outputs and item counts on every launch through the same
     # argument array; a ragged last work-group in each
@@ -107,5 +110,5 @@ def test_launch_refusals(env):
     import errno
     d = g.gsys_launch_desc()
     assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL           # no kernel
-    assert demo.gsys_demo_pread_fnv(ctx.h, 9, g.PLAIN, 1, 64, 0, 0, 0, 0, 1, ITEM, 1, 1,
+    assert demo.gsys_demo_pread_fnv(ctx.h, 4, g.PLAIN, 1, 64, 0, 0, 0, 0, 1, ITEM, 1, 1,
                                     None) == -errno.EINVAL                       # bad granularity
