@@ -623,7 +623,7 @@ def _kv_run(args, kv, reqs, clients, sub):
                     device_timeout_ns=60_000_000_000,
                     flags=g.CFG_DOORBELL if args.kv_doorbell else 0)
     srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=tk_["grid"],
-                   batch=tk_["batch"])
+                   batch=tk_["batch"], pipelined=bool(tk_.get("pipelined", 1)))
     # beside the sweep: one warm-up pass and two timed passes of the 4M GETs
     warmup = 1 if sub else args.warmup
     steps = 2 if sub else max(1, min(args.steps, 3))
@@ -691,6 +691,7 @@ def _kv_run(args, kv, reqs, clients, sub):
                                "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, 256-datagram "
                                "recvfrom/sendto list calls per work-group",
                    "server_workgroups": tk_["grid"], "batch": tk_["batch"],
+                   "server_loop": "pipelined" if tk_.get("pipelined", 1) else "blocking",
                    "tuned": tk_, "client_threads": clients,
                    "service_threads": pollers,
                    "client_window": args.kv_window, "doorbell": bool(args.kv_doorbell)},

@@ -363,7 +363,11 @@ int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
  * (16 + len B): u64 id; u8 status (0 hit, 1 miss, 2 bad request); u8 pad;
  * u16 len; u32 pad; value[len]; sent to the request's source address.
  * Each work-group receives up to `batch` (<= 256) datagrams per recvfrom
- * list call.  io: registered GSYS_BUF_HOST region of io_bytes, at least
+ * list call.  flags: 0 = pipelined loop (the receive of a work-group's next
+ * batch is in flight while it answers the current one; sends are
+ * non-blocking over two sets of buffers), GSYS_KV_BLOCKING = one blocking
+ * receive, then one blocking send, per batch.  io: registered GSYS_BUF_HOST
+ * region of io_bytes, at least
  * gsys_kv_io_bytes() per work-group (the grid shrinks to fit; grid 0 =
  * as many as fit and are resident).  stop: registered host word; the server
  * exits when it reads nonzero, or after lifetime_ms (0 = 60 s).  served:
@@ -374,9 +378,10 @@ int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
 int gsys_kv_build(gsys_ctx *ctx, uint64_t table, uint64_t cap, uint64_t keys, uint64_t voff,
                   uint64_t vlen, uint64_t n, void *stream);
 uint64_t gsys_kv_io_bytes(void);
+#define GSYS_KV_BLOCKING 1u
 int gsys_kv_serve(gsys_ctx *ctx, int fd, uint64_t table, uint64_t cap, uint64_t heap, uint64_t io,
                   uint64_t io_bytes, uint64_t stop, uint64_t served, uint32_t batch, uint32_t grid,
-                  uint64_t lifetime_ms, void *stream);
+                  uint32_t flags, uint64_t lifetime_ms, void *stream);
 
 /*
  * UDP load generator for the key-value server (the CPU load generator of

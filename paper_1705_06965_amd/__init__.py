@@ -32,6 +32,7 @@ GRAN_WI, GRAN_WG, GRAN_KERNEL = 0, 1, 2
 CELL_STRONG, CELL_BLOCKING = 0x4, 0x8
 PLAIN, PERSISTENT, GRAPH = 0, 1, 2
 CFG_LEDGER, CFG_NO_DEVICE, CFG_NO_PIN, CFG_SHARED_FDS, CFG_DOORBELL = 0x1, 0x2, 0x4, 0x8, 0x10
+KV_BLOCKING = 0x1  # gsys_kv_serve: blocking receive-then-send loop
 FD_READ, FD_WRITE, FD_SOCK, FD_DIR = 0x1, 0x2, 0x4, 0x8
 BUF_HOST, BUF_DEVICE = 1, 2
 NOT_WAITED = -115   # a non-blocking call's result slot before anyone waited
@@ -130,7 +131,7 @@ _SIGS = {
     "gsys_kv_io_bytes": (C.c_uint64, []),
     "gsys_kv_serve": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                                 C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
-                                C.c_uint64, _P]),
+                                C.c_uint32, C.c_uint64, _P]),
     "gsys_kv_loadgen": (C.c_int64, [C.c_uint32, _P, C.c_uint32, C.c_uint64, C.c_uint32,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _P, C.c_uint32, _P, _P,
                                     _P]),

@@ -36,17 +36,17 @@ DEFAULTS_BY = {
     "sweep": DEFAULTS,
     "wordscan": {"service_threads": 12, "buffers": 128, "sleep_max": 64},
     "serve": {"grid": 64, "sleep_max": 64, "service_threads": 0},
-    "kv": {"grid": 16, "batch": 256, "service_threads": 12},
-    "kv8": {"grid": 16, "batch": 256, "service_threads": 8},
+    "kv": {"grid": 16, "batch": 256, "service_threads": 12, "pipelined": 1},
+    "kv8": {"grid": 16, "batch": 256, "service_threads": 8, "pipelined": 1},
 }
 SPACE_BY = {
     "wordscan": [("service_threads", [8, 10, 12, 14, 15]), ("buffers", [96, 128, 160, 256]),
                  ("sleep_max", [16, 64, 256])],
     "serve": [("grid", [32, 48, 64, 96]), ("sleep_max", [16, 64, 256]),
               ("service_threads", [12, 14, 15])],
-    "kv": [("grid", [8, 16, 32]), ("batch", [64, 128, 256]),
+    "kv": [("pipelined", [0, 1]), ("grid", [8, 16, 32]), ("batch", [64, 128, 256]),
            ("service_threads", [8, 10, 12])],
-    "kv8": [("grid", [4, 8, 16, 32]), ("service_threads", [6, 7, 8]),
+    "kv8": [("pipelined", [0, 1]), ("grid", [4, 8, 16, 32]), ("service_threads", [6, 7, 8]),
             ("batch", [128, 256])],
 }
 
@@ -200,7 +200,7 @@ def measure_kv(params: dict, kv, reqs, clients: int = 4) -> float:
     srv = None
     try:
         srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=params["grid"],
-                       batch=params["batch"])
+                       batch=params["batch"], pipelined=bool(params.get("pipelined", 1)))
         best = 0.0
         for _ in range(2):
             srv.start(lifetime_ms=120_000)

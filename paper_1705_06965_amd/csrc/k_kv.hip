@@ -13,12 +13,17 @@
 // hash = FNV-1a-64 of the key, linear probing; 32-byte buckets.  Values live
 // in an HBM heap, each 16-byte aligned.
 //
-// Server loop of one work-group: a recvfrom list call of 256 datagrams
-// (relaxed consumer, blocking: the group waits for it), lookups by every lane
-// that got a datagram, replies copied by whole wavefronts into pinned host
-// staging (one reply per step, 64 lanes x 16 B, coalesced), then a sendto
-// list call (relaxed producer, blocking: the barrier comes before it and only
-// the caller's wavefront waits).
+// Server loop of one work-group: a recvfrom list call of up to 256
+// datagrams (relaxed consumer), lookups by every lane that got a datagram,
+// replies copied by whole wavefronts into pinned host staging (one reply per
+// step, 64 lanes x 16 B, coalesced), then a sendto list call (relaxed
+// producer: the barrier comes before it).  Two forms of the loop:
+//   pipelined (default): two sets of lists and buffers; the receive of the
+//     next batch is in flight while this one is answered, and sends are
+//     non-blocking, waited for only before their set is reused, so the host
+//     pool always holds a call of every work-group;
+//   blocking (GSYS_KV_BLOCKING): one set; each receive and send is a
+//     blocking call (only the caller's wavefront waits for a send).
 #include "gsys_device.hpp"
 #include "gsys.h"
 #include "kernels.hpp"
@@ -41,13 +46,15 @@ struct Bucket {
 };
 static_assert(sizeof(Bucket) == 32, "bucket is 32 bytes");
 
-// Per-work-group I/O region in pinned host memory.
+// Per-work-group I/O region in pinned host memory: two sets of lists and
+// buffers (the blocking loop uses the first).
 constexpr uint32_t kOffRecvList = 0;
 static_assert(sizeof(gsys_netdesc) == 32, "descriptors are written as two 16-byte vectors");
 constexpr uint32_t kOffSendList = kOffRecvList + kWG * sizeof(gsys_netdesc);
 constexpr uint32_t kOffRecv = kOffSendList + kWG * sizeof(gsys_netdesc);
 constexpr uint32_t kOffSend = kOffRecv + kWG * kReqBuf;
-constexpr uint32_t kIoBytes = kOffSend + kWG * kRepBuf;
+constexpr uint32_t kSetBytes = kOffSend + kWG * kRepBuf;
+constexpr uint32_t kIoBytes = 2 * kSetBytes;
 
 __device__ __forceinline__ uint64_t fnv16(uint64_t k0, uint64_t k1) {
   uint64_t h = 0xcbf29ce484222325ull;
@@ -102,114 +109,202 @@ struct KvArgs {
   uint32_t batch;                  // datagrams per recvfrom list (<= 256)
 };
 
-__global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
-  __shared__ int s_stop;
-  uint8_t* io = reinterpret_cast<uint8_t*>(A.io) + (uint64_t)blockIdx.x * kIoBytes;
-  gsys_netdesc* rl = reinterpret_cast<gsys_netdesc*>(io + kOffRecvList);
-  gsys_netdesc* sl = reinterpret_cast<gsys_netdesc*>(io + kOffSendList);
-  uint8_t* rbuf = io + kOffRecv;
-  uint8_t* sbuf = io + kOffSend;
-  const uint64_t rbase = A.io + (uint64_t)blockIdx.x * kIoBytes + kOffRecv;
-  const uint64_t sbase = A.io + (uint64_t)blockIdx.x * kIoBytes + kOffSend;
-  const uint32_t lane = lane_id();
+// One set of a work-group's lists and buffers.
+struct IoSet {
+  gsys_netdesc* rl;   // receive list
+  gsys_netdesc* sl;   // send list
+  uint8_t* rbuf;      // received datagrams, kReqBuf each
+  uint8_t* sbuf;      // replies, kRepBuf each
+  uint64_t rbase, sbase;
+};
+
+__device__ __forceinline__ IoSet io_set(const KvArgs& A, uint32_t k) {
+  const uint64_t base = A.io + (uint64_t)blockIdx.x * kIoBytes + (uint64_t)k * kSetBytes;
+  uint8_t* io = reinterpret_cast<uint8_t*>(base);
+  return IoSet{reinterpret_cast<gsys_netdesc*>(io + kOffRecvList),
+               reinterpret_cast<gsys_netdesc*>(io + kOffSendList), io + kOffRecv, io + kOffSend,
+               base + kOffRecv, base + kOffSend};
+}
+
+// The receive list of a set: batch empty datagram slots.  Written by the
+// caller's wavefront only (a relaxed consumer call has no barrier before it);
+// every work-item calls this.
+template <B b>
+__device__ __forceinline__ void post_recv(const KvArgs& A, const IoSet& S, Ticket* tk) {
   const uint32_t tid = threadIdx.x;
+  if (tid < 64)
+    for (uint32_t i = tid; i < A.batch; i += 64) {
+      // {buf_off, len_ret, addr_len, pad}, then an empty address
+      stg16((uint64_t)(S.rl + i), u32x4{i * kReqBuf, kReqBuf, 0u, 0u});
+      stg16((uint64_t)(S.rl + i) + 16, u32x4{0u, 0u, 0u, 0u});
+    }
+  Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)S.rl, A.batch, S.rbase, 0, 0}};
+  call_wg<O::Relaxed, b>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra, tk);
+}
+
+// This work-item's datagram of a completed receive list, if it got one
+// (datagrams arrive as a prefix of the list: the host stops at -EAGAIN).
+__device__ __forceinline__ int32_t received(const KvArgs& A, const IoSet& S) {
+  const uint32_t tid = threadIdx.x;
+  return tid < A.batch ? __hip_atomic_load(gp(&S.rl[tid].len_ret), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM)
+                       : -1;
+}
+
+// Look up every received request and write its reply and send descriptor
+// into the set.  Every work-item calls this.
+__device__ void answer(const KvArgs& A, const IoSet& S, int32_t got) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const bool have = got >= 0;
+  uint64_t id = 0, voff = 0;
+  uint32_t status = 2, vlen = 0;
+  if (have) {
+    const uint8_t* q = S.rbuf + tid * kReqBuf;
+    const u32x4 w0 = ldg16((uint64_t)q);
+    const u32x4 w1 = ldg16((uint64_t)(q + 16));
+    if (got >= 8) id = ((uint64_t)w0.y << 32) | w0.x;
+    if (got == 32 && (w0.z & 0xffu) == 1u) {
+      const uint64_t k0 = ((uint64_t)w1.y << 32) | w1.x;
+      const uint64_t k1 = ((uint64_t)w1.w << 32) | w1.z;
+      uint64_t b = __umul64hi(fnv16(k0, k1), A.cap);
+      status = 1;
+      for (uint64_t p = 0; p < A.cap; ++p) {
+        const gptr_t<const Bucket> bk = gp<const Bucket>((uint64_t)(A.tab + b));
+        if (!bk->used) break;
+        if (bk->k0 == k0 && bk->k1 == k1) {
+          status = 0;
+          voff = bk->voff;
+          vlen = bk->vlen;
+          break;
+        }
+        b = b + 1 == A.cap ? 0 : b + 1;
+      }
+    }
+    // reply descriptor {buf_off, len_ret, addr_len, pad, addr}: back to
+    // the sender recvfrom reported
+    const u32x4 rh = ldg16((uint64_t)(S.rl + tid));
+    const u32x4 ra = ldg16((uint64_t)(S.rl + tid) + 16);
+    stg16((uint64_t)(S.sl + tid), u32x4{tid * kRepBuf, 16u + vlen, rh.z, 0u});
+    stg16((uint64_t)(S.sl + tid) + 16, ra);
+  }
+  // replies: one wavefront copies one reply per step, 16 B per lane
+  uint64_t m = __ballot(have);
+  while (m) {
+    const uint32_t j = first_lane(m);
+    m &= m - 1;
+    const uint64_t jid = bcast64(id, j);
+    const uint64_t jvoff = bcast64(voff, j);
+    const uint32_t jst = __builtin_amdgcn_readlane(status, j);
+    const uint32_t jlen = __builtin_amdgcn_readlane(vlen, j);
+    uint8_t* dst = S.sbuf + (uint64_t)((tid & ~63u) + j) * kRepBuf;
+    const uint32_t chunks = 1 + (jlen + 15) / 16;
+    for (uint32_t c = lane; c < chunks; c += 64) {
+      u32x4 v;
+      if (c == 0) {
+        v = u32x4{(uint32_t)jid, (uint32_t)(jid >> 32), jst | (jlen << 16), 0u};
+      } else {
+        v = ldg16((uint64_t)(A.heap + jvoff + 16 * (c - 1)));
+      }
+      stg16((uint64_t)(dst + 16 * c), v);
+    }
+  }
+}
+
+// Back off before asking an empty socket again (thread 0 sleeps; the
+// barrier ends its region before the loop's back edge, where the next
+// iteration opens with another thread-0 region: two such regions joined
+// across a back edge can leave thread 0 out of the following barrier).
+__device__ __forceinline__ void idle_backoff(uint32_t idle) {
+  if (threadIdx.x == 0) {
+    const uint32_t reps = 1u << min(idle, 8u);
+    for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(8);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool stop_now(const KvArgs& A, uint64_t t_end) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = ld_sys(A.stop) != 0 || wall_clock64() > t_end;
+  __syncthreads();
+  const bool r = s_stop != 0;
+  __syncthreads();  // s_stop is written again by the next check
+  return r;
+}
+
+__global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
+  const uint32_t tid = threadIdx.x;
+  const IoSet S = io_set(A, 0);
   uint32_t idle = 0;
   const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
   for (;;) {
-    if (tid == 0) s_stop = ld_sys(A.stop) != 0 || wall_clock64() > t_end;
-    __syncthreads();
-    if (s_stop) break;
-    // receive list: the caller's wavefront writes it (consumer call: no
-    // barrier before it)
-    if (tid < 64)
-      for (uint32_t i = tid; i < A.batch; i += 64) {
-        // {buf_off, len_ret, addr_len, pad}, then an empty address
-        stg16((uint64_t)(rl + i), u32x4{i * kReqBuf, kReqBuf, 0u, 0u});
-        stg16((uint64_t)(rl + i) + 16, u32x4{0u, 0u, 0u, 0u});
-      }
-    Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)rl, A.batch, rbase, 0, 0}};
-    call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra);
-    // datagrams arrive as a prefix of the list (the host stops at -EAGAIN)
-    int32_t got = tid < A.batch ? __hip_atomic_load(gp(&rl[tid].len_ret), __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_SYSTEM)
-                                : -1;
-    const bool have = got >= 0;
-    const uint32_t n = (uint32_t)__syncthreads_count(have);
+    if (stop_now(A, t_end)) break;
+    post_recv<B::Blocking>(A, S, nullptr);
+    const int32_t got = received(A, S);
+    const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
     if (n == 0) {
-      // empty socket: back off before asking again.  The barrier ends the
-      // thread-0 region before the loop's back edge, where the next
-      // iteration opens with another one (two such regions joined across a
-      // back edge can leave thread 0 out of the following barrier).
-      if (tid == 0) {
-        const uint32_t reps = 1u << min(idle, 8u);
-        for (uint32_t r = 0; r < reps; ++r) __builtin_amdgcn_s_sleep(8);
-      }
-      ++idle;
-      __syncthreads();
+      idle_backoff(idle++);
       continue;
     }
     idle = 0;
-    // parse and look up
-    uint64_t id = 0, voff = 0;
-    uint32_t status = 2, vlen = 0;
-    if (have) {
-      const uint8_t* q = rbuf + tid * kReqBuf;
-      const u32x4 w0 = ldg16((uint64_t)q);
-      const u32x4 w1 = ldg16((uint64_t)(q + 16));
-      if (got >= 8) id = ((uint64_t)w0.y << 32) | w0.x;
-      if (got == 32 && (w0.z & 0xffu) == 1u) {
-        const uint64_t k0 = ((uint64_t)w1.y << 32) | w1.x;
-        const uint64_t k1 = ((uint64_t)w1.w << 32) | w1.z;
-        uint64_t b = __umul64hi(fnv16(k0, k1), A.cap);
-        status = 1;
-        for (uint64_t p = 0; p < A.cap; ++p) {
-          const gptr_t<const Bucket> bk = gp<const Bucket>((uint64_t)(A.tab + b));
-          if (!bk->used) break;
-          if (bk->k0 == k0 && bk->k1 == k1) {
-            status = 0;
-            voff = bk->voff;
-            vlen = bk->vlen;
-            break;
-          }
-          b = b + 1 == A.cap ? 0 : b + 1;
-        }
-      }
-      // reply descriptor {buf_off, len_ret, addr_len, pad, addr}: back to
-      // the sender recvfrom reported
-      const u32x4 rh = ldg16((uint64_t)(rl + tid));
-      const u32x4 ra = ldg16((uint64_t)(rl + tid) + 16);
-      stg16((uint64_t)(sl + tid), u32x4{tid * kRepBuf, 16u + vlen, rh.z, 0u});
-      stg16((uint64_t)(sl + tid) + 16, ra);
-    }
-    // replies: one wavefront copies one reply per step, 16 B per lane
-    uint64_t m = __ballot(have);
-    while (m) {
-      const uint32_t j = first_lane(m);
-      m &= m - 1;
-      const uint64_t jid = bcast64(id, j);
-      const uint64_t jvoff = bcast64(voff, j);
-      const uint32_t jst = __builtin_amdgcn_readlane(status, j);
-      const uint32_t jlen = __builtin_amdgcn_readlane(vlen, j);
-      uint8_t* dst = sbuf + (uint64_t)((tid & ~63u) + j) * kRepBuf;
-      const uint32_t chunks = 1 + (jlen + 15) / 16;
-      for (uint32_t c = lane; c < chunks; c += 64) {
-        u32x4 v;
-        if (c == 0) {
-          v = u32x4{(uint32_t)jid, (uint32_t)(jid >> 32), jst | (jlen << 16), 0u};
-        } else {
-          v = ldg16((uint64_t)(A.heap + jvoff + 16 * (c - 1)));
-        }
-        stg16((uint64_t)(dst + 16 * c), v);
-      }
-    }
+    answer(A, S, got);
     // send the replies (producer call: every lane's reply is released before)
-    Args6 sa{{(uint64_t)(int64_t)A.fd, (uint64_t)sl, n, sbase, 0, 0}};
+    Args6 sa{{(uint64_t)(int64_t)A.fd, (uint64_t)S.sl, n, S.sbase, 0, 0}};
     call_wg<O::Relaxed, B::Blocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa);
     if (tid == 0) atomicAdd(A.served, (unsigned long long)n);
     // the caller's wavefront waited for the sends; the rest wait here before
     // the buffers are reused
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kWG) void kv_serve_pipelined(KvArgs A) {
+  const uint32_t tid = threadIdx.x;
+  const IoSet S0 = io_set(A, 0), S1 = io_set(A, 1);
+  // tickets are meaningful on thread 0; send_busy is uniform
+  Ticket r0{0, 0, 0}, r1{0, 0, 0}, s0{0, 0, 0}, s1{0, 0, 0};
+  bool send_busy0 = false, send_busy1 = false;
+  uint32_t idle = 0, k = 0;
+  const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
+  post_recv<B::NonBlocking>(A, S0, &r0);
+  for (;;) {
+    if (stop_now(A, t_end)) break;
+    const IoSet& S = k ? S1 : S0;
+    // the next batch's receive goes out before this one is answered (its
+    // set was answered in the previous step)
+    if (k) post_recv<B::NonBlocking>(A, S0, &r0);
+    else post_recv<B::NonBlocking>(A, S1, &r1);
+    wait_wg(A.c, k ? r1 : r0);
+    const int32_t got = received(A, S);
+    const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
+    if (n == 0) {
+      idle_backoff(idle++);
+      k ^= 1u;
+      continue;
+    }
+    idle = 0;
+    // the set's previous send must be done before its list and replies are
+    // rewritten
+    if (k ? send_busy1 : send_busy0) wait_wg(A.c, k ? s1 : s0);
+    answer(A, S, got);
+    Args6 sa{{(uint64_t)(int64_t)A.fd, (uint64_t)S.sl, n, S.sbase, 0, 0}};
+    if (k) {
+      call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa, &s1);
+      send_busy1 = true;
+    } else {
+      call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa, &s0);
+      send_busy0 = true;
+    }
+    if (tid == 0) atomicAdd(A.served, (unsigned long long)n);
+    __syncthreads();  // closes the thread-0 region before the back edge
+    k ^= 1u;
+  }
+  // the receive in flight and the sends not yet waited for finish before
+  // the work-group leaves (stop is raised once every request is answered,
+  // so the receive finds an empty socket)
+  wait_wg(A.c, k ? r1 : r0);
+  if (send_busy0) wait_wg(A.c, s0);
+  if (send_busy1) wait_wg(A.c, s1);
 }
 
 }  // namespace gsys_kv
@@ -233,13 +328,16 @@ uint64_t gsys_kv_io_bytes(void) { return kIoBytes; }
 
 int gsys_kv_serve(gsys_ctx* ctx, int fd, uint64_t table, uint64_t cap, uint64_t heap, uint64_t io,
                   uint64_t io_bytes, uint64_t stop, uint64_t served, uint32_t batch, uint32_t grid,
-                  uint64_t lifetime_ms, void* stream) {
+                  uint32_t flags, uint64_t lifetime_ms, void* stream) {
   if (!ctx || !table || !cap || !heap || !stop || !served) return -EINVAL;
   if (batch == 0 || batch > kWG) return -EINVAL;
   if (gsys_internal::check_host_range(ctx, io, io_bytes)) return -EFAULT;
   if (gsys_internal::check_host_range(ctx, stop, 8)) return -EFAULT;
   uint32_t fit = (uint32_t)std::min<uint64_t>(io_bytes / kIoBytes, 0x7fffffffull);
-  uint32_t res = gsys_internal::resident_grid(ctx, (const void*)kv_serve, kWG, 0);
+  if (flags & ~GSYS_KV_BLOCKING) return -EINVAL;
+  const void* kernel = (flags & GSYS_KV_BLOCKING) ? (const void*)kv_serve
+                                                  : (const void*)kv_serve_pipelined;
+  uint32_t res = gsys_internal::resident_grid(ctx, kernel, kWG, 0);
   if (!res) return -ENODEV;
   if (!grid || grid > fit) grid = fit;
   if (grid > res) grid = res;
@@ -256,5 +354,6 @@ int gsys_kv_serve(gsys_ctx* ctx, int fd, uint64_t table, uint64_t cap, uint64_t 
   A.batch = batch;
   A.lifetime_ticks = gsys_internal::ticks_per_ms(ctx) * (lifetime_ms ? lifetime_ms : 60000);
   void* args[] = {&A};
-  return gsys_internal::launch(ctx, (const void*)kv_serve, grid, kWG, 0, args, (hipStream_t)stream);
+  const void* k = kernel;
+  return gsys_internal::launch(ctx, k, grid, kWG, 0, args, (hipStream_t)stream);
 }

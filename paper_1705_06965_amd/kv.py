@@ -8,7 +8,7 @@ import socket
 
 import numpy as np
 
-from . import FD_SOCK, check, lib, _stream
+from . import FD_SOCK, KV_BLOCKING, check, lib, _stream
 
 REQ_LEN = 32
 REPLY_STRIDE = 1040
@@ -43,7 +43,8 @@ def padded_heap(val_off: np.ndarray, val_len: np.ndarray, heap: np.ndarray):
 
 class KVServer:
     def __init__(self, ctx, keys, val_off, val_len, heap, cap: int | None = None,
-                 grid: int = 16, batch: int = 256, device: str = "cuda"):
+                 grid: int = 16, batch: int = 256, device: str = "cuda",
+                 pipelined: bool = True):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -67,6 +68,7 @@ class KVServer:
         ctx.allow_fd(self.sock.fileno(), FD_SOCK)
         self.grid = grid
         self.batch = batch
+        self.flags = 0 if pipelined else KV_BLOCKING
         self.io_bytes = int(lib.gsys_kv_io_bytes()) * grid
         self.io = ctx.host_alloc(self.io_bytes)
         self.ctl = ctx.host_alloc(64)
@@ -77,7 +79,8 @@ class KVServer:
         self.ctl.view(np.uint64)[0] = 0
         check(lib.gsys_kv_serve(self.ctx.h, self.sock.fileno(), self.table.data_ptr(), self.cap,
                                 self.heap.data_ptr(), self.io.dev, self.io_bytes, self.ctl.dev,
-                                self.served.data_ptr(), self.batch, self.grid, lifetime_ms,
+                                self.served.data_ptr(), self.batch, self.grid, self.flags,
+                                lifetime_ms,
                                 _stream(stream)), "gsys_kv_serve")
         self.running = True
 

@@ -28,16 +28,21 @@ def gs():
     assert ctx.shutdown() == 0
 
 
+@pytest.mark.parametrize("loop", ["pipelined", "blocking"])
 @pytest.mark.parametrize("grid,batch", [(1, 256), (8, 64), (32, 256)])
-def test_kv_replies_match_oracle(gs, grid, batch):
+def test_kv_replies_match_oracle(gs, grid, batch, loop):
+    """Both server loops: the pipelined one (receive of the next batch in
+    flight, non-blocking sends over two sets of buffers) and the blocking one
+    (GSYS_KV_BLOCKING)."""
     g, ctx = gs
     from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
     kv = synth.kv_set(n_keys=20000, n_req=40000, miss_every=16)
     ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
-    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=grid, batch=batch)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=grid, batch=batch,
+                   pipelined=loop == "pipelined")
     reqs = make_requests(kv.req_keys)
     reqs[7, 8] = 9                      # bad op -> status 2
-    say("kv grid", grid, "batch", batch)
+    say("kv grid", grid, "batch", batch, loop)
     srv.start(lifetime_ms=60_000)
     try:
         got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=4, window=64)
