@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--kv-doorbell", action="store_true",
                     help="kv: idle pollers block on the GPU's interrupt doorbell")
     ap.add_argument("--serve-jobs", type=int, default=55000, help="serve: jobs in the stream")
+    ap.add_argument("--ws-passes", type=int, default=50,
+                    help="wordscan: passes over the corpus per persistent launch")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="serve: arrivals per second")
     ap.add_argument("--serve-inflight", type=int, default=512, help="serve: admission limit")
     ap.add_argument("--serve-ledger", action="store_true",
@@ -490,9 +492,9 @@ def run_wordscan(args, sub=False):
                        persistent_buffers=tw_["buffers"])
     stream = torch.cuda.current_stream()
 
-    def timed(form, steps, warmup):
+    def timed(form, steps, warmup, passes=1):
         for _ in range(warmup):
-            r.launch(form, stream)
+            r.launch(form, stream, passes)
             torch.cuda.synchronize()
             ctx.wait(60_000_000_000)
         ctx.stats(reset=True)
@@ -504,7 +506,7 @@ def run_wordscan(args, sub=False):
         for i in range(steps):
             s0 = time.perf_counter()
             evs[i][0].record(stream)
-            r.launch(form, stream)
+            r.launch(form, stream, passes)
             evs[i][1].record(stream)
             torch.cuda.synchronize()
             if ctx.wait(60_000_000_000):
@@ -513,8 +515,14 @@ def run_wordscan(args, sub=False):
         total = time.perf_counter() - t0
         return total, wall, [a.elapsed_time(b) for a, b in evs], ctx.stats()
 
-    tp = timed(g.PERSISTENT, args.steps, args.warmup)
+    # the persistent form scans the corpus `passes` times per launch (work-groups
+    # go from pass to pass without draining); single-pass launches beside it
+    passes = max(1, args.ws_passes)
+    single = timed(g.PERSISTENT, args.steps, args.warmup)
     counts = r.result()
+    tp = timed(g.PERSISTENT, max(3, args.steps // 4), 1, passes)
+    if not (r.result() == counts * passes).all():
+        raise RuntimeError("multi-pass counts are not passes x the single-pass counts")
     tw = None
     if not args.no_plain:
         tw = timed(g.PLAIN, max(3, args.steps // 2), 1)
@@ -534,7 +542,7 @@ def run_wordscan(args, sub=False):
                                            "(files split over %d POSIX threads)" % threads}
     total, wall, kern_ms, st = tp
     steps = len(wall)
-    gbps = c.total_bytes * steps / total / 1e9
+    gbps = c.total_bytes * passes * steps / total / 1e9
     kavg = float(np.mean(kern_ms))
     link_bytes = st["bytes_in"] / steps        # bytes the host delivered per pass
     achieved = link_bytes / (kavg * 1e-3) / 1e9
@@ -547,6 +555,7 @@ def run_wordscan(args, sub=False):
         "config": {"workload": "word search: 2,000 files, log-normal sizes (median 64 KiB, "
                                "sigma 1, cap 8 MiB), Zipf(1.1) words from a 50k vocabulary, "
                                "64 queries, 1 MiB chunk preads", "form": "persistent",
+                   "passes_per_launch": passes,
                    "files": len(c.paths), "bytes": c.total_bytes, "chunks": r.n_chunks,
                    "service_threads": int(ctx.cfg.service_threads) or
                    max(1, len(os.sched_getaffinity(0)) - 1),
@@ -566,6 +575,13 @@ def run_wordscan(args, sub=False):
     hp = round(host_pread_rate(r, res["config"]["service_threads"]), 2)
     res["roofline"]["host_pread_GBps"] = hp
     res["roofline"]["frac_of_host_pread"] = round(achieved / hp, 4)
+    ot, ow, ok_, ost = single
+    ok_avg = float(np.mean(ok_))
+    res["single_pass"] = {"value": round(c.total_bytes * len(ow) / ot / 1e9, 3), "unit": "GB/s",
+                          "ms_per_step": round(1e3 * ot / len(ow), 3),
+                          "kernel_ms": round(ok_avg, 3),
+                          "link_frac": round(ost["bytes_in"] / len(ow) / (ok_avg * 1e-3) / 1e9
+                                             / LINK_PEAK_GBPS, 4)}
     if tw:
         pt, pw, pk, _ = tw
         res["plain_form"] = {"value": round(c.total_bytes * len(pw) / pt / 1e9, 3), "unit": "GB/s",

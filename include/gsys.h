@@ -341,11 +341,16 @@ typedef struct gsys_chunk {
  *             counter and prefetch the next chunk with a non-blocking call;
  *             GSYS_GRAPH runs the zeroing of counts and counter and the scan
  *             as one hipGraph per shape, replayed with this call's arguments
+ *   passes    times the persistent forms read and scan every chunk within
+ *             the one launch (work-groups go from one pass to the next
+ *             without draining); counts add up, so each is passes times the
+ *             file's.  The plain form takes 1 only; n_chunks * passes < 2^32.
  * Errors: -EINVAL (shapes), -EFAULT (staging not registered), -ENODEV.
  */
 int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t chunk_max,
                   uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts, uint32_t nfiles,
-                  uint64_t staging, uint64_t staging_bytes, uint32_t form, void *stream);
+                  uint64_t staging, uint64_t staging_bytes, uint32_t form, uint32_t passes,
+                  void *stream);
 
 /*
  * Key-value GET server (the network case study of section 7.3: GPU

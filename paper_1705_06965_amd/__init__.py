@@ -125,7 +125,7 @@ _SIGS = {
                                      C.c_uint64, C.c_uint32, C.c_uint32, _P]),
     "gsys_wordscan": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64,
                                 C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
-                                C.c_uint32, _P]),
+                                C.c_uint32, C.c_uint32, _P]),
     "gsys_kv_build": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
                                 C.c_uint64, _P]),
     "gsys_kv_io_bytes": (C.c_uint64, []),

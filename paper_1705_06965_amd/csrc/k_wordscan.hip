@@ -57,6 +57,7 @@ struct WsArgs {
   uint32_t cbuf;
   uint32_t n_chunks;
   uint32_t nq;
+  uint32_t passes;          // persistent forms: scans of every chunk in one launch
 };
 
 struct Shared {
@@ -277,22 +278,27 @@ __device__ __forceinline__ uint32_t grab(const WsArgs& A, Shared& S) {
   return v;
 }
 
-// Persistent form: chunks come from a device work counter; the pread of the
-// next chunk is issued before the current one is scanned.
+// Persistent form: work items come from a device work counter; the pread of
+// the next one is issued before the current one is scanned.  Work item w is
+// chunk w mod n_chunks of pass w / n_chunks: with several passes the
+// work-groups go from one pass to the next without draining, and each pass
+// adds its counts.
 __global__ __launch_bounds__(kWG) void wordscan_persistent(WsArgs A) {
   __shared__ Shared S;
   build_table(A, S);
+  const uint32_t total = A.n_chunks * A.passes;
   uint32_t cur = grab(A, S);
-  if (cur >= A.n_chunks) return;
+  if (cur >= total) return;
   uint32_t bi = 0;
-  Ticket tk = issue_chunk(A, cur, (uint64_t)blockIdx.x * 2 + bi);
+  Ticket tk = issue_chunk(A, cur % A.n_chunks, (uint64_t)blockIdx.x * 2 + bi);
   for (;;) {
     const uint32_t nxt = grab(A, S);
     Ticket tkn{0, 0, 0};
-    if (nxt < A.n_chunks) tkn = issue_chunk(A, nxt, (uint64_t)blockIdx.x * 2 + (bi ^ 1u));
+    if (nxt < total)
+      tkn = issue_chunk(A, nxt % A.n_chunks, (uint64_t)blockIdx.x * 2 + (bi ^ 1u));
     const int64_t r = wait_wg(A.c, tk);
-    scan_chunk(A, S, cur, (uint64_t)blockIdx.x * 2 + bi, r);
-    if (nxt >= A.n_chunks) break;
+    scan_chunk(A, S, cur % A.n_chunks, (uint64_t)blockIdx.x * 2 + bi, r);
+    if (nxt >= total) break;
     cur = nxt;
     tk = tkn;
     bi ^= 1u;
@@ -444,8 +450,12 @@ using namespace gsys_ws;
 
 int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t chunk_max,
                   uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts, uint32_t nfiles,
-                  uint64_t staging, uint64_t staging_bytes, uint32_t form, void* stream) {
+                  uint64_t staging, uint64_t staging_bytes, uint32_t form, uint32_t passes,
+                  void* stream) {
   if (!ctx || !chunks || !queries || !qlens || !counts) return -EINVAL;
+  if (passes == 0 || (form == GSYS_PLAIN && passes != 1) ||
+      (uint64_t)n_chunks * passes > 0xffffffffull)
+    return -EINVAL;
   if (nq == 0 || nq > kMaxQ || chunk_max == 0 || chunk_max > (64u << 20)) return -EINVAL;
   const uint32_t cbuf = (chunk_max + 64 + 15) & ~15u;
   if (gsys_internal::check_host_range(ctx, staging, staging_bytes)) return -EFAULT;
@@ -462,6 +472,7 @@ int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
   A.cbuf = cbuf;
   A.n_chunks = n_chunks;
   A.nq = nq;
+  A.passes = passes;
   if (form != GSYS_PLAIN && form != GSYS_PERSISTENT && form != GSYS_GRAPH) return -EINVAL;
   // zero the counts and the work counter, then scan
   uint64_t ncount = (uint64_t)nfiles * nq;
@@ -483,7 +494,8 @@ int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
     if (n_chunks && staging_bytes < per_wg) return -EINVAL;
     uint32_t grid = gsys_internal::resident_grid(ctx, (const void*)wordscan_persistent, kWG, 0);
     if (!grid) return -ENODEV;
-    grid = (uint32_t)std::min<uint64_t>({(uint64_t)grid, staging_bytes / per_wg, (uint64_t)n_chunks});
+    grid = (uint32_t)std::min<uint64_t>(
+        {(uint64_t)grid, staging_bytes / per_wg, (uint64_t)n_chunks * passes});
     const uint32_t req = gsys_internal::persistent_grid_override(ctx);
     if (req && req < grid) grid = req;
     k[2].kernel = (const void*)wordscan_persistent;
@@ -537,6 +549,7 @@ int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
   A.w.staging = staging;
   A.w.cbuf = cbuf;
   A.w.n_chunks = 0;
+  A.w.passes = 1;
   A.w.nq = nq;
   A.paths = paths;
   A.file_ret = (int64_t*)file_ret;

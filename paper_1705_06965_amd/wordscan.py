@@ -65,7 +65,9 @@ class WordScanRunner:
         self.staging_p = ctx.host_alloc(self.persistent_bytes)
         self.staging_w = None
 
-    def launch(self, form=PERSISTENT, stream=None):
+    def launch(self, form=PERSISTENT, stream=None, passes: int = 1):
+        """One launch; the persistent forms scan the corpus `passes` times in
+        it (counts add up)."""
         if form == PLAIN:
             if self.staging_w is None:
                 self.staging_w = self.ctx.host_alloc(self.plain_bytes)
@@ -75,11 +77,11 @@ class WordScanRunner:
         return check(lib.gsys_wordscan(self.ctx.h, self.chunks.data_ptr(), self.n_chunks,
                                        self.chunk_max, self.queries.data_ptr(),
                                        self.qlens.data_ptr(), self.nq, self.counts.data_ptr(),
-                                       self.nfiles, st.dev, sb, form, _stream(stream)),
+                                       self.nfiles, st.dev, sb, form, passes, _stream(stream)),
                      "gsys_wordscan")
 
-    def run(self, form=PERSISTENT, stream=None):
-        self.launch(form, stream)
+    def run(self, form=PERSISTENT, stream=None, passes: int = 1):
+        self.launch(form, stream, passes)
         self.torch.cuda.synchronize()
         rc = self.ctx.wait(60_000_000_000)
         if rc:
@@ -97,18 +99,19 @@ class WordScanRunner:
         self.fds = []
 
 
-def host_pread_rate(runner: "WordScanRunner", threads: int, reps: int = 3) -> float:
-    """GB/s at which `threads` host threads pread the runner's chunks into its
-    persistent staging with no GPU work (gsys_host_pread_rate): the host's
-    side of the file scan's roofline."""
+def host_pread_rate(runner: "WordScanRunner", threads: int, reps: int = 3,
+                    passes: int = 10) -> float:
+    """GB/s at which `threads` host threads pread the runner's chunks, `passes`
+    times over, into its persistent staging with no GPU work
+    (gsys_host_pread_rate): the host's side of the file scan's roofline."""
     import ctypes as C
     tab = chunk_table(runner.fds, runner.sizes, runner.chunk_max)
-    fds = np.ascontiguousarray(tab["fd"], dtype=np.int32)
-    offs = np.ascontiguousarray(tab["off"], dtype=np.uint64)
-    lens = np.ascontiguousarray(tab["len"], dtype=np.uint32)
+    fds = np.ascontiguousarray(np.tile(tab["fd"], passes), dtype=np.int32)
+    offs = np.ascontiguousarray(np.tile(tab["off"], passes), dtype=np.uint64)
+    lens = np.ascontiguousarray(np.tile(tab["len"], passes), dtype=np.uint32)
     slot = staging_bytes(runner.chunk_max, 1)
     out = C.c_double()
-    check(lib.gsys_host_pread_rate(fds.ctypes.data, offs.ctypes.data, lens.ctypes.data, len(tab),
+    check(lib.gsys_host_pread_rate(fds.ctypes.data, offs.ctypes.data, lens.ctypes.data, len(lens),
                                    runner.staging_p.host, slot, runner.persistent_bytes // slot,
                                    threads, reps, C.byref(out)), "gsys_host_pread_rate")
     return out.value

@@ -107,3 +107,34 @@ def test_empty_files_and_long_tokens(gs, tmpdata):
         for form in (g.PERSISTENT, g.PLAIN):
             assert (r.run(form) == want).all()
         r.close()
+
+
+@pytest.mark.parametrize("form", ["persistent", "graph"])
+@pytest.mark.parametrize("passes", [2, 5])
+def test_passes_in_one_launch(gs, corpus, form, passes):
+    """Several passes over the corpus in one persistent launch (the
+    measurement form of section 7.1's scan): every count is `passes` times
+    the oracle's; one pass of the same runner afterwards gives the oracle's."""
+    g, ctx = gs
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    c, want = corpus
+    r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=65536, persistent_buffers=16)
+    fm = g.PERSISTENT if form == "persistent" else g.GRAPH
+    say("passes", passes, form)
+    got = r.run(fm, passes=passes)
+    assert (got == want * passes).all()
+    assert (r.run(fm) == want).all()
+    r.close()
+
+
+def test_passes_refused_where_not_meaningful(gs, corpus):
+    g, ctx = gs
+    import errno
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    c, _ = corpus
+    r = WordScanRunner(ctx, c.paths[:2], c.queries, chunk_max=65536)
+    for form, passes in ((g.PERSISTENT, 0), (g.PLAIN, 2)):
+        with pytest.raises(g.GsysError) as e:
+            r.launch(form, passes=passes)
+        assert e.value.errno == errno.EINVAL
+    r.close()
