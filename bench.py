@@ -445,6 +445,9 @@ def run_sweep(args):
                              "ms_per_step": round(1e3 * pt / len(pw), 3),
                              "kernel_ms": round(float(np.mean(pk)), 3)}
         res["persistent_over_plain"] = round(value / pv, 3)
+        # the plain form on all the pollers it can have (its best pool): the
+        # same run when the persistent form's pool is already all of them
+        res["persistent_over_best_plain"] = res["persistent_over_plain"]
         if "plain_full" in out:
             qt, qw, qk, _ = out["plain_full"]
             qv = calls_per_step * len(qw) / qt
