@@ -130,7 +130,7 @@ __device__ __forceinline__ IoSet io_set(const KvArgs& A, uint32_t k) {
 // caller's wavefront only (a relaxed consumer call has no barrier before it);
 // every work-item calls this.
 template <B b>
-__device__ __forceinline__ void post_recv(const KvArgs& A, const IoSet& S, Ticket* tk) {
+__device__ __forceinline__ Ticket post_recv(const KvArgs& A, const IoSet& S) {
   const uint32_t tid = threadIdx.x;
   if (tid < 64)
     for (uint32_t i = tid; i < A.batch; i += 64) {
@@ -139,7 +139,9 @@ __device__ __forceinline__ void post_recv(const KvArgs& A, const IoSet& S, Ticke
       stg16((uint64_t)(S.rl + i) + 16, u32x4{0u, 0u, 0u, 0u});
     }
   Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)S.rl, A.batch, S.rbase, 0, 0}};
-  call_wg<O::Relaxed, b>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra, tk);
+  Ticket tk{0, 0, 0};
+  call_wg<O::Relaxed, b>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra, &tk);
+  return tk;  // meaningful on thread 0 of a non-blocking call
 }
 
 // This work-item's datagram of a completed receive list, if it got one
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
   const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
   for (;;) {
     if (stop_now(A, t_end)) break;
-    post_recv<B::Blocking>(A, S, nullptr);
+    post_recv<B::Blocking>(A, S);
     const int32_t got = received(A, S);
     const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
     if (n == 0) {
@@ -260,21 +262,22 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
 
 __global__ __launch_bounds__(kWG) void kv_serve_pipelined(KvArgs A) {
   const uint32_t tid = threadIdx.x;
-  const IoSet S0 = io_set(A, 0), S1 = io_set(A, 1);
   // tickets are meaningful on thread 0; send_busy is uniform
   Ticket r0{0, 0, 0}, r1{0, 0, 0}, s0{0, 0, 0}, s1{0, 0, 0};
   bool send_busy0 = false, send_busy1 = false;
   uint32_t idle = 0, k = 0;
   const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
-  post_recv<B::NonBlocking>(A, S0, &r0);
+  r0 = post_recv<B::NonBlocking>(A, io_set(A, 0));
   for (;;) {
     if (stop_now(A, t_end)) break;
-    const IoSet& S = k ? S1 : S0;
+    const IoSet S = io_set(A, k);
     // the next batch's receive goes out before this one is answered (its
     // set was answered in the previous step)
-    if (k) post_recv<B::NonBlocking>(A, S0, &r0);
-    else post_recv<B::NonBlocking>(A, S1, &r1);
-    wait_wg(A.c, k ? r1 : r0);
+    const Ticket nr = post_recv<B::NonBlocking>(A, io_set(A, k ^ 1u));
+    if (k) r0 = nr;
+    else r1 = nr;
+    const Ticket rt = k ? r1 : r0;  // by value: a selected reference would live in memory
+    wait_wg(A.c, rt);
     const int32_t got = received(A, S);
     const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
     if (n == 0) {
@@ -285,14 +288,19 @@ __global__ __launch_bounds__(kWG) void kv_serve_pipelined(KvArgs A) {
     idle = 0;
     // the set's previous send must be done before its list and replies are
     // rewritten
-    if (k ? send_busy1 : send_busy0) wait_wg(A.c, k ? s1 : s0);
+    if (k ? send_busy1 : send_busy0) {
+      const Ticket wt = k ? s1 : s0;
+      wait_wg(A.c, wt);
+    }
     answer(A, S, got);
     Args6 sa{{(uint64_t)(int64_t)A.fd, (uint64_t)S.sl, n, S.sbase, 0, 0}};
+    Ticket st{0, 0, 0};
+    call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa, &st);
     if (k) {
-      call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa, &s1);
+      s1 = st;
       send_busy1 = true;
     } else {
-      call_wg<O::Relaxed, B::NonBlocking>(A.c, GSYS_NR_SENDTO, GSYS_F_LIST, sa, &s0);
+      s0 = st;
       send_busy0 = true;
     }
     if (tid == 0) atomicAdd(A.served, (unsigned long long)n);
@@ -302,7 +310,8 @@ __global__ __launch_bounds__(kWG) void kv_serve_pipelined(KvArgs A) {
   // the receive in flight and the sends not yet waited for finish before
   // the work-group leaves (stop is raised once every request is answered,
   // so the receive finds an empty socket)
-  wait_wg(A.c, k ? r1 : r0);
+  const Ticket last = k ? r1 : r0;
+  wait_wg(A.c, last);
   if (send_busy0) wait_wg(A.c, s0);
   if (send_busy1) wait_wg(A.c, s1);
 }
