@@ -461,6 +461,29 @@ def run_sweep(args):
     res["roofline"]["host_pread_GBps"] = round(hp, 2)
     res["roofline"]["host_pread_calls_per_s"] = round(hp * 1e9 / ITEM, 1)
     res["roofline"]["frac_of_host_pread"] = round(achieved / hp, 4)
+    # context: the kernel-split model (section 2, Fig. 1 left).  The host
+    # has just read every item into staging (the probe above, item i at
+    # staging + i * 4 KiB); one kernel then checksums them all.  Its time is
+    # the host's reads followed by that kernel, nothing overlapped.
+    if r.staging_bytes >= calls_per_step * ITEM:
+        from paper_1705_06965_amd.fnv import consume
+        rets = torch.full((calls_per_step,), ITEM, dtype=torch.int64, device="cuda")
+        out_split = torch.zeros(calls_per_step, dtype=torch.int64, device="cuda")
+        ks = []
+        for _ in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            consume(ctx, r.staging.dev, rets, ITEM, out_split, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ks.append(e0.elapsed_time(e1))
+        if not torch.equal(out_split, r.out_fnv):
+            raise RuntimeError("kernel-split checksums differ from the persistent form's")
+        host_ms = calls_per_step * ITEM / (hp * 1e9) * 1e3
+        kms = float(np.median(ks[1:]))
+        res["kernel_split"] = {"value": round(calls_per_step / ((host_ms + kms) * 1e-3), 1),
+                               "unit": "syscalls/s", "host_pread_ms": round(host_ms, 3),
+                               "kernel_ms": round(kms, 3)}
     if cpu:
         res["cpu_baseline"] = cpu
     r.close()
