@@ -8,13 +8,15 @@ value so far; a new value must beat the best by 1% to replace it.
             sleep_max (GPU wait backoff cap), ring_slots D, coalescing (K, T)
             (section 4.2); objective: host calls per second
   wordscan  service_threads, buffers (two per persistent work-group, so also
-            the grid), sleep_max; objective: scanned GB/s
+            the grid), sleep_max; objective: scanned GB/s over launches of
+            several passes (the form the benchmark times)
   serve     grid (persistent work-groups), sleep_max, service_threads;
             objective: p99 latency at the offered load, among settings that
             keep up with it
   kv, kv8   grid (server work-groups), batch (datagrams per list call),
-            service_threads, with 4 (kv) or 8 (kv8) load-generator threads
-            on the same host; objective: GETs per second
+            service_threads, and for kv the server loop (pipelined or
+            blocking), with 4 (kv) or 8 (kv8) load-generator threads on the
+            same host; objective: GETs per second
 """
 from __future__ import annotations
 
@@ -146,8 +148,9 @@ def tune_sweep(path: str, offs, log=print) -> dict:
             "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
 
 
-def measure_wordscan(params: dict, corpus, passes: int = 4) -> float:
-    """Scanned GB/s of the persistent word search with `params`."""
+def measure_wordscan(params: dict, corpus, launches: int = 2, passes: int = 10) -> float:
+    """Scanned GB/s of the persistent word search with `params`, over
+    `launches` launches of `passes` passes each (after two warm-up launches)."""
     import torch
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.wordscan import WordScanRunner
@@ -156,15 +159,15 @@ def measure_wordscan(params: dict, corpus, passes: int = 4) -> float:
     try:
         r = WordScanRunner(ctx, corpus.paths, corpus.queries, chunk_max=1 << 20,
                            persistent_buffers=params["buffers"])
-        for k in range(2 + passes):
+        for k in range(2 + launches):
             if k == 2:
                 t = time.perf_counter()
-            r.launch(g.PERSISTENT)
+            r.launch(g.PERSISTENT, passes=passes)
             torch.cuda.synchronize()
             ctx.wait()
         dt = time.perf_counter() - t
         r.close()
-        return round(corpus.total_bytes * passes / dt / 1e9, 3)
+        return round(corpus.total_bytes * passes * launches / dt / 1e9, 3)
     finally:
         ctx.shutdown()
 
