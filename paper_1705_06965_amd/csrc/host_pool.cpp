@@ -286,15 +286,20 @@ void Pool::note_errno(int64_t ret) {
   bump(ctr().ehist[b], 1);
 }
 
-// Execute one single (non-list) request.
+// Execute one request (a descriptor list goes to exec_list).
 int64_t Pool::execute(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
-  if (s.flags & GSYS_F_LIST) return exec_list(s, calls, merged);
   if (inj_left_.load(std::memory_order_acquire) && s.nr == inj_nr_.load(std::memory_order_relaxed)) {
+    // an injected fault fails the whole request before anything runs
     uint32_t left = inj_left_.load(std::memory_order_acquire);
     while (left && !inj_left_.compare_exchange_weak(left, left - 1, std::memory_order_acq_rel))
       ;
-    if (left) return -(int64_t)inj_err_.load(std::memory_order_relaxed);
+    if (left) {
+      const int64_t e = -(int64_t)inj_err_.load(std::memory_order_relaxed);
+      if (s.flags & GSYS_F_LIST) note_errno(e);  // single calls are counted by the caller
+      return e;
+    }
   }
+  if (s.flags & GSYS_F_LIST) return exec_list(s, calls, merged);
   const uint64_t* a = s.args;
   int64_t r;
   switch (s.nr) {

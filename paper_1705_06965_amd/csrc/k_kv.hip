@@ -128,9 +128,10 @@ __device__ __forceinline__ IoSet io_set(const KvArgs& A, uint32_t k) {
 
 // The receive list of a set: batch empty datagram slots.  Written by the
 // caller's wavefront only (a relaxed consumer call has no barrier before it);
-// every work-item calls this.
+// every work-item calls this.  Returns the call's result to every work-item
+// (blocking) or GSYS_NOT_WAITED with the ticket in *tk on thread 0.
 template <B b>
-__device__ __forceinline__ Ticket post_recv(const KvArgs& A, const IoSet& S) {
+__device__ __forceinline__ int64_t post_recv(const KvArgs& A, const IoSet& S, Ticket* tk) {
   const uint32_t tid = threadIdx.x;
   if (tid < 64)
     for (uint32_t i = tid; i < A.batch; i += 64) {
@@ -139,18 +140,27 @@ __device__ __forceinline__ Ticket post_recv(const KvArgs& A, const IoSet& S) {
       stg16((uint64_t)(S.rl + i) + 16, u32x4{0u, 0u, 0u, 0u});
     }
   Args6 ra{{(uint64_t)(int64_t)A.fd, (uint64_t)S.rl, A.batch, S.rbase, 0, 0}};
-  Ticket tk{0, 0, 0};
-  call_wg<O::Relaxed, b>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra, &tk);
-  return tk;  // meaningful on thread 0 of a non-blocking call
+  return call_wg<O::Relaxed, b>(A.c, GSYS_NR_RECVFROM, GSYS_F_LIST, ra, tk);
 }
 
 // This work-item's datagram of a completed receive list, if it got one
 // (datagrams arrive as a prefix of the list: the host stops at -EAGAIN).
-__device__ __forceinline__ int32_t received(const KvArgs& A, const IoSet& S) {
+// `ret` is the list call's result: when it failed, the list is not read at
+// all (a call the host never ran leaves every descriptor as the GPU wrote
+// it), and the batch is dropped: clients send again, and a GET is
+// idempotent.
+__device__ __forceinline__ int32_t received(const KvArgs& A, const IoSet& S, int64_t ret) {
   const uint32_t tid = threadIdx.x;
+  if (ret < 0) return -1;
   return tid < A.batch ? __hip_atomic_load(gp(&S.rl[tid].len_ret), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_SYSTEM)
                        : -1;
+}
+
+// A call failure that ends the server: the host stopped serving the
+// context, or a wait outlived the watchdog.
+__device__ __forceinline__ bool fatal(int64_t ret) {
+  return ret == GSYS_ETIMEDOUT_RET || ret == GSYS_ESHUTDOWN_RET;
 }
 
 // Look up every received request and write its reply and send descriptor
@@ -241,8 +251,9 @@ __global__ __launch_bounds__(kWG) void kv_serve(KvArgs A) {
   const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
   for (;;) {
     if (stop_now(A, t_end)) break;
-    post_recv<B::Blocking>(A, S);
-    const int32_t got = received(A, S);
+    const int64_t rr = post_recv<B::Blocking>(A, S, nullptr);
+    if (fatal(rr)) break;
+    const int32_t got = received(A, S, rr);
     const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
     if (n == 0) {
       idle_backoff(idle++);
@@ -267,18 +278,23 @@ __global__ __launch_bounds__(kWG) void kv_serve_pipelined(KvArgs A) {
   bool send_busy0 = false, send_busy1 = false;
   uint32_t idle = 0, k = 0;
   const uint64_t t_end = wall_clock64() + A.lifetime_ticks;
-  r0 = post_recv<B::NonBlocking>(A, io_set(A, 0));
+  post_recv<B::NonBlocking>(A, io_set(A, 0), &r0);
   for (;;) {
     if (stop_now(A, t_end)) break;
     const IoSet S = io_set(A, k);
     // the next batch's receive goes out before this one is answered (its
     // set was answered in the previous step)
-    const Ticket nr = post_recv<B::NonBlocking>(A, io_set(A, k ^ 1u));
+    Ticket nr{0, 0, 0};
+    post_recv<B::NonBlocking>(A, io_set(A, k ^ 1u), &nr);
     if (k) r0 = nr;
     else r1 = nr;
     const Ticket rt = k ? r1 : r0;  // by value: a selected reference would live in memory
-    wait_wg(A.c, rt);
-    const int32_t got = received(A, S);
+    const int64_t rr = wait_wg(A.c, rt);
+    if (fatal(rr)) {
+      k ^= 1u;  // the receive just posted is the one in flight
+      break;
+    }
+    const int32_t got = received(A, S, rr);
     const uint32_t n = (uint32_t)__syncthreads_count(got >= 0);
     if (n == 0) {
       idle_backoff(idle++);

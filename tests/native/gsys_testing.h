@@ -63,10 +63,12 @@ int gsys_test_unregister_now(gsys_ctx *ctx, uint32_t id);
 int gsys_test_ring_ctl(gsys_ctx *ctx, uint64_t *out, uint64_t max);
 
 /*
- * Fault injection: the next `count` single (non-list) requests with call
- * number `nr` are answered with -err instead of being executed (any
- * context, device or CPU-only).  count 0 clears it.  Used to check that a
- * caller sees exactly the -errno the host produced.  Returns 0 or -EINVAL.
+ * Fault injection: the next `count` requests with call number `nr`, single
+ * or descriptor-list, are answered with -err instead of being executed (a
+ * list's descriptors are left as the caller wrote them) in any context,
+ * device or CPU-only.  count 0 clears it.  Used to check that a caller sees
+ * exactly the -errno the host produced, and what it does when a whole call
+ * fails.  Returns 0 or -EINVAL.
  */
 int gsys_test_inject(gsys_ctx *ctx, uint16_t nr, int32_t err, uint32_t count);
 

@@ -116,3 +116,39 @@ def test_kv_full_table_sampled_requests(gs):
     assert 0 < hits < len(reqs)
     srv.close()
     ix.close()
+
+
+@pytest.mark.parametrize("loop", ["pipelined", "blocking"])
+def test_failed_receive_calls_are_dropped(gs, loop):
+    """Receive list calls that fail as a whole (20 injected -EIO, before the
+    host touches the list) are dropped by the server: no reply is built from
+    the list the GPU wrote, so no send goes to an empty address (no -EINVAL
+    from the host), and every request is still answered byte-exact (clients
+    send again after a loss; a GET is idempotent)."""
+    g, ctx = gs
+    import errno
+    import gsys_hooks as hooks
+    from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
+    kv = synth.kv_set(n_keys=5000, n_req=8000, miss_every=16)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=4, batch=64,
+                   pipelined=loop == "pipelined")
+    reqs = make_requests(kv.req_keys)
+    ctx.stats(reset=True)
+    assert hooks.lib.gsys_test_inject(ctx.h, g.NR_RECVFROM, errno.EIO, 20) == 0
+    say("kv with 20 failed receive calls", loop)
+    srv.start(lifetime_ms=60_000)
+    try:
+        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=2, window=32)
+    finally:
+        srv.stop()
+    assert hooks.lib.gsys_test_inject(ctx.h, g.NR_RECVFROM, errno.EIO, 0) == 0
+    assert got == len(reqs)
+    st = ctx.stats()
+    assert st["errno_hist"][3] == 0          # no -EINVAL: nothing sent to an empty address
+    assert st["errno_hist"][7] >= 20         # the injected -EIO calls ('other')
+    for k in range(len(reqs)):
+        want = ix.reply(reqs[k].tobytes())
+        assert rlen[k] == len(want) and replies[k, :rlen[k]].tobytes() == want, k
+    srv.close()
+    ix.close()

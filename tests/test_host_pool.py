@@ -689,6 +689,37 @@ def test_injected_errno_reaches_the_caller(datafile):
         os.close(fd)
 
 
+def test_injected_errno_fails_a_whole_list(datafile):
+    """A fault injected for a descriptor-list call fails the whole call
+    before anything runs: the call returns -EIO and every descriptor keeps
+    what the caller wrote; the next list runs normally."""
+    fd = os.open(datafile, os.O_RDONLY)
+    ctx = _ctx(ring_slots=256)
+    try:
+        ctx.allow_fd(fd, g.FD_READ)
+        buf = ctx.host_alloc(8 * 4096)
+        lst = ctx.host_alloc(8 * 16)
+        d = np.zeros(8, dtype=[("off", "<u8"), ("buf_off", "<u4"), ("len_ret", "<i4")])
+        d["off"] = np.arange(8) * 8192
+        d["buf_off"] = np.arange(8) * 4096
+        d["len_ret"] = 4096
+        lst.array[:d.nbytes] = d.view(np.uint8)
+        assert hooks.lib.gsys_test_inject(ctx.h, g.NR_PREAD64, errno.EIO, 1) == 0
+        r = _raw(ctx, g.NR_PREAD64, [fd, lst.dev, 8, buf.dev], flags=g.F_BLOCKING | g.F_LIST)
+        assert r == -errno.EIO
+        assert (lst.array[:d.nbytes].view(d.dtype)["len_ret"] == 4096).all()
+        assert not buf.array.any()
+        assert ctx.stats()["errno_hist"][7] == 1
+        r = _raw(ctx, g.NR_PREAD64, [fd, lst.dev, 8, buf.dev], flags=g.F_BLOCKING | g.F_LIST)
+        assert r == 8 * 4096
+        data = np.fromfile(datafile, dtype=np.uint8)
+        for i in range(8):
+            assert (buf.array[i * 4096:(i + 1) * 4096] == data[i * 8192:i * 8192 + 4096]).all()
+    finally:
+        ctx.shutdown()
+        os.close(fd)
+
+
 def test_stats_reset_and_ledger_capacity(datafile):
     """Statistics and ledger records are kept per poller and summed when read:
     a reset makes the current sums the new zero, the ledger keeps at most its
