@@ -91,6 +91,11 @@ typedef struct gsys_comp {
  * len_ret with the call's return value (bytes moved, or -errno), as the
  * slot's args field is reused for the return value.
  * List slot args: [0] fd, [1] list address, [2] count, [3] base address.
+ * The list call's own result is the bytes moved by all its descriptors once
+ * the host has run the list, whatever their individual results; a negative
+ * result means the list never ran (refused as a whole, an injected fault,
+ * or a device-side -ETIMEDOUT / -ESHUTDOWN) and every descriptor still holds
+ * what the caller wrote.
  */
 typedef struct gsys_iodesc {
     uint64_t off;

@@ -467,14 +467,16 @@ void Pool::close_owned() {
 
 // A descriptor-list request: the group's calls run in list order on this
 // thread.  File transfers adjacent both in the file and in memory are merged
-// into one call and the result is split back over the descriptors.
+// into one call and the result is split back over the descriptors.  Returns
+// the bytes moved once the list has run (each descriptor's len_ret holds its
+// own result, errors included), or -errno when the list is refused before any
+// descriptor runs.
 int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
   const uint64_t* a = s.args;
   const int64_t fd = (int64_t)a[0];
   const uint64_t count = a[2];
   const uint64_t base = a[3];
   if (count > (1ull << 24)) return -EINVAL;
-  int64_t first_err = 0;
   uint64_t total = 0;
   if (s.nr == GSYS_NR_PREAD64 || s.nr == GSYS_NR_PWRITE64) {
     const bool rd = s.nr == GSYS_NR_PREAD64;
@@ -524,7 +526,6 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
         }
         prefix += (uint64_t)(lk > 0 ? lk : 0);
         d[k].len_ret = (int32_t)rk;
-        if (rk < 0 && !first_err) first_err = rk;
         if (rk > 0) total += (uint64_t)rk;
         note_errno(rk);
       }
@@ -551,7 +552,6 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
     bool drained = false;
     auto finish = [&](uint64_t i, int64_t r) {
       d[i].len_ret = (int32_t)r;
-      if (r < 0 && r != -EAGAIN && !first_err) first_err = r;
       if (r > 0) total += (uint64_t)r;
       if (r != -EAGAIN) note_errno(r);
     };
@@ -623,7 +623,9 @@ int64_t Pool::exec_list(const gsys_slot& s, uint64_t* calls, uint64_t* merged) {
     bump(ctr().rej, 1);
     return -EPERM;
   }
-  return first_err ? first_err : (int64_t)total;
+  // the list ran: its result is the bytes moved; each descriptor holds its
+  // own result (a negative call result means the list did not run at all)
+  return (int64_t)total;
 }
 
 // Post the result (section 5): the return value goes to the slot's argument

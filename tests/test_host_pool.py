@@ -504,9 +504,9 @@ def test_socket_lists_keep_per_datagram_semantics():
         lst.array[:d.nbytes] = d.view(np.uint8)
         r = _raw(ctx, g.NR_RECVFROM, [srv.fileno(), lst.dev, n_desc, bufs.dev, 0],
                  flags=g.F_BLOCKING | g.F_LIST)
-        assert r == -errno.EINVAL                   # the first error of the list
         out = lst.array[:d.nbytes].view(NETDESC)
         got = out["len_ret"]
+        assert r == int(got[got > 0].sum())         # the list ran: the bytes it moved
         assert got[10] == -errno.EINVAL and got[20] == -errno.EFAULT
         valid = [i for i in range(n_desc) if i not in (10, 20)]
         for k, i in enumerate(valid):
@@ -526,8 +526,8 @@ def test_socket_lists_keep_per_datagram_semantics():
         lst.array[:s.nbytes] = s.view(np.uint8)
         r = _raw(ctx, g.NR_SENDTO, [srv.fileno(), lst.dev, n_dgram, bufs.dev, 0],
                  flags=g.F_BLOCKING | g.F_LIST)
-        assert r == -errno.EINVAL
         sent = lst.array[:s.nbytes].view(NETDESC)["len_ret"]
+        assert r == int(sent[sent > 0].sum())
         assert sent[5] == -errno.EINVAL
         assert (np.delete(sent, 5) == np.delete(s["len_ret"], 5)).all()
         cli.settimeout(2.0)
