@@ -3,6 +3,7 @@
 Every cell of the granularity x ordering x blocking grid (8 legal cells,
 section 4.1) and the persistent / graph forms must give the oracle's vector
 bit for bit.  Calls go through the C ABI (gsys_fnv4k)."""
+import errno
 import os
 import sys
 
@@ -299,4 +300,33 @@ def test_direct_descriptor_lists_match_oracle(gs, mid, wg, monkeypatch):
         f, ret = r.run(*cell)
         assert (ret == want_ret).all(), (wg, cell)
         assert (f == want_fnv).all(), (wg, cell)
+    r.close()
+
+
+def test_failed_item_does_not_mark_its_group(gs, mid):
+    """Items whose pread fails (offsets past 2^63: -EINVAL from the host)
+    inside a work-group's or the kernel's descriptor list: those items
+    report -EINVAL and hash nothing, and every other item of the same list
+    keeps its own bytes and checksum, as the oracle's one-call-per-item
+    reads give (a list call's result is the bytes it moved; each descriptor
+    carries its own result)."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    r0, _ = mid
+    offs = r0.offsets.cpu().numpy().view(np.uint64).copy()
+    bad = [5, 300, 301, len(offs) - 1]
+    offs[bad[0]] = np.uint64(1 << 63)
+    offs[bad[1]] = np.uint64(1 << 63)
+    offs[bad[2]] = np.uint64((1 << 63) + 4096)   # adjacent to the one before: one merged pread
+    offs[bad[3]] = np.uint64((1 << 64) - 4096)
+    want_fnv, want_ret = oracle.pread_fnv(r0.path, offs, 4096)
+    assert (want_ret[bad] == -errno.EINVAL).all() and (np.delete(want_ret, bad) == 4096).all()
+    r = FnvRunner(ctx, r0.path, offs, 4096, wg_size=256)
+    for cell in [("WI", "strong", "block"), ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
+                 ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
+                 ("K", "relaxed", "block"), ("K", "relaxed", "nonblock"), None]:
+        say("failed items", cell)
+        f, ret = r.run(*cell) if cell else r.run(form=g.PERSISTENT)
+        assert (ret == want_ret).all(), (cell, np.nonzero(ret != want_ret)[0][:8])
+        assert (f == want_fnv).all(), cell
     r.close()
