@@ -344,7 +344,8 @@ typedef struct gsys_chunk {
  *   passes    times the persistent forms read and scan every chunk within
  *             the one launch (work-groups go from one pass to the next
  *             without draining); counts add up, so each is passes times the
- *             file's.  The plain form takes 1 only; n_chunks * passes < 2^32.
+ *             file's (uint32, modulo 2^32).  The plain form takes 1 only;
+ *             n_chunks * passes < 2^32.
  * Errors: -EINVAL (shapes), -EFAULT (staging not registered), -ENODEV.
  */
 int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t chunk_max,
