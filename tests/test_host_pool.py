@@ -293,6 +293,24 @@ def test_exported_symbols_exist():
         assert hasattr(hooks.lib, n), n
 
 
+def test_binding_arity_matches_the_header():
+    """Every function include/gsys.h declares is bound with as many argument
+    types as its prototype has parameters (the ctypes layer cannot check
+    this itself: a missing or extra argument would shift every later one)."""
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "gsys.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    protos = re.findall(r"^[A-Za-z_][A-Za-z0-9_ ]*?[\s*]+(gsys_\w+)\s*\(([^;]*?)\)\s*;", src,
+                        flags=re.M | re.S)
+    assert len(protos) >= 25
+    for name, params in protos:
+        params = " ".join(params.split())
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        f = getattr(g.lib, name)
+        assert f.argtypes is not None and len(f.argtypes) == n, (name, n, f.argtypes)
+
+
 def _links_to(path):
     """Open descriptors of this process that refer to `path`."""
     real = os.path.realpath(path)
