@@ -134,6 +134,16 @@ def profile_traffic(workload):
     return d["traffic_bytes"] if d.get("source_sha") == h.hexdigest()[:16] else None
 
 
+def oracle_leg(args):
+    """The oracle, for the CPU-baseline leg only: its timed runs and the
+    comparison of its results with the GPU's.  None with --no-cpu, so that
+    no other part of a run loads it."""
+    if args.no_cpu:
+        return None
+    import oracle
+    return oracle
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -363,8 +373,8 @@ def run_sweep(args):
             ctx2.shutdown()
 
     cpu = None
-    if not args.no_cpu:
-        import oracle
+    oracle = oracle_leg(args)
+    if oracle:
         threads = len(os.sched_getaffinity(0))
         reps = 5
         t0 = time.perf_counter()
@@ -555,8 +565,8 @@ def run_wordscan(args, sub=False):
         if not (r.result() == counts).all():
             raise RuntimeError("plain and persistent forms disagree")
     cpu = None
-    if not args.no_cpu:
-        import oracle
+    oracle = oracle_leg(args)
+    if oracle:
         threads = len(os.sched_getaffinity(0))
         t1 = time.perf_counter()
         want = oracle.wordcount(c.paths, c.queries, threads=threads)
@@ -685,15 +695,16 @@ def _kv_run(args, kv, reqs, clients, sub):
             res_steps.append((dt, lat.copy(), rt, stt))
         print("kv step %d: %.3f s, %.0f GET/s, retransmits %d" % (st, dt, len(reqs) / dt, rt),
               file=sys.stderr, flush=True)
-    # parity on a sample of replies
-    import oracle
-    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
-    for k in np.random.default_rng(9).choice(len(reqs), 4096, replace=False):
-        want = ix.reply(reqs[k].tobytes())
-        if replies[k, :rlen[k]].tobytes() != want:
-            raise RuntimeError("kv reply %d differs from the oracle" % k)
+    # CPU-baseline leg: the oracle's replies for a sample of requests
+    oracle = oracle_leg(args)
+    if oracle:
+        ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+        for k in np.random.default_rng(9).choice(len(reqs), 4096, replace=False):
+            want = ix.reply(reqs[k].tobytes())
+            if replies[k, :rlen[k]].tobytes() != want:
+                raise RuntimeError("kv reply %d differs from the oracle" % k)
     cpu = None
-    if not args.no_cpu:
+    if oracle:
         # the oracle as a CPU server on the same loopback path, same client
         n_cpu = 1_000_000
         threads = max(1, len(os.sched_getaffinity(0)) - clients)
@@ -717,7 +728,8 @@ def _kv_run(args, kv, reqs, clients, sub):
                "sample": "first 1,000,000 GETs against the oracle's CPU UDP server (sorted "
                          "index + bsearch), %d server threads on one socket, same load "
                          "generator" % threads}
-    ix.close()
+    if oracle:
+        ix.close()
     dts = [d for d, _, _, _ in res_steps]
     dt_med = float(np.median(dts))
     lat_all = np.concatenate([l for _, l, _, _ in res_steps]).astype(np.float64)
@@ -821,13 +833,13 @@ def run_serve(args, sub=False):
     lat_s = lat[warm:].astype(np.float64) / 1e3
     span_s = (float(js.arrival_ns[-1]) - float(js.arrival_ns[warm])) / 1e9 + \
         float(np.median(lat_s)) / 1e6
-    # parity on a sample of jobs
-    import oracle
-    rng = np.random.default_rng(11)
+    # CPU-baseline leg: the oracle's results for a sample of jobs
+    oracle = oracle_leg(args)
     data = np.memmap(in_path, dtype=np.uint8, mode="r")
     out = np.memmap(out_path, dtype=np.uint8, mode="r")
     jobs = sr.jobs_np
-    for i in rng.choice(len(js.kind), 300, replace=False):
+    sample = np.random.default_rng(11).choice(len(js.kind), 300, replace=False) if oracle else []
+    for i in sample:
         k = int(js.kind[i])
         if k == 0:
             nb = int(jobs["len"][i]) // 4096
@@ -862,7 +874,7 @@ def run_serve(args, sub=False):
                  "latency_us_p99": round(float(np.percentile(lps, 99)), 1)}
         sp.close()
     cpu = None
-    if not args.no_cpu:
+    if oracle:
         # the oracle runs the first 5,000 jobs on a thread pool, as fast as it can
         threads = len(os.sched_getaffinity(0))
         ofd = os.open(out_path + ".cpu", os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
@@ -1024,16 +1036,18 @@ def run_permute(args):
             med = float(np.median(wall))
             curves[name[cell]][it] = round(med / it * 1e6, 2)      # us per iteration
             kern[name[cell]][it] = round(float(np.median(kms)), 4)  # ms per launch
-        # the file now holds the last iteration count's blocks: spot-check
-        import oracle
-        got = r.file_bytes().reshape(n_blocks, 8192)[pick].ravel()
-        sub = ps.data.reshape(n_blocks, 1024)[pick].ravel()
-        chk = os.path.join(synth.data_dir(), "permute_check.bin")
-        fd = os.open(chk, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
-        oracle.permute(fd, sub, ps.sigma, ps.tau, iters_list[-1], threads=4)
-        os.close(fd)
-        if not np.array_equal(got, np.fromfile(chk, dtype=np.uint8)):
-            raise RuntimeError("GPU blocks differ from the oracle (%s)" % name[cell])
+        # the file now holds the last iteration count's blocks: the CPU-
+        # baseline leg spot-checks them against the oracle
+        oracle = oracle_leg(args)
+        if oracle:
+            got = r.file_bytes().reshape(n_blocks, 8192)[pick].ravel()
+            sub = ps.data.reshape(n_blocks, 1024)[pick].ravel()
+            chk = os.path.join(synth.data_dir(), "permute_check.bin")
+            fd = os.open(chk, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
+            oracle.permute(fd, sub, ps.sigma, ps.tau, iters_list[-1], threads=4)
+            os.close(fd)
+            if not np.array_equal(got, np.fromfile(chk, dtype=np.uint8)):
+                raise RuntimeError("GPU blocks differ from the oracle (%s)" % name[cell])
         print("cell %s done" % name[cell], file=sys.stderr, flush=True)
     lo = iters_list[0]
     best = min(curves, key=lambda c: curves[c][lo])
@@ -1053,8 +1067,8 @@ def run_permute(args):
     lds_peak = 128 * 256 * 2.4e9 / 1e12      # 128 B/clk per CU, 256 CUs, 2.4 GHz
     lds_tbs = lds_bytes / (kern["weak-nonblock"][hi] * 1e-3) / 1e12
     cpu = None
-    if not args.no_cpu:
-        import oracle
+    oracle = oracle_leg(args)
+    if oracle:
         threads = len(os.sched_getaffinity(0))
         chk = os.path.join(synth.data_dir(), "permute_cpu.bin")
         fd = os.open(chk, os.O_RDWR | os.O_CREAT | os.O_TRUNC, 0o600)
@@ -1114,13 +1128,12 @@ def run_tiny(args):
     CLOCK_MONOTONIC).  value = 64 calls / median end-to-end time."""
     import numpy as np
     import torch
-    import oracle
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
     path = synth.random_file(1, 262144, name="c1_256k.bin")
     offs = synth.tiny_offsets(64)
-    want, _ = oracle.pread_fnv(path, offs, 4096)
+    oracle = oracle_leg(args)
     ctx = g.Context(ring_slots=1 << 10, service_threads=max(0, args.service_threads),
                     device_timeout_ns=10_000_000_000, flags=g.CFG_LEDGER)
     r = FnvRunner(ctx, path, offs, 4096, wg_size=64)
@@ -1153,10 +1166,14 @@ def run_tiny(args):
         to_done.extend(((t_end - t0) / 1e3).tolist())
         service.extend(((t_end - led[:, 4].astype(np.int64)) / 1e3).tolist())
     f, ret = r.result()
-    if not ((ret == 4096).all() and (f == want).all()):
-        raise RuntimeError("GPU checksums differ from the oracle")
+    if not (ret == 4096).all():
+        raise RuntimeError("a tiny-case pread returned %s" % ret[ret != 4096][:4])
     cpu = None
-    if not args.no_cpu:
+    if oracle:
+        # CPU-baseline leg: the oracle's checksums, then its latency
+        want, _ = oracle.pread_fnv(path, offs, 4096)
+        if not (f == want).all():
+            raise RuntimeError("GPU checksums differ from the oracle")
         n_cpu = 2000
         ts = []
         for _ in range(n_cpu):
@@ -1189,10 +1206,13 @@ def run_tiny(args):
     print(json.dumps(res), flush=True)
 
 
-def _spot_check(path, offs, item, f, ret, k=64):
-    """Recompute k evenly spaced items with the oracle."""
+def _spot_check(args, path, offs, item, f, ret, k=64):
+    """CPU-baseline leg: recompute k evenly spaced items with the oracle
+    (nothing with --no-cpu)."""
     import numpy as np
-    import oracle
+    oracle = oracle_leg(args)
+    if not oracle:
+        return
     pick = np.unique(np.linspace(0, len(offs) - 1, k).astype(np.int64))
     want_f, want_r = oracle.pread_fnv(path, offs[pick], item)
     if not ((f[pick] == want_f).all() and (ret[pick] == want_r).all()):
@@ -1252,7 +1272,7 @@ def run_granularity(args):
             code = g.cell_code(*cell)
             t = _time_runs(r, ctx, code, g.PLAIN, steps, 1)
             f, ret = r.result()
-            _spot_check(path, offs, ITEM, f, ret)
+            _spot_check(args, path, offs, ITEM, f, ret)
             name = "/".join(cell)
             left[S][name] = round(1e3 * t, 3)
             if S == sizes[-1] and n / t > best[0]:
@@ -1267,7 +1287,7 @@ def run_granularity(args):
         r = FnvRunner(ctx, path, offs, ITEM, wg_size=wg)
         t = _time_runs(r, ctx, g.cell_code("WG", "relaxed", "block"), g.PLAIN, steps, 1)
         f, ret = r.result()
-        _spot_check(path, offs, ITEM, f, ret)
+        _spot_check(args, path, offs, ITEM, f, ret)
         st = ctx.stats()
         right[wg] = round(1e3 * t, 3)
         r.close()
@@ -1319,7 +1339,7 @@ def run_coalesce(args):
             r = FnvRunner(ctx, path, offs, piece, wg_size=256)
             t = _time_runs(r, ctx, cell, g.PLAIN, steps, 1)
             f, ret = r.result()
-            _spot_check(path, offs, piece, f, ret)
+            _spot_check(args, path, offs, piece, f, ret)
             st = ctx.stats(reset=True)
             out[key][piece] = {"ms": round(1e3 * t, 3),
                                "ns_per_byte": round(1e9 * t / (n * piece), 4),
@@ -1410,8 +1430,8 @@ def run_wordopen(args):
         pread_gbps = c.total_bytes * len(pw) / pt / 1e9
         ws.close()
     cpu = None
-    if not args.no_cpu:
-        import oracle
+    oracle = oracle_leg(args)
+    if oracle:
         threads = len(os.sched_getaffinity(0))
         t1 = time.perf_counter()
         want, _ = oracle.wordcount_open(d, names, c.queries, chunk=1 << 20, threads=threads)
@@ -1471,14 +1491,14 @@ def run_doorbell(args):
     value = 64 calls / median tiny latency with the doorbell."""
     import numpy as np
     import torch
-    import oracle
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fnv import FnvRunner
     from paper_1705_06965_amd.serve import ServeRun
     path = synth.random_file(1, 262144, name="c1_256k.bin")
     offs = synth.tiny_offsets(64)
-    want, _ = oracle.pread_fnv(path, offs, 4096)
+    oracle = oracle_leg(args)
+    want = oracle.pread_fnv(path, offs, 4096)[0] if oracle else None
     reps = max(50, args.steps)
     cell = g.cell_code("WI", "strong", "block")
     stream = torch.cuda.current_stream()
@@ -1515,7 +1535,7 @@ def run_doorbell(args):
             e2e.append((time.perf_counter() - t0) * 1e6)
         tiny_cores = (_cpu_s() - c0) / (time.perf_counter() - w0)
         f, ret = r.result()
-        if not ((ret == 4096).all() and (f == want).all()):
+        if not ((ret == 4096).all() and (want is None or (f == want).all())):
             raise RuntimeError("GPU checksums differ from the oracle (%s)" % mode)
         m = {"idle_host_cores_busy": round(idle_cores, 3),
              "tiny_after_gap": {"gap_us": args.db_gap_us, "runs": reps,
@@ -1568,7 +1588,6 @@ def run_fileio(args):
     with one kernel-wide read(); per-launch latency."""
     import numpy as np
     import torch
-    import oracle
     import synth
     import paper_1705_06965_amd as g
     from paper_1705_06965_amd.fileio import FileRoundtrip, kernel_io
@@ -1642,7 +1661,8 @@ def run_fileio(args):
     stg.free()
     ctx.shutdown()
     cpu = None
-    if not args.no_cpu:
+    oracle = oracle_leg(args)
+    if oracle:
         threads = len(os.sched_getaffinity(0))
         dc = os.path.join(base, "cpu")
         os.makedirs(dc, exist_ok=True)
