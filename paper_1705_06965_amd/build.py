@@ -1,5 +1,6 @@
 """Build libgsys.so in-tree for gfx950 (hipcc for the HIP sources, g++ for
-the plain C++ host pool), and the CPU oracle next to it when asked."""
+the plain C++ host pool), the demo user program's library beside it, and the
+test-hook library under tests/native."""
 from __future__ import annotations
 
 import concurrent.futures as cf
