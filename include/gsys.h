@@ -474,7 +474,7 @@ typedef struct gsys_job {
  */
 typedef struct gsys_serve_params {
     uint32_t form;               /* GSYS_PERSISTENT: resident work-groups claim tasks in
-                                    job order as jobs are posted; a scan longer than 16 MiB
+                                    job order as jobs are posted; a scan longer than 8 MiB
                                     (environment GSYS_SERVE_SPLIT_MIB overrides the size,
                                     0 = never split) is cut into tasks of that size run by
                                     different work-groups, and the work-group finishing its

@@ -15,7 +15,7 @@
 //
 // Persistent form: the host driver posts a job by raising a counter in
 // host-coherent memory; resident work-groups claim tasks in job order from a
-// device cursor (job, task).  A scan longer than 16 MiB is cut into 16 MiB
+// device cursor (job, task).  A scan longer than 8 MiB is cut into 8 MiB
 // tasks that different work-groups run at once (a 64 MiB scan no longer
 // holds one work-group for its whole read-and-hash time); every other job
 // is one task.
@@ -47,7 +47,7 @@ constexpr uint32_t kWG = 256;
 constexpr uint32_t kPiece = 1u << 20;          // scan read size (256 blocks of 4 KiB)
 constexpr uint32_t kBlock = 4096;
 constexpr uint64_t kRelBytes = 2ull << 20;
-constexpr uint64_t kSplitMiB = 16;             // persistent form: default scan task size
+constexpr uint64_t kSplitMiB = 8;              // persistent form: default scan task size
 // Default persistent grid: work-groups waiting for work poll host memory,
 // and a few hundred of them slow the host pool's calls (see gsys_serve_run).
 constexpr uint32_t kServeGrid = 64;

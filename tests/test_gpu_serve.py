@@ -175,7 +175,7 @@ def test_release_readback_matches_oracle_release_job(gs, mix, tmpdata):
 @pytest.mark.parametrize("form", ["persistent", "plain"])
 def test_split_scans_match_oracle(gs, tmpdata, form):
     """Scans up to 32 MiB: the persistent form cuts every scan longer than
-    its task size (4 MiB here, 16 MiB by default) into tasks run by
+    its task size (4 MiB here, 8 MiB by default) into tasks run by
     different work-groups (up to 8 per job); digests and return values must
     equal the oracle's, as in the plain form (one work-group per job)."""
     g, ctx = gs
@@ -223,7 +223,7 @@ def test_byte_budget_admission(gs, mix, tmpdata):
 
 def test_full_size_scans_default_split(gs, tmpdata):
     """The serving config's largest scans (64 MiB, and 64 MiB - 4 KiB at an
-    unaligned-to-the-split offset) at the default 16 MiB task size, next to
+    unaligned-to-the-split offset) at the default 8 MiB task size, next to
     a pwrite and a release: digests, file bytes and return values equal the
     oracle's."""
     g, ctx = gs
