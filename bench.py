@@ -273,7 +273,7 @@ def run_sweep(args):
         # tuned size came from one of them.
         stream0 = torch.cuda.current_stream()
         pool_trials = {}
-        for P in sorted({int(tp["service_threads"]) or cores - 1, 12, cores - 1}):
+        for P in sorted({int(tp["service_threads"]) or cores - 1, 12, 14, cores - 1}):
             if not 1 <= P <= cores - 1:
                 continue
             c0 = g.Context(ring_slots=tp["ring_slots"], service_threads=P,
