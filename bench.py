@@ -154,6 +154,14 @@ def percentile(xs, q):
 
 def main():
     args = parse()
+    # the pool (and the host pread probe) give every poller its own open file
+    # description of every allowed file: 2,000 files x 15 threads need more
+    # descriptors than a default soft limit allows
+    import resource
+    soft, hard = resource.getrlimit(resource.RLIMIT_NOFILE)
+    want = hard if hard != resource.RLIM_INFINITY else 1 << 20
+    if soft != resource.RLIM_INFINITY and soft < want:
+        resource.setrlimit(resource.RLIMIT_NOFILE, (min(want, 1 << 20), hard))
     if args.gpus != 1:
         print("bench.py measures one GPU: a gsys context drives one GPU, and there is no "
               "multi-GPU path (each GPU would run its own ring and host pool); use --gpus 1",

@@ -411,7 +411,7 @@ int64_t gsys_kv_loadgen(uint32_t server_port, const uint8_t *reqs, uint32_t req_
  * counter, in runs of up to 256 (at least 8 runs per thread), and pread
  * range i into dst + (i mod n_slots) * slot_bytes, each
  * through its own open file description of the file (a read-only re-open of
- * the caller's fd), as the service pool does for GPU-issued preads (the
+ * the caller's fd, made before the timed passes), as the service pool does for GPU-issued preads (the
  * sweep's items, the word search's chunks of section 7.1); the best
  * of `reps` passes, in returned bytes per nanosecond (GB/s), is stored in
  * *out_gbps.  dst must hold n_slots * slot_bytes bytes (caller-owned).

@@ -83,3 +83,35 @@ def test_runs_of_ranges(datafile):
     for i in range(n):
         o, k = int(offs[i]), int(lens[i])
         assert bytes(buf[i * slot:i * slot + k]) == data[o:o + k], i
+
+
+def test_out_of_descriptors_falls_back_to_the_callers(datafile, tmp_path):
+    """With too few descriptors for a private copy of every file in every
+    thread (a low RLIMIT_NOFILE, in a child process), the probe reads through
+    the caller's descriptors instead, as the pool's pollers do, and the bytes
+    are still the file's."""
+    import subprocess
+    import sys
+    fd, data = datafile
+    path = os.readlink("/proc/self/fd/%d" % fd)
+    code = """
+import ctypes as C, os, resource, sys
+import numpy as np
+sys.path.insert(0, %r)
+import paper_1705_06965_amd as g
+fds = [os.open(%r, os.O_RDONLY) for _ in range(24)]
+resource.setrlimit(resource.RLIMIT_NOFILE, (max(fds) + 12, resource.getrlimit(resource.RLIMIT_NOFILE)[1]))
+n = 96
+f = np.array([fds[i %% 24] for i in range(n)], dtype=np.int32)
+o = (np.arange(n, dtype=np.uint64) * 4096)
+l = np.full(n, 4096, dtype=np.uint32)
+buf = np.zeros(n * 4096, dtype=np.uint8)
+out = C.c_double()
+rc = g.lib.gsys_host_pread_rate(f.ctypes.data, o.ctypes.data, l.ctypes.data, n, buf.ctypes.data,
+                                4096, n, 8, 1, C.byref(out))
+want = open(%r, "rb").read(n * 4096)
+print(rc, bytes(buf) == want)
+""" % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), path, path)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split()[-2:] == ["0", "True"], r.stdout
