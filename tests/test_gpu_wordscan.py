@@ -138,3 +138,21 @@ def test_passes_refused_where_not_meaningful(gs, corpus):
             r.launch(form, passes=passes)
         assert e.value.errno == errno.EINVAL
     r.close()
+
+
+def test_full_corpus_in_the_benchmark_configuration(gs):
+    """The benchmark's workload as it is timed: the 2,000-file corpus in
+    1 MiB chunks, 128 chunk buffers (64 work-groups of 512), several passes in
+    one persistent launch and in its graph form: every count is the passes
+    times the oracle's, and a single pass equals the oracle's."""
+    g, ctx = gs
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    c = synth.wordcount_corpus()
+    want = oracle.wordcount(c.paths, c.queries, threads=16)
+    r = WordScanRunner(ctx, c.paths, c.queries, chunk_max=1 << 20, persistent_buffers=128)
+    say("full corpus, one pass")
+    assert (r.run(g.PERSISTENT) == want).all()
+    for fm, passes in ((g.PERSISTENT, 3), (g.GRAPH, 2)):
+        say("full corpus, passes", passes, fm)
+        assert (r.run(fm, passes=passes) == want * passes).all()
+    r.close()
