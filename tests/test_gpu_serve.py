@@ -246,3 +246,43 @@ def test_full_size_scans_default_split(gs, tmpdata):
     sr.close()
     n_scan, n_pw, n_rel = check_outputs(sr, js, res, dig, in_path, out_path, "full-size")
     assert (n_scan, n_pw, n_rel) == (3, 1, 1)
+
+
+def test_full_session_in_the_benchmark_configuration(gs, tmpdata):
+    """The benchmark's serving session as it is timed: 55,000 Poisson jobs at
+    20k/s over the 1 GiB file (scans up to 64 MiB in 8 MiB tasks), 64
+    work-groups, 256 staging buffers: every job returns what the oracle's
+    calls return, every pwrite and release leaves the oracle's bytes in the
+    output file, and a sample of 200 scans has the oracle's digests."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    in_path = synth.random_file(2, 1 << 30, name="c2_1g.bin")
+    js = synth.job_stream(n_jobs=55_000, rate_per_s=20_000.0)
+    out_path = os.path.join(tmpdata, "serve_out_full.bin")
+    sr = ServeRun(ctx, js, in_path, out_path)
+    say("serve full session, jobs", sr.n)
+    res, dig, lat = sr.run(g.PERSISTENT, max_inflight=512, staging_bytes=(2 << 20) * 256,
+                           timeout_ns=300_000_000_000)
+    sr.close()
+    assert (lat != np.uint64(2**64 - 1)).all()
+    jobs = sr.jobs_np
+    kind = js.kind
+    scan, pw, rel = np.nonzero(kind == 0)[0], np.nonzero(kind == 1)[0], np.nonzero(kind == 2)[0]
+    assert (res[scan] == jobs["len"][scan].astype(np.int64)).all()
+    assert (res[pw] == jobs["len"][pw].astype(np.int64)).all()
+    assert (res[rel] == 0).all()
+    data = np.memmap(in_path, dtype=np.uint8, mode="r")
+    out = np.memmap(out_path, dtype=np.uint8, mode="r")
+    for i in pw:
+        off, ln, src = int(jobs["off"][i]), int(jobs["len"][i]), int(jobs["src"][i])
+        assert (out[off:off + ln] == js.content[src:src + ln]).all(), i
+    for i in rel:
+        off, src, pg = int(jobs["off"][i]), int(jobs["src"][i]), int(jobs["page"][i])
+        assert (out[off:off + 64] == data[src + 4096 * pg:src + 4096 * pg + 64]).all(), i
+        assert not out[off + 64:off + 128].any(), i
+    for i in np.random.default_rng(5).choice(scan, 200, replace=False):
+        nb = int(jobs["len"][i]) // 4096
+        offs = int(jobs["off"][i]) + 4096 * np.arange(nb, dtype=np.uint64)
+        want, _ = oracle.pread_fnv(in_path, offs, 4096, threads=8)
+        d0 = int(sr.digest_start[i])
+        assert (dig[d0:d0 + nb] == want).all(), i
