@@ -152,3 +152,30 @@ def test_failed_receive_calls_are_dropped(gs, loop):
         assert rlen[k] == len(want) and replies[k, :rlen[k]].tobytes() == want, k
     srv.close()
     ix.close()
+
+
+@pytest.mark.parametrize("clients,grid,batch", [(4, 32, 64), (8, 8, 128)])
+def test_kv_benchmark_configurations(gs, clients, grid, batch):
+    """The benchmark's key-value runs as they are timed: the 1,000,000-key
+    table, all 4,000,000 Zipf(0.99) GETs, the tuned server shapes for 4 and 8
+    load-generator threads (blocking loop): every request answered, 50,000
+    sampled replies byte-exact per request id against the oracle."""
+    g, ctx = gs
+    from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
+    kv = synth.kv_set()
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=grid, batch=batch,
+                   pipelined=False)
+    reqs = make_requests(kv.req_keys)
+    say("kv benchmark configuration", clients, grid, batch)
+    srv.start(lifetime_ms=120_000)
+    try:
+        got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=clients, window=128)
+    finally:
+        srv.stop()
+    assert got == len(reqs) == 4_000_000
+    for k in np.random.default_rng(clients).choice(len(reqs), 50_000, replace=False):
+        want = ix.reply(reqs[k].tobytes())
+        assert rlen[k] == len(want) and replies[k, :rlen[k]].tobytes() == want, k
+    srv.close()
+    ix.close()
