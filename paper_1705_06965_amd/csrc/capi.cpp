@@ -578,6 +578,24 @@ void* kstate(gsys_ctx* c) { return c->dev_words + 32; }
 uint32_t resident_grid(gsys_ctx* c, const void* kernel, uint32_t block, uint32_t lds) {
   int per_cu = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, lds);
+  if (e == hipSuccess && per_cu < 1) {
+    // The runtime has answered 0 for a work-group that fills a compute unit's
+    // register file exactly (16 wavefronts of 128 VGPRs).  A work-group the
+    // compiler built for this size (its flat work-group size bounds its
+    // registers) whose LDS fits runs alone on an idle compute unit, so one
+    // per compute unit is resident.
+    hipFuncAttributes a{};
+    int dev = 0, lds_cu = 0;
+    hipGetDevice(&dev);
+    if (hipFuncGetAttributes(&a, kernel) == hipSuccess && (int)block <= a.maxThreadsPerBlock &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess &&
+        (uint64_t)lds + a.sharedSizeBytes <= (uint64_t)lds_cu) {
+      fprintf(stderr, "gsys: occupancy query answered 0 (block %u, LDS %u bytes): one "
+              "work-group per compute unit\n", block, lds);
+      return (uint32_t)c->cu_count;
+    }
+  }
   if (e != hipSuccess || per_cu < 1) {
     hipFuncAttributes a{};
     const hipError_t ea = hipFuncGetAttributes(&a, kernel);

@@ -261,13 +261,8 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
   if (form == GSYS_PERSISTENT || form == GSYS_GRAPH) {
     const uint64_t nb = (n_items + wg_size - 1) / wg_size;
     const void* kp = small ? (const void*)fnv4k_persistent<256> : (const void*)fnv4k_persistent<1024>;
-    // Work-groups of this kernel never wait on one another (each one issues
-    // and consumes its own batches), so residency only sizes the grid, and the
-    // grid is capped below one work-group per compute unit.  If the runtime
-    // reports no resident work-group at all (1,024-wide groups fill the
-    // register file exactly), the launch itself checks the shape.
     uint32_t grid = gsys_internal::resident_grid(ctx, kp, wg_size, lds);
-    if (grid == 0) grid = kPersistentGrid;
+    if (grid == 0) return -ENODEV;
     if ((uint64_t)grid > nb) grid = (uint32_t)nb;
     const uint32_t req = gsys_internal::persistent_grid_override(ctx);
     if (req && req < grid) grid = req;
