@@ -750,8 +750,8 @@ def _kv_run(args, kv, reqs, clients, sub):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "key-value GET over loopback UDP: 1M 16-byte keys, values "
-                               "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, 256-datagram "
-                               "recvfrom/sendto list calls per work-group",
+                               "32-1024 B, 4M GETs Zipf(0.99), table load 0.5, %d-datagram "
+                               "recvfrom/sendto list calls per work-group" % tk_["batch"],
                    "server_workgroups": tk_["grid"], "batch": tk_["batch"],
                    "server_loop": "pipelined" if tk_.get("pipelined", 1) else "blocking",
                    "tuned": tk_, "client_threads": clients,

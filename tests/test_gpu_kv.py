@@ -89,9 +89,9 @@ def test_kv_short_and_long_datagrams(gs):
 
 def test_kv_full_table_sampled_requests(gs):
     """The key-value config's table size: 1,000,000 keys (values 32-1,024 B,
-    load 0.5) served by the benchmark's 16 work-groups with 256-datagram
-    batches; 200,000 Zipf(0.99) GETs with planted misses, every reply
-    byte-exact per request id against the oracle."""
+    load 0.5) served by 16 work-groups with 256-datagram batches (the
+    largest list the server takes); 200,000 Zipf(0.99) GETs with planted
+    misses, every reply byte-exact per request id against the oracle."""
     g, ctx = gs
     from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
     kv = synth.kv_set(n_keys=1_000_000, n_req=200_000, miss_every=64)
