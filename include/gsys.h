@@ -302,7 +302,8 @@ const char *gsys_strerror(int code);
  *             pool by a few percent.
  *   wg_size   work-items per work-group: 64, 128, 256, 512 or 1024
  * item_bytes must be a multiple of 64 and at most 1 MiB; n_items % wg_size
- * need not be 0 (the tail work-group is partial).
+ * need not be 0 (the tail work-group is partial).  n_items == 0 returns 0 at
+ * once, launching nothing.
  * Errors: -EINVAL (shapes), -EFAULT (unregistered buffers), -ENODEV.
  */
 int gsys_fnv4k(gsys_ctx *ctx, int fd, uint64_t offsets, uint64_t n_items, uint32_t item_bytes,
@@ -326,7 +327,9 @@ typedef struct gsys_chunk {
  *   chunks    device gsys_chunk[n_chunks]: every file cut into chunks of at
  *             most chunk_max bytes that cover it exactly (a token belongs to
  *             the chunk in which it starts; each chunk's pread also fetches
- *             the byte before it and 16 bytes after it)
+ *             the byte before it and 16 bytes after it).  n_chunks == 0
+ *             (every file empty, or nfiles == 0) launches only the zeroing
+ *             of counts; chunks may then be 0
  *   queries   device uint8[nq * 16], query q in bytes [16q, 16q + qlens[q]);
  *             1 <= qlens[q] <= 16, no delimiter bytes, all distinct;
  *             1 <= nq <= 64
@@ -565,8 +568,10 @@ int gsys_canary(gsys_ctx *ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
  *            read, 3 scanning, 4 close, 5 no more files) and [2w + 1] =
  *            piece << 32 | low 32 bits of the ticket waited for, stored at
  *            system scope so the host can read them while the kernel runs
- * Asynchronous on `stream`; gsys_wait drains the host side.  Errors:
- * -EINVAL, -EFAULT (paths, staging or progress not registered), -ENODEV.
+ * Asynchronous on `stream`; gsys_wait drains the host side.  nfiles == 0
+ * returns 0 once the shapes (nq, chunk) pass, launching nothing; the
+ * pointers may then be null.  Errors: -EINVAL, -EFAULT (paths, staging or
+ * progress not registered), -ENODEV.
  */
 /* Bytes of one piece buffer of gsys_wordcount_open for reads of `chunk`
  * bytes: the carried bytes, the piece and the scanner's window past it. */
@@ -626,7 +631,8 @@ int gsys_permute(gsys_ctx *ctx, int fd, uint64_t in, const uint16_t *sigma, cons
  * max(file_bytes, 16) rounded up to 16 (write area, then read area, per
  * file).  dirfd must be allowed with GSYS_FD_DIR and GSYS_FD_READ |
  * GSYS_FD_WRITE.  file_bytes <= 2 GiB, K <= 2^20.  Asynchronous on
- * `stream`.  Errors: -EINVAL, -EFAULT (paths or staging not registered),
+ * `stream`.  nfiles == 0 returns 0 at once (rets and mismatch may then be
+ * null).  Errors: -EINVAL, -EFAULT (paths or staging not registered),
  * -ENODEV.
  */
 int gsys_file_roundtrip(gsys_ctx *ctx, int dirfd, uint64_t paths, uint32_t nfiles, uint64_t data,
@@ -659,6 +665,7 @@ int gsys_file_kernel_io(gsys_ctx *ctx, int fd, uint32_t nr, uint64_t data, uint6
  * out_fnv[i] = FNV-1a-64 of the first rets[i] bytes (rets: device int64[n],
  * values <= 0 hash nothing) of staging + i * item_bytes.  grid 0 = one
  * work-group per wg_size items, otherwise a grid-stride loop over them.
+ * n_items == 0 returns 0 at once (the pointers may then be null).
  * Errors: -EINVAL.
  */
 int gsys_fnv4k_consume(gsys_ctx *ctx, uint64_t staging, uint64_t rets, uint64_t n_items,

@@ -183,13 +183,13 @@ int gsys_file_roundtrip(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
                         uint64_t file_bytes, uint32_t piece, uint64_t staging,
                         uint64_t staging_bytes, uint64_t rets, uint64_t mismatch, uint32_t cell,
                         void* stream) {
-  if (!ctx || !rets || !mismatch || (file_bytes && !data)) return -EINVAL;
-  if (!piece || file_bytes > (1ull << 31)) return -EINVAL;
+  if (!ctx || !piece || file_bytes > (1ull << 31)) return -EINVAL;
   // stateful calls are issued blocking, at work-group granularity
   if (GSYS_CELL_GRAN(cell) != GSYS_GRAN_WG || !(cell & GSYS_CELL_BLOCKING)) return -EINVAL;
   const uint64_t pieces = (file_bytes + piece - 1) / piece;
   if (pieces > (1u << 20)) return -EINVAL;
-  if (!nfiles) return 0;
+  if (!nfiles) return 0;  // the outputs are empty and may be null
+  if (!rets || !mismatch || (file_bytes && !data)) return -EINVAL;
   const uint64_t area = (std::max<uint64_t>(file_bytes, kEofRead) + 15) & ~15ull;
   if (staging_bytes < 2 * area * nfiles) return -EINVAL;
   if (gsys_internal::check_host_range(ctx, staging, 2 * area * nfiles)) return -EFAULT;

@@ -321,8 +321,9 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
 int gsys_fnv4k_consume(gsys_ctx* ctx, uint64_t staging, uint64_t rets, uint64_t n_items,
                        uint32_t item_bytes, uint64_t out_fnv, uint32_t wg_size, uint32_t grid,
                        void* stream) {
-  if (!ctx || !staging || !rets || !out_fnv) return -EINVAL;
-  if (!n_items) return 0;
+  if (!ctx) return -EINVAL;
+  if (!n_items) return 0;  // the outputs are empty and may be null
+  if (!staging || !rets || !out_fnv) return -EINVAL;
   if (item_bytes == 0 || item_bytes % 64 || item_bytes > (1u << 20)) return -EINVAL;
   if (!(wg_size == 64 || wg_size == 128 || wg_size == 256 || wg_size == 512 || wg_size == 1024))
     return -EINVAL;

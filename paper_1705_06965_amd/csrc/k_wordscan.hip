@@ -452,7 +452,8 @@ int gsys_wordscan(gsys_ctx* ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
                   uint64_t queries, uint64_t qlens, uint32_t nq, uint64_t counts, uint32_t nfiles,
                   uint64_t staging, uint64_t staging_bytes, uint32_t form, uint32_t passes,
                   void* stream) {
-  if (!ctx || !chunks || !queries || !qlens || !counts) return -EINVAL;
+  // no chunks (every file empty, or no files) only zeroes the counts
+  if (!ctx || (!chunks && n_chunks) || !queries || !qlens || !counts) return -EINVAL;
   if (passes == 0 || (form == GSYS_PLAIN && passes != 1) ||
       (uint64_t)n_chunks * passes > 0xffffffffull)
     return -EINVAL;
@@ -525,10 +526,11 @@ int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
                         uint64_t file_ret, uint32_t chunk, uint64_t staging,
                         uint64_t staging_bytes, uint64_t progress, uint32_t progress_groups,
                         void* stream) {
-  if (!ctx || !queries || !qlens || !counts || !file_ret) return -EINVAL;
+  if (!ctx) return -EINVAL;
   if (nq == 0 || nq > kMaxQ) return -EINVAL;
   if (chunk < 64 || chunk % 64 || chunk > (64u << 20)) return -EINVAL;
-  if (!nfiles) return 0;
+  if (!nfiles) return 0;  // the outputs are empty and may be null
+  if (!queries || !qlens || !counts || !file_ret) return -EINVAL;
   if (gsys_internal::check_host_range(ctx, paths, (uint64_t)nfiles * GSYS_PATH_MAX)) return -EFAULT;
   // carry head + data + the scanner's window past the last valid byte
   const uint32_t cbuf = (uint32_t)gsys_wordcount_open_buffer_bytes(chunk);

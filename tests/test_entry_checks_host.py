@@ -1,0 +1,103 @@
+"""Argument checks of the entry points on the CPU: a CPU-only context
+(GSYS_CFG_NO_DEVICE) answers -EINVAL or -EFAULT for a bad call and -ENODEV
+once every check passes (the launch itself needs a GPU).  Empty inputs
+(no items, no files) return 0 without launching, whatever their output
+pointers."""
+import errno
+
+import pytest
+
+import paper_1705_06965_amd as g
+
+WG_BLOCK = g.cell(g.GRAN_WG, strong=True, blocking=True)
+DEV = 0x10000          # device addresses are not dereferenced before the launch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = g.Context(flags=g.CFG_NO_DEVICE | g.CFG_NO_PIN, service_threads=1)
+    yield c
+    c.shutdown()
+
+
+def roundtrip(c, nfiles=2, file_bytes=1000, piece=256, staging=None, paths=None,
+              rets=DEV, mismatch=DEV, data=DEV, cell=WG_BLOCK, staging_bytes=None):
+    area = (max(file_bytes, 16) + 15) // 16 * 16
+    if staging_bytes is None:
+        staging_bytes = 2 * area * nfiles
+    return g.lib.gsys_file_roundtrip(c.h, 3, paths, nfiles, data, file_bytes, piece, staging,
+                                     staging_bytes, rets, mismatch, cell, None)
+
+
+def test_roundtrip_checks(ctx):
+    st = ctx.host_alloc(1 << 16)
+    pa = ctx.host_alloc(2 * g.PATH_MAX)
+    try:
+        ok = dict(staging=st.dev, paths=pa.dev)
+        assert roundtrip(ctx, **ok) == -errno.ENODEV
+        # no files: nothing to do, and the outputs may be null
+        assert roundtrip(ctx, nfiles=0, rets=0, mismatch=0, data=0, paths=0, staging=0) == 0
+        # the cell is checked first: stateful calls are blocking work-group calls
+        for bad in (g.cell(g.GRAN_WI, True, True), g.cell(g.GRAN_WG, True, False),
+                    g.cell(g.GRAN_KERNEL, False, True)):
+            assert roundtrip(ctx, nfiles=0, cell=bad, **ok) == -errno.EINVAL
+            assert roundtrip(ctx, cell=bad, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, rets=0, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, mismatch=0, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, data=0, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, data=0, file_bytes=0, **ok) == -errno.ENODEV   # empty files
+        assert roundtrip(ctx, piece=0, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, file_bytes=(1 << 31) + 1, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, file_bytes=(1 << 20) + 1, piece=1, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, staging_bytes=2 * 1008 * 2 - 1, **ok) == -errno.EINVAL
+        assert roundtrip(ctx, staging=DEV, paths=pa.dev) == -errno.EFAULT
+        assert roundtrip(ctx, staging=st.dev, paths=DEV) == -errno.EFAULT
+    finally:
+        st.free()
+        pa.free()
+
+
+def test_kernel_io_checks(ctx):
+    st = ctx.host_alloc(1 << 16)
+    try:
+        def kio(nr=g.NR_WRITE, data=DEV, nbytes=4096, staging=st.dev, ret=DEV, mismatch=DEV,
+                grid=4):
+            return g.lib.gsys_file_kernel_io(ctx.h, 3, nr, data, nbytes, staging, ret, mismatch,
+                                             grid, None)
+        assert kio() == -errno.ENODEV
+        assert kio(nr=g.NR_READ) == -errno.ENODEV
+        assert kio(nr=g.NR_PREAD64) == -errno.EINVAL
+        for k in ("data", "nbytes", "ret", "mismatch", "grid"):
+            assert kio(**{k: 0}) == -errno.EINVAL, k
+        assert kio(grid=65536) == -errno.EINVAL
+        assert kio(nbytes=(1 << 16) + 1) == -errno.EFAULT     # past the registered range
+        assert kio(staging=DEV) == -errno.EFAULT
+    finally:
+        st.free()
+
+
+def test_empty_inputs_launch_nothing(ctx):
+    # checksums: no items
+    assert g.lib.gsys_fnv4k(ctx.h, 3, 0, 0, 4096, 0, 0, 0, 0, 0, g.cell(g.GRAN_WI, True, True),
+                            g.PLAIN, 256, None) == 0
+    assert g.lib.gsys_fnv4k_consume(ctx.h, 0, 0, 0, 4096, 0, 256, 0, None) == 0
+    # the open / read / close search: no files, once its shapes pass
+    def wo(nfiles, nq=2, chunk=4096):
+        return g.lib.gsys_wordcount_open(ctx.h, 3, 0, nfiles, 0, 0, nq, 0, 0, chunk, 0, 0, 0, 0,
+                                         None)
+    assert wo(0) == 0
+    assert wo(0, nq=0) == -errno.EINVAL
+    assert wo(0, nq=65) == -errno.EINVAL
+    assert wo(0, chunk=100) == -errno.EINVAL
+    assert wo(1) == -errno.EINVAL          # a file but null outputs
+
+
+def test_consume_checks(ctx):
+    def cs(staging=DEV, rets=DEV, n=100, item=4096, out=DEV, wg=256, grid=0):
+        return g.lib.gsys_fnv4k_consume(ctx.h, staging, rets, n, item, out, wg, grid, None)
+    for k in ("staging", "rets", "out"):
+        assert cs(**{k: 0}) == -errno.EINVAL, k
+    for item in (0, 100, (1 << 20) + 64):
+        assert cs(item=item) == -errno.EINVAL
+    for wg in (0, 32, 96, 2048):
+        assert cs(wg=wg) == -errno.EINVAL

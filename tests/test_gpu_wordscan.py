@@ -109,6 +109,29 @@ def test_empty_files_and_long_tokens(gs, tmpdata):
         r.close()
 
 
+def test_corpus_without_chunks(gs, tmpdata):
+    """Files that are all empty give no chunks: every form only zeroes the
+    counts (filled with garbage first), and no files at all is a valid call."""
+    g, ctx = gs
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    paths = []
+    for k in range(3):
+        p = os.path.join(tmpdata, "empty_%d.txt" % k)
+        open(p, "wb").close()
+        paths.append(p)
+    for ps in (paths, []):
+        r = WordScanRunner(ctx, ps, [b"a", b"bc"], chunk_max=4096)
+        assert r.n_chunks == 0
+        for form in (g.PERSISTENT, g.GRAPH, g.PLAIN):
+            r.counts.fill_(-1)
+            say("no chunks", len(ps), form)
+            got = r.run(form)
+            assert got.shape == (len(ps), 2)
+            assert not got.any()
+            assert not r.counts[:len(ps) * 2].any()
+        r.close()
+
+
 @pytest.mark.parametrize("form", ["persistent", "graph"])
 @pytest.mark.parametrize("passes", [2, 5])
 def test_passes_in_one_launch(gs, corpus, form, passes):

@@ -22,3 +22,27 @@ def test_chunk_table_covers_files_exactly():
 def test_staging_bytes_rounds_to_16():
     assert staging_bytes(13, 1) == 80
     assert staging_bytes(1 << 20, 2) == 2 * ((1 << 20) + 64)
+
+
+def test_empty_chunk_table_is_a_valid_call():
+    """A corpus of empty files has no chunks: gsys_wordscan takes a null
+    chunk table with n_chunks == 0 in every form (it only zeroes the counts,
+    which needs the device: -ENODEV on a CPU-only context), and refuses a
+    null table that claims chunks."""
+    import errno
+
+    import paper_1705_06965_amd as g
+    c = g.Context(flags=g.CFG_NO_DEVICE | g.CFG_NO_PIN, service_threads=1)
+    try:
+        st = c.host_alloc(staging_bytes(4096, 2))
+
+        def call(chunks, n_chunks, form, passes=1):
+            return g.lib.gsys_wordscan(c.h, chunks, n_chunks, 4096, 0x1000, 0x2000, 1, 0x3000, 3,
+                                       st.dev, st.nbytes, form, passes, None)
+        for form in (g.PLAIN, g.PERSISTENT, g.GRAPH):
+            assert call(0, 0, form) == -errno.ENODEV
+            assert call(0, 1, form) == -errno.EINVAL
+        assert call(0, 0, g.PERSISTENT, passes=3) == -errno.ENODEV
+        st.free()
+    finally:
+        c.shutdown()
