@@ -49,7 +49,7 @@ class KVServer:
         self.torch = torch
         self.ctx = ctx
         n = len(keys)
-        self.cap = int(cap or 2 * n)
+        self.cap = int(cap or max(1, 2 * n))   # an empty store still has one bucket
         poff, pheap = padded_heap(val_off, val_len, heap)
         self.keys = torch.from_numpy(np.ascontiguousarray(keys).reshape(-1)).to(device)
         self.voff = torch.from_numpy(poff.view(np.int64)).to(device)

@@ -61,6 +61,61 @@ def test_kv_replies_match_oracle(gs, grid, batch, loop):
     ix.close()
 
 
+@pytest.mark.parametrize("loop", ["pipelined", "blocking"])
+def test_kv_degenerate_tables_and_no_traffic(gs, loop):
+    """A server started and stopped with no request answers nothing and
+    leaves no failed call; an empty store answers every GET with a miss; a
+    full table (capacity = keys, every bucket used) answers hits and misses
+    byte-exact, a miss probing every bucket once."""
+    g, ctx = gs
+    from paper_1705_06965_amd.kv import KVServer, loadgen, make_requests
+    pipelined = loop == "pipelined"
+    # no traffic
+    kv = synth.kv_set(n_keys=2000, n_req=5000, miss_every=16)
+    srv = KVServer(ctx, kv.keys, kv.val_off, kv.val_len, kv.heap, grid=8, batch=64,
+                   pipelined=pipelined)
+    say("kv no traffic", loop)
+    ctx.stats(reset=True)
+    srv.start(lifetime_ms=60_000)
+    import time
+    time.sleep(0.3)
+    srv.stop()
+    assert int(srv.served.cpu().item()) == 0
+    st = ctx.stats(reset=True)
+    # every failure but EAGAIN (an empty socket) counts
+    assert all(v == 0 for i, v in enumerate(st["errno_hist"]) if i != 4), st["errno_hist"]
+    srv.close()
+    # empty store, then a full table
+    rng = np.random.default_rng(41)
+    empty = (np.zeros((0, 16), np.uint8), np.zeros(0, np.uint64), np.zeros(0, np.uint32),
+             np.zeros(0, np.uint8))
+    cases = [("empty", empty, None, make_requests(rng.integers(0, 256, (500, 16), np.uint8))),
+             ("full", (kv.keys, kv.val_off, kv.val_len, kv.heap), len(kv.keys),
+              make_requests(kv.req_keys))]
+    for label, (keys, voff, vlen, heap), cap, reqs in cases:
+        ix = oracle.KVIndex(keys, voff, vlen, heap)
+        srv = KVServer(ctx, keys, voff, vlen, heap, cap=cap, grid=8, batch=64,
+                       pipelined=pipelined)
+        say("kv", label, "table, cap", srv.cap, loop)
+        srv.start(lifetime_ms=60_000)
+        try:
+            got, replies, rlen, lat, rt = loadgen(srv.port, reqs, threads=2, window=32)
+        finally:
+            srv.stop()
+        assert got == len(reqs)
+        status = []
+        for k in range(len(reqs)):
+            want = ix.reply(reqs[k].tobytes())
+            assert rlen[k] == len(want) and replies[k, :rlen[k]].tobytes() == want, (label, k)
+            status.append(want[8])
+        if label == "empty":
+            assert set(status) == {1}
+        else:
+            assert 0 in status and 1 in status
+        srv.close()
+        ix.close()
+
+
 def test_kv_short_and_long_datagrams(gs):
     """Datagrams that are not 32 bytes get status 2 with their id."""
     g, ctx = gs

@@ -109,6 +109,33 @@ def test_default_grid_matches_oracle(gs, mix, tmpdata):
     assert (lat != np.uint64(2**64 - 1)).all()
 
 
+def test_empty_session_then_a_session(gs, mix, tmpdata):
+    """A session of no jobs is a valid call in both forms and through the
+    allocation-free entry (the persistent work-groups start, find the stop
+    flag and leave); a session run after it gives the oracle's results."""
+    g, ctx = gs
+    from paper_1705_06965_amd.serve import ServeRun
+    js, in_path = mix
+    empty = synth.job_stream(n_jobs=0, scan_file_bytes=64 << 20)
+    sr = ServeRun(ctx, empty, in_path, os.path.join(tmpdata, "serve_out_empty.bin"))
+    for form, entry in ((g.PERSISTENT, None), (g.PLAIN, None),
+                        (g.PERSISTENT, g.lib.gsys_serve_run_noalloc)):
+        say("serve empty session", form, entry is not None)
+        res, dig, lat = sr.run(form, max_inflight=64, staging_bytes=(2 << 20) * 32, entry=entry)
+        assert len(res) == 0 and len(lat) == 0
+        assert not dig.any()
+    sr.close()
+    sub = sub_stream(js, np.arange(60))
+    out_path = os.path.join(tmpdata, "serve_out_after_empty.bin")
+    sr = ServeRun(ctx, sub, in_path, out_path)
+    say("serve after empty, jobs", sr.n)
+    res, dig, lat = sr.run(g.PERSISTENT, max_inflight=64, staging_bytes=(2 << 20) * 32)
+    sr.close()
+    counts = check_outputs(sr, sub, res, dig, in_path, out_path, "after empty")
+    assert sum(counts) == 60
+    assert (lat != np.uint64(2**64 - 1)).all()
+
+
 def test_jobs_alone_equal_in_mix(gs, mix, tmpdata):
     g, ctx = gs
     from paper_1705_06965_amd.serve import ServeRun
