@@ -101,3 +101,35 @@ def test_consume_checks(ctx):
         assert cs(item=item) == -errno.EINVAL
     for wg in (0, 32, 96, 2048):
         assert cs(wg=wg) == -errno.EINVAL
+
+
+def test_checksum_shape_checks(ctx):
+    n = 200
+    st = ctx.host_alloc(n * 4096)
+    li = ctx.host_alloc(n * 16)
+    try:
+        def fv(n=n, item=4096, wg=64, offsets=DEV, staging=st.dev, staging_bytes=n * 4096,
+               lists=li.dev, out_fnv=DEV, out_ret=DEV, form=g.PLAIN):
+            return g.lib.gsys_fnv4k(ctx.h, 3, offsets, n, item, staging, staging_bytes, lists,
+                                    out_fnv, out_ret, g.cell(g.GRAN_WI, True, True), form, wg,
+                                    None)
+        assert fv() == -errno.ENODEV
+        assert fv(item=64, staging_bytes=n * 64) == -errno.ENODEV
+        for item in (0, 100, 4097, (1 << 20) + 64):
+            assert fv(item=item) == -errno.EINVAL, item
+        for wg in (0, 32, 96, 192, 2048):
+            assert fv(wg=wg) == -errno.EINVAL, wg
+        for k in ("offsets", "out_fnv", "out_ret"):
+            assert fv(**{k: 0}) == -errno.EINVAL, k
+        assert fv(n=(1 << 32) + 1) == -errno.EINVAL
+        # the plain form stages every item; the persistent forms need two
+        # work-groups' batches
+        assert fv(staging_bytes=n * 4096 - 1) == -errno.EINVAL
+        assert fv(staging_bytes=2 * 64 * 4096, form=g.PERSISTENT) == -errno.ENODEV
+        assert fv(staging_bytes=2 * 64 * 4096 - 1, form=g.PERSISTENT) == -errno.EINVAL
+        assert fv(staging=DEV) == -errno.EFAULT
+        assert fv(n=n + 1, staging_bytes=(n + 1) * 4096) == -errno.EFAULT   # past staging
+        assert fv(lists=DEV) == -errno.EFAULT
+    finally:
+        st.free()
+        li.free()

@@ -152,6 +152,32 @@ def test_short_reads_and_small_items(gs, tmpdata):
         r.close()
 
 
+def test_largest_items(gs):
+    """Items of 1 MiB, the largest the entry point takes: two work-groups of
+    64 (the second ragged), reads that cross or start past the end of the
+    file, in a work-item, a work-group and a kernel cell and the persistent
+    form."""
+    g, ctx = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    p = synth.random_file(2, 64 << 20, name="c2_64m.bin")
+    item = 1 << 20
+    rng = np.random.default_rng([170506965, 77])
+    offs = (rng.integers(0, (64 << 20) // 256, 100) * 256).astype(np.uint64)
+    offs[[3, 70]] = (64 << 20) - 1000            # 1,000 bytes before EOF
+    offs[[5, 99]] = (64 << 20) + 4096            # past EOF
+    offs[64] = (64 << 20) - item                 # ends exactly at EOF
+    want_fnv, want_ret = oracle.pread_fnv(p, offs, item, threads=8)
+    assert {0, 1000, item} <= set(want_ret.tolist())
+    r = FnvRunner(ctx, p, offs, item, wg_size=64)
+    for cell in (("WI", "strong", "block"), ("WG", "relaxed", "nonblock"),
+                 ("K", "relaxed", "block"), None):
+        say("1 MiB items", cell)
+        f, ret = r.run(*cell) if cell else r.run(form=g.PERSISTENT)
+        assert (ret == want_ret).all(), cell
+        assert (f == want_fnv).all(), cell
+    r.close()
+
+
 def test_single_item_and_revoked_fd(gs):
     g, ctx = gs
     from paper_1705_06965_amd.fnv import FnvRunner

@@ -109,6 +109,32 @@ def test_empty_files_and_long_tokens(gs, tmpdata):
         r.close()
 
 
+def test_largest_chunks(gs, tmpdata):
+    """Chunks of 64 MiB, the largest the entry point takes: an 80 MiB file in
+    two chunks, the second starting inside a planted token, in every form."""
+    g, ctx = gs
+    from paper_1705_06965_amd.wordscan import WordScanRunner
+    rng = np.random.default_rng([170506965, 78])
+    vocab = [b"w%d" % i for i in range(300)] + [b"needle", b"x" * 16]
+    words = rng.integers(0, len(vocab), 200_000)
+    seps = rng.integers(0, 2, 200_000)
+    block = b"".join(vocab[w] + (b" " if s_ else b"\n") for w, s_ in zip(words, seps))
+    body = bytearray(block * ((80 << 20) // len(block) + 1))
+    cut = 64 << 20
+    body[cut - 4:cut + 4] = b" needle "          # straddles the chunk edge
+    p = os.path.join(tmpdata, "largest_chunks.txt")
+    open(p, "wb").write(body)
+    qs = [b"needle", b"w7", b"w299", b"x" * 16, b"nee", b"dle"]
+    want = oracle.wordcount([p], qs)
+    assert want[0, 0] > 0
+    r = WordScanRunner(ctx, [p], qs, chunk_max=64 << 20)
+    assert r.n_chunks == 2
+    for form in (g.PERSISTENT, g.GRAPH, g.PLAIN):
+        say("64 MiB chunks", form)
+        assert (r.run(form) == want).all(), form
+    r.close()
+
+
 def test_corpus_without_chunks(gs, tmpdata):
     """Files that are all empty give no chunks: every form only zeroes the
     counts (filled with garbage first), and no files at all is a valid call."""
