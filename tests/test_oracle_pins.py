@@ -170,6 +170,31 @@ def test_kv_lookup_vs_dict():
     ix.close()
 
 
+def test_kv_reply_shapes_and_empty_index():
+    """The request format fixes every malformed reply: status 2, the id from
+    the first 8 bytes (0 when the datagram is shorter), 16 bytes and no value;
+    an index of no keys answers every well-formed GET with a miss."""
+    kv = synth.kv_set(n_keys=100, n_req=10, miss_every=0)
+    ix = oracle.KVIndex(kv.keys, kv.val_off, kv.val_len, kv.heap)
+    good = (77).to_bytes(8, "little") + bytes([1]) + bytes(7) + kv.keys[3].tobytes()
+    assert ix.reply(good)[8] == 0
+    for req in (b"", b"\x01", good[:7], good[:8], good[:31], good + b"\x00", good * 2,
+                good[:8] + bytes([2]) + good[9:]):
+        rep = ix.reply(req)
+        want_id = req[:8] if len(req) >= 8 else bytes(8)
+        assert len(rep) == 16 and rep[:8] == want_id and rep[8] == 2, req
+        assert rep[9:] == bytes(7)
+    ix.close()
+    empty = oracle.KVIndex(np.zeros((0, 16), np.uint8), np.zeros(0, np.uint64),
+                           np.zeros(0, np.uint32), np.zeros(0, np.uint8))
+    for k in range(5):
+        key = kv.keys[k].tobytes()
+        assert empty.find(key) == -1
+        rep = empty.reply(good[:16] + key)
+        assert rep[8] == 1 and len(rep) == 16 and rep[:8] == good[:8]
+    empty.close()
+
+
 def test_release_zero_pages_after_dontneed():
     stamp = bytes(range(64))
     rc, before, after = oracle.release(2 << 20, stamp)
