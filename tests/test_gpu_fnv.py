@@ -64,6 +64,23 @@ def mid(gs):
     r.close()
 
 
+def assert_quiescent(ctx):
+    """Every claimed ticket has retired after the drain: each slot it used is
+    FREE for its next lap (freed by the GPU waiter of a blocking call, by the
+    host for a non-blocking one).  The retire scan may be running on a
+    poller when the drain asks for it, so this looks a few times."""
+    import time
+    st = {}
+    for _ in range(200):
+        assert ctx.wait(5_000_000_000) == 0
+        st = ctx.stats()
+        if st["retired_lo"] == st["claimed"]:
+            return
+        time.sleep(0.01)
+    raise AssertionError("ring not quiescent: %d of %d tickets retired"
+                         % (st["retired_lo"], st["claimed"]))
+
+
 @pytest.mark.parametrize("cell", [("WI", "strong", "block"), ("WI", "strong", "nonblock"),
                                   ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
                                   ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
@@ -88,6 +105,7 @@ def test_all_legal_cells_match_oracle(gs, mid, cell):
     got_bytes = np.sort(led[:, 2].astype(np.int64))
     sizes = [min(per, r.n - k * per) * 4096 for k in range(want_requests)]
     assert (got_bytes == np.sort(np.array(sizes, dtype=np.int64))).all()
+    assert_quiescent(ctx)
 
 
 @pytest.mark.parametrize("form", ["persistent", "graph"])
@@ -100,6 +118,7 @@ def test_persistent_and_graph_forms(gs, mid, form):
         f, ret = r.run(form=fm)
         assert (ret == want_ret).all()
         assert (f == want_fnv).all()
+        assert_quiescent(ctx)
 
 
 @pytest.mark.parametrize("ring_batches", [4, 6])

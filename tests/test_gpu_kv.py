@@ -84,6 +84,15 @@ def test_kv_degenerate_tables_and_no_traffic(gs, loop):
     st = ctx.stats(reset=True)
     # every failure but EAGAIN (an empty socket) counts
     assert all(v == 0 for i, v in enumerate(st["errno_hist"]) if i != 4), st["errno_hist"]
+    # the stopped server left every slot it used free (the receive in flight
+    # when it stopped included)
+    for _ in range(200):
+        st = ctx.stats()
+        if st["retired_lo"] == st["claimed"]:
+            break
+        assert ctx.wait(5_000_000_000) == 0
+        time.sleep(0.01)
+    assert st["retired_lo"] == st["claimed"], (st["retired_lo"], st["claimed"])
     srv.close()
     # empty store, then a full table
     rng = np.random.default_rng(41)
