@@ -1125,7 +1125,7 @@ def run_permute(args):
         res["cpu_baseline"] = cpu
     r.close()
     ctx.shutdown()
-    return emit(res, sub)
+    print(json.dumps(res), flush=True)
 
 
 def run_tiny(args, sub=False):
@@ -1480,7 +1480,7 @@ def run_wordopen(args):
         res["cpu_baseline"] = cpu
     r.close()
     ctx.shutdown()
-    return emit(res, sub)
+    print(json.dumps(res), flush=True)
 
 
 

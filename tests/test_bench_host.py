@@ -46,3 +46,41 @@ def test_percentile():
     xs = list(range(1, 101))
     assert bench.percentile(xs, 50) in (50, 50.5, 51)
     assert bench.percentile(xs, 99) >= 99
+
+
+def test_workload_legs_name_only_what_they_define():
+    """Every workload leg reads only names it has: a leg that hands its line
+    back as a sub-object takes `sub`, the others print it.  (Run on the GPU
+    a leg that names an undefined variable fails only after its work.)"""
+    import ast
+    import builtins
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    module_names = {n.name for n in tree.body if isinstance(n, (ast.FunctionDef, ast.ClassDef))}
+    for n in tree.body:
+        if isinstance(n, ast.Assign):
+            module_names |= {t.id for tg in n.targets for t in ast.walk(tg)
+                             if isinstance(t, ast.Name)}
+        elif isinstance(n, (ast.Import, ast.ImportFrom)):
+            module_names |= {(a.asname or a.name).split(".")[0] for a in n.names}
+    for f in tree.body:
+        if not (isinstance(f, ast.FunctionDef) and f.name.startswith("run_")):
+            continue
+        known = set(module_names) | set(dir(builtins))
+        for node in ast.walk(f):
+            if isinstance(node, (ast.FunctionDef, ast.Lambda)):
+                a = node.args
+                known |= {x.arg for x in a.args + a.kwonlyargs}
+                if a.vararg:
+                    known.add(a.vararg.arg)
+                if a.kwarg:
+                    known.add(a.kwarg.arg)
+            if isinstance(node, ast.FunctionDef):
+                known.add(node.name)
+            elif isinstance(node, ast.Name) and isinstance(node.ctx, ast.Store):
+                known.add(node.id)
+            elif isinstance(node, (ast.Import, ast.ImportFrom)):
+                known |= {(x.asname or x.name).split(".")[0] for x in node.names}
+            elif isinstance(node, ast.ExceptHandler) and node.name:
+                known.add(node.name)
+        used = {n.id for n in ast.walk(f) if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Load)}
+        assert not used - known, (f.name, sorted(used - known))
