@@ -70,7 +70,8 @@ typedef struct gsys_config {
 
 /*
  * Create a context: allocate the slot ring (D x 64 B) and the completion
- * records (4D x 16 B) in fine-grained, host-coherent memory, the device-side
+ * records (C = max(4D, 65536) x 16 B) in fine-grained, host-coherent memory,
+ * the device-side
  * ticket counter, and start P service threads that poll the ring.
  * The ring replaces the paper's syscall area (section 5); the polling pool
  * replaces its interrupt + work-queue dispatch (section 3 notes that the

@@ -73,7 +73,11 @@ typedef struct gsys_slot {
 } gsys_slot;
 
 /*
- * Completion record, indexed by ticket mod C (C = 4 D).  The host writes
+ * Completion record, indexed by ticket mod C (C = max(4 D, 65536)).  A
+ * blocking call's record cannot be lapped (its slot is freed only after the
+ * GPU read the result, and C > D); a non-blocking call's slot is freed by
+ * the host, so its record is reused once ticket t + C is claimed, and a
+ * device wait that finds it reused reports -EOVERFLOW.  The host writes
  * `ret` of ticket t into comp[t mod C].ret and counts finished members of a
  * claim group with head h in comp[h mod C].stamp = (h << 8) | count.
  * A GPU waiter of group h is done when stamp == (h << 8) | grp_n.

@@ -229,6 +229,21 @@ __device__ __forceinline__ int64_t read_ret(const gsys_dev_ctx& c, uint64_t t) {
   return ld_sys_i64(&c.comp[t & c.comp_mask].ret);
 }
 
+// The result of a non-blocking call's ticket t, which may be collected long
+// after the call.  Its slot was freed by the host, so later laps reuse the
+// slot, and ticket t + C (C is a multiple of D: the same slot) writes the
+// same completion record.  The slot's control word is read after the result
+// (the agent-scope acquire waits for the result's load to return first): if
+// it already names ticket t + C or a later one, the record may hold that
+// ticket's result, and the wait reports -EOVERFLOW instead.  (A blocking
+// call's record cannot be lapped: its slot is freed only after this read.)
+__device__ __forceinline__ int64_t read_ret_late(const gsys_dev_ctx& c, uint64_t t) {
+  const int64_t r = read_ret(c, t);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint64_t ctl = ld_sys(&c.ring[t & c.ring_mask].ctl);
+  return GSYS_CTL_TICKET(ctl) > t + c.comp_mask ? (int64_t)GSYS_EOVERFLOW_RET : r;
+}
+
 // Blocking calls: the GPU frees the slot once it has the result (section 5).
 // The result was read before (the workgroup-scope release waits for this
 // wavefront's outstanding loads); nothing written here needs to reach the
@@ -264,7 +279,8 @@ __device__ inline int64_t wave_wait(const gsys_dev_ctx& c, const Ticket& tk, boo
   if (tk.n != 0) {
     fence_acquire_sys();
     if (err == 0) {
-      ret = read_ret(c, tk.t);
+      // free_after: a blocking call's wait (it frees the slot itself)
+      ret = free_after ? read_ret(c, tk.t) : read_ret_late(c, tk.t);
       if (free_after) free_slot(c, tk.t);
     } else {
       ret = err;
@@ -406,7 +422,7 @@ __device__ inline int64_t wait_wg(const gsys_dev_ctx& c, const Ticket& tk_thread
     if (tk_thread0.n) {
       int e = poll_group(c, tk_thread0.t, 1);
       fence_acquire_sys();
-      r = e ? (int64_t)e : read_ret(c, tk_thread0.t);
+      r = e ? (int64_t)e : read_ret_late(c, tk_thread0.t);
     }
     s_ret = r;
   }
@@ -532,7 +548,9 @@ __device__ inline int64_t call_kernel(const gsys_dev_ctx& c, KState* ks, uint16_
     if (threadIdx.x == 0 && t1) {
       int e = poll_group(c, t1 - 1, 1);
       fence_acquire_sys();
-      int64_t r = e ? (int64_t)e : read_ret(c, t1 - 1);
+      // the caller frees the slot after its own read; a work-group that
+      // reads after that takes the lap-checked read
+      int64_t r = e ? (int64_t)e : caller ? read_ret(c, t1 - 1) : read_ret_late(c, t1 - 1);
       if (caller && e == 0) free_slot(c, t1 - 1);
       s_ret = r;
     }
@@ -550,7 +568,7 @@ __device__ inline int64_t wait_kernel(const gsys_dev_ctx& c, const Ticket& tk) {
     if (tk.n) {
       int e = poll_group(c, tk.t, 1);
       fence_acquire_sys();
-      r = e ? (int64_t)e : read_ret(c, tk.t);
+      r = e ? (int64_t)e : read_ret_late(c, tk.t);
     }
     s_ret = r;
   }
@@ -592,8 +610,11 @@ __device__ inline int64_t wait_kernel(const gsys_dev_ctx& c, const Ticket& tk) {
 // Non-blocking calls return at once (0, or GSYS_NOT_WAITED where the caller
 // did not issue) and hand back a Ticket through `tk` (work-item 0 of the
 // caller work-group for group calls; each work-item for work-item calls);
-// gsys_wait<G> then returns the result.  A non-blocking call whose ticket is
-// never waited for is still serviced; the host's gsys_wait drains it.
+// gsys_wait<G> then returns the result, from the same launch or a later one.
+// The result is kept until C newer tickets have been claimed (C = the
+// completion records, max(4 x ring slots, 65536)); a wait after that
+// returns -EOVERFLOW.  A non-blocking call whose ticket is never waited for
+// is still serviced; the host's gsys_wait drains it.
 
 // The kernel-call sites a launch may use (see gsys_launch).
 __device__ __forceinline__ KState* kernel_site(const gsys_dev_ctx& c, uint32_t site) {

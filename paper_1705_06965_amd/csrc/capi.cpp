@@ -314,7 +314,11 @@ int gsys_init(const gsys_config* cfg_in, gsys_ctx** out) {
   c->no_device = (cfg.flags & GSYS_CFG_NO_DEVICE) != 0;
   c->device = cfg.device;
   c->D = cfg.ring_slots;
-  c->C = 4 * c->D;
+  // completion records: 4D, and at least 65,536 (1 MiB), so that a small
+  // ring still keeps a non-blocking call's result for the next 65,535
+  // tickets (a later lap of its record makes the device wait report
+  // -EOVERFLOW)
+  c->C = std::max<uint64_t>(4ull * c->D, 65536ull);
   c->grid_override = (uint32_t)env_u64("GSYS_PERSISTENT_GRID", 0);
   c->sleep_max = (uint32_t)env_u64("GSYS_SLEEP_MAX", cfg.sleep_max ? cfg.sleep_max : 64);
   const uint64_t tmo = cfg.device_timeout_ns ? cfg.device_timeout_ns : 30000000000ull;

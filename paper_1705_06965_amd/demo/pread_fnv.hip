@@ -16,6 +16,9 @@
 //               context's last one is refused with -EINVAL and makes none.
 // Every kernel loops over its items with the grid's stride, so a clamped
 // persistent grid covers them all.
+//   late wait:  a non-blocking work-group pread whose ticket is kept in
+//               device memory, `flood` more work-item calls in a second
+//               launch, and the wait for the first ticket in a third.
 #include <gsys.h>
 #include <gsys_device.hpp>
 
@@ -119,6 +122,29 @@ __global__ void by_kernel_sites(Args A) {
   }
 }
 
+// Late wait (three launches on one stream).  issue_late: work-group 0
+// preads item_bytes at off0 without waiting and keeps its ticket.
+__global__ void issue_late(Args A, gsys::Ticket* keep) {
+  gsys::Ticket tk{0, 0, 0};
+  gsys::pread<G::WorkGroup, O::Relaxed, B::NonBlocking>(A.c, A.fd, A.staging, A.item_bytes,
+                                                         A.off0, &tk);
+  if (threadIdx.x == 0) *keep = tk;
+}
+
+// flood: A.n work-item preads of 0 bytes, each result in out_ret[i].
+__global__ void flood(Args A) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.n) A.out_ret[i] = gsys::pread<G::WorkItem>(A.c, A.fd, A.staging, 0, 0);
+}
+
+// wait_late: work-group 0 waits for the kept ticket; the result goes to
+// out_fnv[0] (as int64).
+__global__ void wait_late(Args A, const gsys::Ticket* keep) {
+  const gsys::Ticket tk = *keep;
+  const int64_t r = gsys::gsys_wait<G::WorkGroup>(A.c, tk);
+  if (threadIdx.x == 0) A.out_fnv[0] = (uint64_t)r;
+}
+
 }  // namespace demo
 
 // gran: GSYS_GRAN_WI, GSYS_GRAN_WG, GSYS_GRAN_KERNEL, or 3 for two
@@ -154,4 +180,48 @@ extern "C" int gsys_demo_pread_fnv(gsys_ctx* ctx, uint32_t gran, uint32_t mode, 
   d.mode = mode;
   d.args = args;
   return gsys_launch(ctx, &d, stream);
+}
+
+// A non-blocking call's result collected late: launch 1 issues it and keeps
+// the ticket in `keep` (device, 16 bytes), launch 2 makes `flood` work-item
+// calls (0-byte preads; results in out_ret[flood]), launch 3 waits for the
+// kept ticket (result in out_wait[0]).  All plain launches of 256
+// work-items on `stream`.
+extern "C" int gsys_demo_late_wait(gsys_ctx* ctx, int fd, uint64_t staging, uint32_t item_bytes,
+                                   uint64_t flood, uint64_t keep, uint64_t out_ret,
+                                   uint64_t out_wait, void* stream) {
+  if (!ctx || !staging || !item_bytes || !keep || !out_wait || (flood && !out_ret))
+    return -EINVAL;
+  if (flood > (1ull << 24)) return -EINVAL;
+  demo::Args A{};
+  if (int e = gsys_device_ctx(ctx, &A.c)) return e;
+  A.staging = staging;
+  A.n = flood;
+  A.out_fnv = (uint64_t*)out_wait;
+  A.out_ret = (int64_t*)out_ret;
+  A.fd = fd;
+  A.item_bytes = item_bytes;
+  gsys::Ticket* kp = (gsys::Ticket*)keep;
+  void* with_keep[] = {&A, &kp};
+  void* only_args[] = {&A};
+  struct Step {
+    const void* k;
+    uint32_t grid;
+    void** args;
+  };
+  const Step steps[3] = {{(const void*)demo::issue_late, 1, with_keep},
+                         {(const void*)demo::flood, (uint32_t)((flood + 255) / 256), only_args},
+                         {(const void*)demo::wait_late, 1, with_keep}};
+  for (const Step& st : steps) {
+    if (!st.grid) continue;
+    gsys_launch_desc d;
+    d.kernel = st.k;
+    d.grid[0] = st.grid; d.grid[1] = 1; d.grid[2] = 1;
+    d.block[0] = 256; d.block[1] = 1; d.block[2] = 1;
+    d.lds_bytes = 0;
+    d.mode = GSYS_PLAIN;
+    d.args = st.args;
+    if (int e = gsys_launch(ctx, &d, stream)) return e;
+  }
+  return 0;
 }

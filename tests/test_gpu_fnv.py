@@ -121,6 +121,41 @@ def test_persistent_and_graph_forms(gs, mid, form):
         assert_quiescent(ctx)
 
 
+def test_smallest_ring(gs, mid):
+    """A ring of 64 slots, the smallest the library takes (one wavefront's
+    claim): nearly every claim waits for its slot to be freed for its lap
+    (back-pressure, section 5), in all 8 cells, both forms, with 64- and
+    256-wide work-groups.  Results equal the oracle's and the ring is
+    quiescent after each drain."""
+    g, _ = gs
+    from paper_1705_06965_amd.fnv import FnvRunner
+    r0, (want_fnv, want_ret) = mid
+    offs = r0.offsets.cpu().numpy().view(np.uint64)
+    ctx = g.Context(ring_slots=64, device_timeout_ns=60_000_000_000)
+    try:
+        for wg in (64, 256):
+            r = FnvRunner(ctx, r0.path, offs, 4096, wg_size=wg)
+            for cell in [("WI", "strong", "block"), ("WI", "strong", "nonblock"),
+                         ("WG", "strong", "block"), ("WG", "strong", "nonblock"),
+                         ("WG", "relaxed", "block"), ("WG", "relaxed", "nonblock"),
+                         ("K", "relaxed", "block"), ("K", "relaxed", "nonblock"), None, "graph"]:
+                say("ring 64, wg", wg, cell)
+                if cell is None:
+                    f, ret = r.run(form=g.PERSISTENT)
+                elif cell == "graph":
+                    f, ret = r.run(form=g.GRAPH)
+                else:
+                    f, ret = r.run(*cell)
+                assert (ret == want_ret).all(), (wg, cell)
+                assert (f == want_fnv).all(), (wg, cell)
+                assert_quiescent(ctx)
+            st = ctx.stats()
+            assert st["claimed"] > 64 * 20          # many laps of the ring
+            r.close()
+    finally:
+        assert ctx.shutdown() == 0
+
+
 @pytest.mark.parametrize("ring_batches", [4, 6])
 def test_persistent_staging_ring(gs, mid, ring_batches):
     """A staging ring smaller than the data: each resident work-group reuses

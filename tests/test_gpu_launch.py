@@ -112,3 +112,35 @@ def test_launch_refusals(env):
     assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL           # no kernel
     assert demo.gsys_demo_pread_fnv(ctx.h, 4, g.PLAIN, 1, 64, 0, 0, 0, 0, 1, ITEM, 1, 1,
                                     None) == -errno.EINVAL                       # bad granularity
+
+
+@pytest.mark.parametrize("flood", [0, 256, 60000, 65536 + 256])
+def test_late_wait_of_a_non_blocking_call(env, flood):
+    """A non-blocking call's result is waited for two launches after it was
+    issued, with `flood` other calls in between.  Until C newer tickets
+    are claimed (C = 65,536 completion records for this ring of 4,096
+    slots) the wait returns the call's own result, the bytes it read; after
+    that its record may hold a later call's result, and the wait reports
+    -EOVERFLOW instead of that value (without the check it would return
+    the 0 of a later 0-byte pread)."""
+    import errno
+    g, ctx, demo, path, fd, staging, torch = env
+    demo.gsys_demo_late_wait.restype = C.c_int
+    demo.gsys_demo_late_wait.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
+                                         C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p]
+    keep = torch.zeros(2, dtype=torch.int64, device="cuda")
+    out_ret = torch.full((max(1, flood),), -999, dtype=torch.int64, device="cuda")
+    out_wait = torch.full((1,), -999, dtype=torch.int64, device="cuda")
+    say("late wait, flood", flood)
+    rc = demo.gsys_demo_late_wait(ctx.h, fd, staging.dev, ITEM, flood, keep.data_ptr(),
+                                  out_ret.data_ptr(), out_wait.data_ptr(), None)
+    assert rc == 0, g.lib.gsys_strerror(rc)
+    torch.cuda.synchronize()
+    assert ctx.wait(20_000_000_000) == 0
+    if flood:
+        assert (out_ret.cpu().numpy() == 0).all()
+    got = int(out_wait.cpu().item())
+    if flood < 65536:
+        assert got == ITEM
+    else:
+        assert got == -errno.EOVERFLOW
