@@ -651,6 +651,7 @@ uint64_t hash_words(std::initializer_list<uint64_t> w) {
 
 int launch(gsys_ctx* c, const void* kernel, uint32_t grid, uint32_t block, uint32_t lds, void** args,
            hipStream_t s) {
+  if (c->no_device) return -ENODEV;  // a CPU-only context launches nothing
   hipSetDevice(c->device);
   const hipError_t e = hipLaunchKernel(kernel, dim3(grid), dim3(block), args, lds, s);
   if (e != hipSuccess) {
@@ -663,6 +664,7 @@ int launch(gsys_ctx* c, const void* kernel, uint32_t grid, uint32_t block, uint3
 
 int launch_graph(gsys_ctx* c, uint64_t key, const KLaunch* k, uint32_t n, hipStream_t s) {
   if (!n) return -EINVAL;
+  if (c->no_device) return -ENODEV;
   hipSetDevice(c->device);
   auto params = [&](uint32_t i) {
     hipKernelNodeParams p;

@@ -116,6 +116,7 @@ int gsys_canary(gsys_ctx* ctx, int fd, uint64_t buf, uint64_t n_items, uint64_t 
     if (strong) return -EINVAL;
     k = blocking ? (const void*)canary<G::Kernel, O::Relaxed, B::Blocking>
                  : (const void*)canary<G::Kernel, O::Relaxed, B::NonBlocking>;
+    if (gsys_internal::no_device(ctx)) return -ENODEV;
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, (hipStream_t)stream,
                        (unsigned long long*)A.ks, (uint32_t)(sizeof(KState) / 8));
   } else {

@@ -207,6 +207,7 @@ int gsys_file_roundtrip(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
   A.piece = piece;
   A.pieces = (uint32_t)pieces;
   A.dirfd = dirfd;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
   hipLaunchKernelGGL(zero_words, dim3((nfiles + 255) / 256), dim3(256), 0, s,
                      (unsigned long long*)mismatch, (uint64_t)nfiles);
   if (hipGetLastError() != hipSuccess) return -ENODEV;
@@ -233,6 +234,7 @@ int gsys_file_kernel_io(gsys_ctx* ctx, int fd, uint32_t nr, uint64_t data, uint6
   A.ret = (int64_t*)ret;
   A.mismatch = (unsigned long long*)mismatch;
   A.fd = fd;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)A.ks,
                      (uint64_t)(sizeof(KState) / 8));
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)mismatch,

@@ -308,6 +308,7 @@ int gsys_fnv4k(gsys_ctx* ctx, int fd, uint64_t offsets, uint64_t n_items, uint32
     k = blocking ? (small ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking, 256> : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::Blocking, 1024>)
                  : (small ? (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking, 256> : (const void*)fnv4k_plain<G::Kernel, O::Relaxed, B::NonBlocking, 1024>);
     // fresh per-launch state for the kernel-granularity call site
+    if (gsys_internal::no_device(ctx)) return -ENODEV;
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)A.ks,
                        (uint32_t)(sizeof(KState) / 8));
     if (hipGetLastError() != hipSuccess) return -ENODEV;

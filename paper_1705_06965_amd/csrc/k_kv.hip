@@ -340,6 +340,8 @@ int gsys_kv_build(gsys_ctx* ctx, uint64_t table, uint64_t cap, uint64_t keys, ui
                   uint64_t vlen, uint64_t n, void* stream) {
   if (!ctx || !table || !cap || (n && (!keys || !voff || !vlen))) return -EINVAL;
   if (n > cap) return -EINVAL;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
+  hipSetDevice(gsys_internal::device_of(ctx));
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(zero_u64, dim3((uint32_t)std::min<uint64_t>((cap + 255) / 256, 65535)),
                      dim3(256), 0, s, (uint64_t*)table, cap * 4);

@@ -559,6 +559,7 @@ int gsys_wordcount_open(gsys_ctx* ctx, int dirfd, uint64_t paths, uint32_t nfile
   A.chunk = chunk;
   A.dirfd = dirfd;
   const uint64_t ncount = (uint64_t)nfiles * nq;
+  if (gsys_internal::no_device(ctx)) return -ENODEV;
   hipLaunchKernelGGL(zero_u32, dim3((uint32_t)std::min<uint64_t>((ncount + 255) / 256, 4096)),
                      dim3(256), 0, s, (uint32_t*)counts, ncount);
   hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, (uint32_t*)A.w.work, (uint64_t)2);

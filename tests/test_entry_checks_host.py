@@ -133,3 +133,46 @@ def test_checksum_shape_checks(ctx):
     finally:
         st.free()
         li.free()
+
+
+def test_cpu_only_context_launches_nothing(ctx, capfd):
+    """A CPU-only context answers every valid call with -ENODEV and launches
+    nothing (on a machine with a GPU the device addresses here are not
+    mapped, so a launch would fault); the library reports every failed
+    launch on stderr, and none is reported."""
+    import numpy as np
+    st = ctx.host_alloc(1 << 20)
+    pa = ctx.host_alloc(2 * g.PATH_MAX)
+    try:
+        K = g.cell(g.GRAN_KERNEL, False, True)
+        WG = g.cell(g.GRAN_WG, True, True)
+        sigma = np.arange(1024, dtype=np.uint16)
+        tau = np.arange(64, dtype=np.uint8)
+        calls = {
+            "kv_build": lambda: g.lib.gsys_kv_build(ctx.h, DEV, 16, 0, 0, 0, 0, None),
+            "fnv4k kernel cell": lambda: g.lib.gsys_fnv4k(ctx.h, 3, DEV, 16, 4096, st.dev, 16 * 4096,
+                                                          st.dev, DEV, DEV, K, g.PLAIN, 64, None),
+            "fnv4k persistent": lambda: g.lib.gsys_fnv4k(ctx.h, 3, DEV, 16, 4096, st.dev, 16 * 4096,
+                                                         st.dev, DEV, DEV, 0, g.PERSISTENT, 64,
+                                                         None),
+            "fnv4k graph": lambda: g.lib.gsys_fnv4k(ctx.h, 3, DEV, 16, 4096, st.dev, 16 * 4096,
+                                                    st.dev, DEV, DEV, 0, g.GRAPH, 64, None),
+            "consume": lambda: g.lib.gsys_fnv4k_consume(ctx.h, DEV, DEV, 16, 4096, DEV, 64, 0, None),
+            "canary": lambda: g.lib.gsys_canary(ctx.h, 3, st.dev, 64, 1, DEV, K, 64, None),
+            "permute": lambda: g.lib.gsys_permute(ctx.h, 3, DEV, sigma.ctypes.data, tau.ctypes.data,
+                                                  1, 0, st.dev, 0, DEV, WG, None),
+            "roundtrip": lambda: roundtrip(ctx, staging=st.dev, paths=pa.dev),
+            "kernel io": lambda: g.lib.gsys_file_kernel_io(ctx.h, 3, g.NR_WRITE, DEV, 4096, st.dev,
+                                                           DEV, DEV, 4, None),
+            "wordscan": lambda: g.lib.gsys_wordscan(ctx.h, DEV, 4, 4096, DEV, DEV, 1, DEV, 2,
+                                                    st.dev, st.nbytes, g.PERSISTENT, 1, None),
+            "wordcount_open": lambda: g.lib.gsys_wordcount_open(
+                ctx.h, 3, pa.dev, 2, DEV, DEV, 1, DEV, DEV, 4096, st.dev, st.nbytes, 0, 0, None),
+        }
+        capfd.readouterr()
+        for name, call in calls.items():
+            assert call() == -errno.ENODEV, name
+        assert "launch" not in capfd.readouterr().err
+    finally:
+        st.free()
+        pa.free()
