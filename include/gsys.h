@@ -202,7 +202,8 @@ typedef struct gsys_launch_desc {
  *               grid, block, LDS); every launch sets its own argument values
  *               into the graph before replaying it, so `args` may point at
  *               the same array with new values each time
- * Asynchronous on `stream`.  Errors: -EINVAL, -ENODEV (HIP launch failure).
+ * Asynchronous on `stream`.  Errors: -EINVAL, -ENODEV (HIP launch failure,
+ * or a CPU-only context).
  */
 int gsys_launch(gsys_ctx *ctx, const gsys_launch_desc *desc, void *stream);
 

@@ -24,19 +24,20 @@ __global__ void clear_sites(unsigned long long* p, uint32_t n) {
 }  // namespace gsys_ln
 
 int gsys_launch(gsys_ctx* c, const gsys_launch_desc* d, void* stream) {
-  if (!c || !d || !d->kernel || gsys_internal::no_device(c)) return -EINVAL;
+  if (!c || !d || !d->kernel) return -EINVAL;
   const dim3 b(d->block[0] ? d->block[0] : 1, d->block[1] ? d->block[1] : 1,
                d->block[2] ? d->block[2] : 1);
   dim3 g(d->grid[0], d->grid[1] ? d->grid[1] : 1, d->grid[2] ? d->grid[2] : 1);
   const uint64_t threads = (uint64_t)b.x * b.y * b.z;
   if (!g.x || threads > 1024) return -EINVAL;
-  if (d->mode == GSYS_PERSISTENT || d->mode == GSYS_GRAPH) {
-    if (g.y != 1 || g.z != 1) return -EINVAL;  // a one-dimensional grid of work-groups
+  const bool persistent = d->mode == GSYS_PERSISTENT || d->mode == GSYS_GRAPH;
+  if (!persistent && d->mode != GSYS_PLAIN) return -EINVAL;
+  if (persistent && (g.y != 1 || g.z != 1)) return -EINVAL;  // a one-dimensional grid
+  if (gsys_internal::no_device(c)) return -ENODEV;  // a CPU-only context launches nothing
+  if (persistent) {
     const uint32_t r = gsys_internal::resident_grid(c, d->kernel, (uint32_t)threads, d->lds_bytes);
     if (!r) return -ENODEV;
     if (g.x > r) g.x = r;
-  } else if (d->mode != GSYS_PLAIN) {
-    return -EINVAL;
   }
   gsys_dev_ctx dc;
   if (int e = gsys_device_ctx(c, &dc)) return e;

@@ -176,3 +176,32 @@ def test_cpu_only_context_launches_nothing(ctx, capfd):
     finally:
         st.free()
         pa.free()
+
+
+def test_launch_descriptor_checks(ctx):
+    """gsys_launch checks its descriptor before anything else: no kernel, an
+    empty grid, more than 1,024 work-items, an unknown mode or a persistent
+    grid of more than one dimension is -EINVAL; a valid descriptor on a
+    CPU-only context is -ENODEV (nothing launched, the kernel address here
+    is not a kernel)."""
+    import ctypes as C
+    d = g.gsys_launch_desc()
+    assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL       # no kernel
+    d.kernel = DEV
+    d.block[0] = 64
+    assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL       # no work-groups
+    d.grid[0] = 4
+    for mode in (g.PLAIN, g.PERSISTENT, g.GRAPH):
+        d.mode = mode
+        assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.ENODEV, mode
+    d.mode = 7
+    assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL
+    d.mode = g.PLAIN
+    d.block[0], d.block[1] = 64, 32                                          # 2,048 work-items
+    assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL
+    d.block[1] = 1
+    d.grid[1] = 2
+    assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.ENODEV       # plain: 2-D is fine
+    for mode in (g.PERSISTENT, g.GRAPH):
+        d.mode = mode
+        assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL, mode
