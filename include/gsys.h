@@ -366,7 +366,7 @@ int gsys_wordscan(gsys_ctx *ctx, uint64_t chunks, uint32_t n_chunks, uint32_t ch
  * (device uint8[n * 16]); voff / vlen (device uint64[n] / uint32[n]) locate
  * each value in a device heap, 16-byte aligned, at most 1024 bytes.  Open
  * addressing: bucket = floor(FNV-1a-64(key) * cap / 2^64), linear probing.
- * Keys must be distinct; n <= cap.
+ * Keys must be distinct; n <= cap <= 2^40.
  *
  * gsys_kv_serve launches the persistent server on the UDP socket `fd`
  * (allowed with GSYS_FD_SOCK, bound by the caller to 127.0.0.1).  Request

@@ -339,7 +339,7 @@ using namespace gsys_kv;
 int gsys_kv_build(gsys_ctx* ctx, uint64_t table, uint64_t cap, uint64_t keys, uint64_t voff,
                   uint64_t vlen, uint64_t n, void* stream) {
   if (!ctx || !table || !cap || (n && (!keys || !voff || !vlen))) return -EINVAL;
-  if (n > cap) return -EINVAL;
+  if (n > cap || cap > (1ull << 40)) return -EINVAL;  // the fill counts cap * 4 words
   if (gsys_internal::no_device(ctx)) return -ENODEV;
   hipSetDevice(gsys_internal::device_of(ctx));
   hipStream_t s = (hipStream_t)stream;

@@ -205,3 +205,16 @@ def test_launch_descriptor_checks(ctx):
     for mode in (g.PERSISTENT, g.GRAPH):
         d.mode = mode
         assert g.lib.gsys_launch(ctx.h, C.byref(d), None) == -errno.EINVAL, mode
+
+
+def test_kv_build_checks(ctx):
+    def kb(table=DEV, cap=16, keys=DEV, voff=DEV, vlen=DEV, n=4):
+        return g.lib.gsys_kv_build(ctx.h, table, cap, keys, voff, vlen, n, None)
+    assert kb() == -errno.ENODEV
+    assert kb(keys=0, voff=0, vlen=0, n=0) == -errno.ENODEV   # an empty table
+    for k in ("table", "keys", "voff", "vlen"):
+        assert kb(**{k: 0}) == -errno.EINVAL, k
+    assert kb(cap=0, n=0) == -errno.EINVAL
+    assert kb(cap=3, n=4) == -errno.EINVAL                    # more keys than buckets
+    assert kb(cap=(1 << 40) + 1) == -errno.EINVAL
+    assert kb(cap=1 << 40) == -errno.ENODEV
