@@ -12,14 +12,18 @@
  *   - A gsys_ctx is not thread-safe for init/shutdown; the launch entry points
  *     may be called from one host thread at a time per context.  Any number of
  *     GPU lanes may issue calls concurrently.
+ *   - Arguments are checked before anything runs.  In a GSYS_CFG_NO_DEVICE
+ *     context every call that would launch a kernel then returns -ENODEV and
+ *     launches nothing.
  *
  * Whitelist.  The service pool executes only pread64, pwrite64, read, write,
  * sendto and recvfrom (IPv4 loopback peers only), mmap (anonymous, inside the
- * context's arena), munmap and madvise (MADV_DONTNEED, inside the arena), on
- * file descriptors the caller allowed with gsys_allow_fd and buffers it
- * registered.  Anything else completes with -EPERM (call not allowed),
- * -EBADF (fd not allowed), -EFAULT (address range not registered) or
- * -EINVAL (flags).
+ * context's arena), munmap and madvise (MADV_DONTNEED, inside the arena),
+ * openat (a relative path beneath a directory allowed with GSYS_FD_DIR) and
+ * close (of a descriptor such an openat returned), on file descriptors the
+ * caller allowed with gsys_allow_fd and buffers it registered.  Anything else
+ * completes with -EPERM (call not allowed), -EBADF (fd not allowed), -EFAULT
+ * (address range not registered) or -EINVAL (flags).
  */
 #ifndef GSYS_H
 #define GSYS_H
