@@ -658,16 +658,22 @@ def run_kv(args, sub=False):
           file=sys.stderr, flush=True)
     if not sub:
         return emit(_kv_run(args, kv, reqs, args.kv_clients, sub), sub)
-    # beside the sweep: 4 load-generator threads, and 8 as a second figure
+    # beside the sweep: 4 load-generator threads with the tuned list size, the
+    # same with the configuration's 256-datagram lists, and 8 threads
     res = _kv_run(args, kv, reqs, 4, sub)
+    res["batch256"] = {k: v for k, v in _kv_run(args, kv, reqs, 4, sub, batch=256,
+                                                with_cpu=False).items()
+                       if k not in SUB_DROP + ("steps", "warmup")}
     res["clients8"] = {k: v for k, v in _kv_run(args, kv, reqs, 8, sub).items()
                        if k not in SUB_DROP + ("steps", "warmup")}
     return emit(res, sub)
 
 
-def _kv_run(args, kv, reqs, clients, sub):
+def _kv_run(args, kv, reqs, clients, sub, batch=0, with_cpu=True):
     """One key-value measurement with `clients` load-generator threads; the
-    pool's knobs come from the cache entry tuned for that client count."""
+    pool's knobs come from the cache entry tuned for that client count
+    (`batch`, when given, sets the datagrams per list call instead).
+    with_cpu=False leaves out the oracle server's run."""
     import socket
     import struct
     import threading
@@ -676,10 +682,13 @@ def _kv_run(args, kv, reqs, clients, sub):
     from paper_1705_06965_amd.kv import KVServer, loadgen
     from paper_1705_06965_amd import autotune
     tk_ = autotune.load("kv8" if clients == 8 else "kv")
+    tuned = dict(tk_)   # the cache entry, before any override below
     if args.kv_grid:
         tk_["grid"] = args.kv_grid
     if args.kv_batch:
         tk_["batch"] = args.kv_batch
+    if batch:
+        tk_["batch"] = batch
     pollers = args.service_threads if args.service_threads >= 0 else tk_["service_threads"]
     ctx = g.Context(ring_slots=1 << 16, service_threads=pollers,
                     device_timeout_ns=60_000_000_000,
@@ -714,7 +723,7 @@ def _kv_run(args, kv, reqs, clients, sub):
             if replies[k, :rlen[k]].tobytes() != want:
                 raise RuntimeError("kv reply %d differs from the oracle" % k)
     cpu = None
-    if oracle:
+    if oracle and with_cpu:
         # the oracle as a CPU server on the same loopback path, same client
         n_cpu = 1_000_000
         threads = max(1, len(os.sched_getaffinity(0)) - clients)
@@ -756,7 +765,7 @@ def _kv_run(args, kv, reqs, clients, sub):
                                "recvfrom/sendto list calls per work-group" % tk_["batch"],
                    "server_workgroups": tk_["grid"], "batch": tk_["batch"],
                    "server_loop": "pipelined" if tk_.get("pipelined", 1) else "blocking",
-                   "tuned": tk_, "client_threads": clients,
+                   "tuned": tuned, "client_threads": clients,
                    "service_threads": pollers,
                    "client_window": args.kv_window, "doorbell": bool(args.kv_doorbell)},
         # calls the GPU's lists asked for (datagrams received or sent) and the
