@@ -301,11 +301,11 @@ const char *gsys_strerror(int code);
  *   form      GSYS_PLAIN (grid n_items / wg_size) or GSYS_PERSISTENT /
  *             GSYS_GRAPH (co-resident grid looping over batches of wg_size
  *             items, double-buffered non-blocking group calls; cell ignored).
- *             The persistent grid is 128 work-groups (fewer if fewer are
+ *             The persistent grid is 64 work-groups (fewer if fewer are
  *             resident or there are fewer batches; environment
  *             GSYS_PERSISTENT_GRID sets it instead): every work-group waiting
- *             for its call polls host memory, and ~512 of them slow the host
- *             pool by a few percent.
+ *             for its call polls host memory, which slows the host pool, and
+ *             64 groups of 256 keep enough reads in flight.
  *   wg_size   work-items per work-group: 64, 128, 256, 512 or 1024
  * item_bytes must be a multiple of 64 and at most 1 MiB; n_items % wg_size
  * need not be 0 (the tail work-group is partial).  n_items == 0 returns 0 at
