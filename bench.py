@@ -1154,7 +1154,13 @@ def run_tiny(args, sub=False):
     path = synth.random_file(1, 262144, name="c1_256k.bin")
     offs = synth.tiny_offsets(64)
     oracle = oracle_leg(args)
-    ctx = g.Context(ring_slots=1 << 10, service_threads=max(0, args.service_threads),
+    # the sweep's tuned pool: with all cores but one, the pinned pollers
+    # share cores with this thread and the runtime's, and about one launch in
+    # a hundred waited 1-5 ms for a poller preempted in the middle of a call
+    from paper_1705_06965_amd import autotune
+    pollers = args.service_threads if args.service_threads >= 0 else \
+        int(autotune.load("sweep")["service_threads"]) or 12
+    ctx = g.Context(ring_slots=1 << 10, service_threads=pollers,
                     device_timeout_ns=10_000_000_000, flags=g.CFG_LEDGER)
     r = FnvRunner(ctx, path, offs, 4096, wg_size=64)
     stream = torch.cuda.current_stream()
@@ -1213,7 +1219,7 @@ def run_tiny(args, sub=False):
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": "tiny plain form: 1 work-group x 64 work-items, blocking 4 KiB "
                                "pread at 4096 i of a 256 KiB file, work-item / strong",
-                   "form": "plain"},
+                   "form": "plain", "service_threads": pollers, "launches": reps},
         "end_to_end_us": {"p50": pc(e2e, 50), "p99": pc(e2e, 99), "min": round(min(e2e), 2)},
         "kernel_us": {"p50": pc(kern, 50), "p99": pc(kern, 99)},
         "per_call_launch_to_serviced_us": {"p50": pc(to_done, 50), "p99": pc(to_done, 99)},
