@@ -1154,9 +1154,9 @@ def run_tiny(args, sub=False):
     path = synth.random_file(1, 262144, name="c1_256k.bin")
     offs = synth.tiny_offsets(64)
     oracle = oracle_leg(args)
-    # the sweep's tuned pool: with all cores but one, the pinned pollers
-    # share cores with this thread and the runtime's, and about one launch in
-    # a hundred waited 1-5 ms for a poller preempted in the middle of a call
+    # the sweep's tuned pool: with pollers spinning on all cores but one,
+    # this thread shares the last core with the runtime's threads, and about
+    # one launch in a hundred took 1-5 ms end to end (the kernel did not)
     from paper_1705_06965_amd import autotune
     pollers = args.service_threads if args.service_threads >= 0 else \
         int(autotune.load("sweep")["service_threads"]) or 12
